@@ -1,0 +1,524 @@
+"""FP64 CPU oracle for the SSIM / MS-SSIM hot path.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, plain, obviously-correct
+definition the HIP path is checked against.  Only the test-suite, the smoke
+check and the CPU-baseline leg of the benchmark may import it; the product
+path (the C-ABI library and its Python binding) never does, and this module
+imports nothing from the product package.
+
+Paper: Venkataramanan, Wu, Bovik, Katsavounidis, Shahid, "A Hitchhiker's Guide
+to Structural Similarity" (arXiv 2101.06354).  Every function cites the passage
+it writes out.  All arithmetic is float64 (integer sums are exact int64).
+
+Readings taken where the paper is silent (each is also listed in the design
+notes of the repository):
+  * Gaussian taps are sampled at integer offsets from the window centre and the
+    1-D taps are normalised to sum to one; the 2-D window is their outer
+    product (Background section: the weights "sum to unity").
+  * The window W_ij is anchored at its top-left pixel (i, j) (Background).
+  * Pooling divides by the number of computed map positions, not by the image
+    size (the valid map is smaller than the image).
+  * Border handling ('valid' | 'zero' | 'reflect') follows the border column of
+    the table of implementation features; 'reflect' is half-sample symmetric
+    (x[-1] = x[0]) and the padded ("same") extent is floor((k-1)/2) before and
+    ceil((k-1)/2) after.
+  * Stride s evaluates windows at (s*i, s*j) from origin (0, 0) (Effect of
+    stride subsection).
+  * MS-SSIM: 2x2 average pooling with floor of odd sizes; CS_j = mean cs map at
+    scales j < M, S_M = mean(l*cs) at the coarsest scale M; score =
+    S_M^{w_M} * prod_j CS_j^{w_j}; weights renormalised to sum one only when
+    asked (the Daala-fast description).  Negative CS_j with a fractional
+    exponent gives NaN unless clamping is asked for.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "SSIMParams", "constants", "window_1d", "window_2d", "pad_image",
+    "map_shape", "moments_direct", "moments_separable", "ssim_terms",
+    "ssim_map", "ssim_pooled", "box_sums_direct", "integral_images",
+    "box_sums_integral", "box_stats", "downsample2x2", "pyramid",
+    "msssim", "ssim_map_backward", "ssim_pooled_backward",
+    "msssim_backward", "rgb_to_y_bt601", "y_grad_to_rgb_bt601",
+    "MS_WEIGHTS",
+]
+
+# Exponents of the original five-scale MS-SSIM, as used by the configurations
+# that reproduce it (Versions of SSIM section, MS-SSIM implementation list).
+MS_WEIGHTS = (0.0448, 0.2856, 0.3001, 0.2363, 0.1333)
+
+
+def constants(K1: float, K2: float, L: float) -> tuple[float, float]:
+    """C1 = (K1 L)^2, C2 = (K2 L)^2 (Background section, saturation constants)."""
+    return (K1 * L) ** 2, (K2 * L) ** 2
+
+
+@dataclass
+class SSIMParams:
+    """The paper's statement of the problem: window type, size and sigma,
+    saturation constants, stride and border handling."""
+    window: str = "gaussian"          # 'gaussian' | 'box'
+    k: int = 11
+    sigma: float = 1.5
+    C1: float = field(default_factory=lambda: constants(0.01, 0.03, 255.0)[0])
+    C2: float = field(default_factory=lambda: constants(0.01, 0.03, 255.0)[1])
+    stride: int = 1
+    padding: str = "valid"            # 'valid' | 'zero' | 'reflect'
+
+    def check(self) -> None:
+        if self.window not in ("gaussian", "box"):
+            raise ValueError("window must be 'gaussian' or 'box'")
+        if self.k < 1:
+            raise ValueError("k must be >= 1")
+        if self.window == "gaussian" and (self.k % 2 == 0 or self.sigma <= 0):
+            raise ValueError("a Gaussian window needs odd k and sigma > 0")
+        if self.stride < 1:
+            raise ValueError("stride must be >= 1")
+        if self.padding not in ("valid", "zero", "reflect"):
+            raise ValueError("padding must be 'valid', 'zero' or 'reflect'")
+
+
+# --------------------------------------------------------------------------
+# Window (Background section; recommended recipe k=11, sigma=1.5)
+# --------------------------------------------------------------------------
+def window_1d(window: str, k: int, sigma: float = 1.5) -> np.ndarray:
+    """1-D taps g_t, t = 0..k-1, summing to one.
+
+    Gaussian: g_t proportional to exp(-(t-c)^2 / (2 sigma^2)), c = (k-1)/2.
+    Box: g_t = 1/k, so the 2-D weight is 1/k^2 (Performance-Efficiency
+    subsection, rectangular window).
+    """
+    if window == "box":
+        return np.full(k, 1.0 / k, dtype=np.float64)
+    c = (k - 1) / 2.0
+    t = np.arange(k, dtype=np.float64) - c
+    g = np.exp(-(t * t) / (2.0 * sigma * sigma))
+    return g / math.fsum(g)
+
+
+def window_2d(window: str, k: int, sigma: float = 1.5) -> np.ndarray:
+    """w(m, n) = g_m g_n; sums to one (Background section)."""
+    g = window_1d(window, k, sigma)
+    return np.outer(g, g)
+
+
+# --------------------------------------------------------------------------
+# Border handling and output geometry
+# --------------------------------------------------------------------------
+def pad_image(img: np.ndarray, k: int, padding: str) -> np.ndarray:
+    """Extend a 2-D plane for 'zero' or 'reflect' border handling.
+
+    'valid' returns the plane unchanged.  Otherwise floor((k-1)/2) rows/cols
+    are added before and ceil((k-1)/2) after, so a stride-1 map has the size of
+    the image.  'reflect' is half-sample symmetric (numpy 'symmetric').
+    """
+    if padding == "valid":
+        return img
+    before = (k - 1) // 2
+    after = (k - 1) - before
+    if padding == "zero":
+        return np.pad(img, ((before, after), (before, after)), mode="constant")
+    if padding == "reflect":
+        return np.pad(img, ((before, after), (before, after)), mode="symmetric")
+    raise ValueError(padding)
+
+
+def map_shape(h: int, w: int, k: int, stride: int, padding: str) -> tuple[int, int]:
+    """Number of window positions: floor((H' - k)/s) + 1 per axis, H' the
+    (padded) extent; 0 when the window does not fit."""
+    hp = h if padding == "valid" else h + k - 1
+    wp = w if padding == "valid" else w + k - 1
+    ho = (hp - k) // stride + 1 if hp >= k else 0
+    wo = (wp - k) // stride + 1 if wp >= k else 0
+    return ho, wo
+
+
+# --------------------------------------------------------------------------
+# Local statistics (Background section, eqs. local_means .. local_corr)
+# --------------------------------------------------------------------------
+def moments_direct(x: np.ndarray, y: np.ndarray, w2: np.ndarray, stride: int = 1):
+    """Weighted raw moments by the direct O(k^2) sum over every window offset.
+
+    Returns (mu_x, mu_y, E[x^2], E[y^2], E[xy]) at the window anchors
+    (s*i, s*j) of already-padded planes.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    k = w2.shape[0]
+    ho = (x.shape[0] - k) // stride + 1
+    wo = (x.shape[1] - k) // stride + 1
+    acc = [np.zeros((ho, wo)) for _ in range(5)]
+    for m in range(k):
+        for n in range(k):
+            xs = x[m:m + stride * (ho - 1) + 1:stride, n:n + stride * (wo - 1) + 1:stride]
+            ys = y[m:m + stride * (ho - 1) + 1:stride, n:n + stride * (wo - 1) + 1:stride]
+            wmn = w2[m, n]
+            acc[0] += wmn * xs
+            acc[1] += wmn * ys
+            acc[2] += wmn * xs * xs
+            acc[3] += wmn * ys * ys
+            acc[4] += wmn * xs * ys
+    return tuple(acc)
+
+
+def _filter_rows(a: np.ndarray, g: np.ndarray, stride: int) -> np.ndarray:
+    """out[r, j] = sum_n g[n] a[r, s*j + n]."""
+    k = g.shape[0]
+    wo = (a.shape[1] - k) // stride + 1
+    win = np.lib.stride_tricks.sliding_window_view(a, k, axis=1)[:, : stride * (wo - 1) + 1 : stride, :]
+    return win @ g
+
+
+def moments_separable(x: np.ndarray, y: np.ndarray, g: np.ndarray, stride: int = 1):
+    """Same five moments with the separable window w = g g^T: a 1-D pass along
+    rows, then along columns (valid only for the outer-product window of the
+    Background section)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    out = []
+    for a in (x, y, x * x, y * y, x * y):
+        h = _filter_rows(a, g, stride)
+        v = _filter_rows(h.T, g, stride).T
+        out.append(v)
+    return tuple(out)
+
+
+def ssim_terms(mu_x, mu_y, exx, eyy, exy, C1: float, C2: float):
+    """Luminance, contrast-structure and quality maps.
+
+    sigma^2 = E[I^2] - mu^2, sigma_12 = E[I1 I2] - mu1 mu2 (eqs. local_means ..
+    local_corr); l (eq. lum_term); cs with C3 = C2/2; Q = l * cs (Background
+    section).
+    """
+    sxx = exx - mu_x * mu_x
+    syy = eyy - mu_y * mu_y
+    sxy = exy - mu_x * mu_y
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l = (2.0 * mu_x * mu_y + C1) / (mu_x * mu_x + mu_y * mu_y + C1)
+        cs = (2.0 * sxy + C2) / (sxx + syy + C2)
+    return l, cs, l * cs, (sxx, syy, sxy)
+
+
+def _as_f64(img) -> np.ndarray:
+    return np.asarray(img).astype(np.float64)
+
+
+def ssim_map(x, y, p: SSIMParams | None = None, form: str = "separable") -> dict:
+    """SSIM quality map of one plane pair (Background section).
+
+    Box windows on integer planes use exact integer window sums and the
+    statistics of the Performance-Efficiency subsection (eqs. mean_from_sum ..
+    corr_from_sum); all other cases use weighted float64 moments, either by
+    the direct double sum (form='direct') or separably (form='separable').
+    Returns a dict with 'map', 'l', 'cs', 'mu_x', 'mu_y', 'sxx', 'syy', 'sxy'.
+    """
+    p = p or SSIMParams()
+    p.check()
+    ho, wo = map_shape(x.shape[0], x.shape[1], p.k, p.stride, p.padding)
+    if ho < 1 or wo < 1:
+        raise ValueError("image smaller than the window")
+    integer = np.issubdtype(np.asarray(x).dtype, np.integer) and np.issubdtype(np.asarray(y).dtype, np.integer)
+    xp = pad_image(_as_f64(x), p.k, p.padding)
+    yp = pad_image(_as_f64(y), p.k, p.padding)
+    if p.window == "box" and integer:
+        xi = pad_image(np.asarray(x).astype(np.int64), p.k, p.padding)
+        yi = pad_image(np.asarray(y).astype(np.int64), p.k, p.padding)
+        sums = box_sums_direct(xi, yi, p.k, p.stride)
+        mu_x, mu_y, sxx, syy, sxy = box_stats(sums, p.k)
+        exx = sxx + mu_x * mu_x
+        eyy = syy + mu_y * mu_y
+        exy = sxy + mu_x * mu_y
+        with np.errstate(divide="ignore", invalid="ignore"):
+            l = (2.0 * mu_x * mu_y + p.C1) / (mu_x * mu_x + mu_y * mu_y + p.C1)
+            cs = (2.0 * sxy + p.C2) / (sxx + syy + p.C2)
+        q = l * cs
+    else:
+        if form == "direct":
+            mom = moments_direct(xp, yp, window_2d(p.window, p.k, p.sigma), p.stride)
+        else:
+            mom = moments_separable(xp, yp, window_1d(p.window, p.k, p.sigma), p.stride)
+        mu_x, mu_y, exx, eyy, exy = mom
+        l, cs, q, (sxx, syy, sxy) = ssim_terms(mu_x, mu_y, exx, eyy, exy, p.C1, p.C2)
+    assert q.shape == (ho, wo)
+    return {"map": q, "l": l, "cs": cs, "mu_x": mu_x, "mu_y": mu_y,
+            "sxx": sxx, "syy": syy, "sxy": sxy}
+
+
+def mean_pool(q: np.ndarray) -> float:
+    """Mean SSIM: average of the quality map (Background section), summed
+    with correct rounding."""
+    return math.fsum(np.asarray(q, dtype=np.float64).ravel().tolist()) / q.size
+
+
+def ssim_pooled(x, y, p: SSIMParams | None = None) -> float:
+    return mean_pool(ssim_map(x, y, p)["map"])
+
+
+# --------------------------------------------------------------------------
+# Rectangular windows: integer sums and integral images
+# (Performance-Efficiency subsection, eqs. integral_image_start ..
+# corr_from_sum)
+# --------------------------------------------------------------------------
+def box_sums_direct(x: np.ndarray, y: np.ndarray, k: int, stride: int = 1):
+    """Exact int64 window sums S1x, S1y, S2x, S2y, S12 over k x k windows at
+    (s*i, s*j), by summing every window offset."""
+    x = np.asarray(x).astype(np.int64)
+    y = np.asarray(y).astype(np.int64)
+    ho = (x.shape[0] - k) // stride + 1
+    wo = (x.shape[1] - k) // stride + 1
+    acc = [np.zeros((ho, wo), dtype=np.int64) for _ in range(5)]
+    for m in range(k):
+        for n in range(k):
+            xs = x[m:m + stride * (ho - 1) + 1:stride, n:n + stride * (wo - 1) + 1:stride]
+            ys = y[m:m + stride * (ho - 1) + 1:stride, n:n + stride * (wo - 1) + 1:stride]
+            acc[0] += xs
+            acc[1] += ys
+            acc[2] += xs * xs
+            acc[3] += ys * ys
+            acc[4] += xs * ys
+    return tuple(acc)
+
+
+def integral_images(x: np.ndarray, y: np.ndarray):
+    """The five summed-area tables of eq. integral_image_start and the four
+    equations after it, with the zero first row and column, reduced modulo
+    2^32 (uint32).  Shape (H+1, W+1) each; entry (i, j) holds the sum over
+    rows < i and cols < j."""
+    x = np.asarray(x).astype(np.int64)
+    y = np.asarray(y).astype(np.int64)
+    out = []
+    for a in (x, y, x * x, y * y, x * y):
+        s = np.zeros((a.shape[0] + 1, a.shape[1] + 1), dtype=np.int64)
+        s[1:, 1:] = a.cumsum(axis=0).cumsum(axis=1)
+        out.append((s % (1 << 32)).astype(np.uint32))
+    return tuple(out)
+
+
+def box_sums_integral(sats, k: int, stride: int, ho: int, wo: int):
+    """Four-corner window sums (eq. integral_image_end) in modulo-2^32
+    arithmetic, returned as int64.  Exact whenever every true window sum is
+    below 2^31 (it is for 8- and 10-bit planes with k <= 45)."""
+    res = []
+    i = np.arange(ho)[:, None] * stride
+    j = np.arange(wo)[None, :] * stride
+    for s in sats:
+        s64 = s.astype(np.int64)
+        v = s64[i + k, j + k] + s64[i, j] - s64[i + k, j] - s64[i, j + k]
+        res.append(v % (1 << 32))
+    return tuple(res)
+
+
+def box_stats(sums, k: int):
+    """Local statistics from window sums (eqs. mean_from_sum .. corr_from_sum),
+    with the variance numerators k^2 S2 - S1^2 formed exactly in integers."""
+    s1x, s1y, s2x, s2y, s12 = (np.asarray(s, dtype=np.int64) for s in sums)
+    kk = k * k
+    k4 = float(kk * kk)
+    mu_x = s1x.astype(np.float64) / kk
+    mu_y = s1y.astype(np.float64) / kk
+    sxx = (kk * s2x - s1x * s1x).astype(np.float64) / k4
+    syy = (kk * s2y - s1y * s1y).astype(np.float64) / k4
+    sxy = (kk * s12 - s1x * s1y).astype(np.float64) / k4
+    return mu_x, mu_y, sxx, syy, sxy
+
+
+# --------------------------------------------------------------------------
+# MS-SSIM (Introduction; MS-SSIM implementation list: 2x2 average pooling,
+# exponent renormalisation when fewer scales are used)
+# --------------------------------------------------------------------------
+def downsample2x2(a: np.ndarray) -> np.ndarray:
+    """Average of each aligned 2x2 block; an odd last row/column is dropped."""
+    a = np.asarray(a, dtype=np.float64)
+    h2, w2 = a.shape[0] // 2, a.shape[1] // 2
+    a = a[: 2 * h2, : 2 * w2]
+    return 0.25 * (a[0::2, 0::2] + a[0::2, 1::2] + a[1::2, 0::2] + a[1::2, 1::2])
+
+
+def pyramid(a: np.ndarray, n_scales: int) -> list[np.ndarray]:
+    lv = [np.asarray(a)]
+    for _ in range(n_scales - 1):
+        lv.append(downsample2x2(lv[-1]))
+    return lv
+
+
+def _ms_weights(weights, n_scales: int, renorm: bool) -> np.ndarray:
+    w = np.asarray(weights[:n_scales], dtype=np.float64)
+    if renorm:
+        w = w / math.fsum(w.tolist())
+    return w
+
+
+def msssim(x, y, p: SSIMParams | None = None, weights=MS_WEIGHTS, n_scales: int = 5,
+           renorm: bool = False, cs_clamp: bool = False) -> dict:
+    """Multi-scale SSIM: cs at every scale, luminance at the coarsest only,
+    combined as an exponentially weighted product (Introduction; the
+    'Product' aggregation of the Versions of SSIM section).
+
+    Returns {'score', 'cs' (list of CS_j, j < M), 's_M', 'weights'}.
+    """
+    p = p or SSIMParams()
+    w = _ms_weights(weights, n_scales, renorm)
+    xs = pyramid(_as_f64(x), n_scales)
+    ys = pyramid(_as_f64(y), n_scales)
+    cs_vals = []
+    s_m = None
+    for j in range(n_scales):
+        r = ssim_map(xs[j], ys[j], p)
+        if j < n_scales - 1:
+            cs_vals.append(mean_pool(r["cs"]))
+        else:
+            s_m = mean_pool(r["map"])
+    score = 1.0
+    with np.errstate(invalid="ignore"):
+        for j, c in enumerate(cs_vals):
+            c = max(c, 0.0) if cs_clamp else c
+            score *= float(np.power(c, w[j])) if c >= 0 else float("nan")
+        sm = max(s_m, 0.0) if cs_clamp else s_m
+        score *= float(np.power(sm, w[-1])) if sm >= 0 else float("nan")
+    return {"score": score, "cs": cs_vals, "s_M": s_m, "weights": w}
+
+
+# --------------------------------------------------------------------------
+# Adjoint with respect to the distorted plane y (derivative of the
+# Background-section definitions; the paper only mentions MS-SSIM as a
+# training objective).
+# --------------------------------------------------------------------------
+def _unpad_adjoint(gp: np.ndarray, shape, k: int, padding: str) -> np.ndarray:
+    """Adjoint of pad_image: drop zero-padded cells, fold reflected cells back
+    onto their source pixels."""
+    if padding == "valid":
+        return gp
+    h, w = shape
+    before = (k - 1) // 2
+    if padding == "zero":
+        return gp[before:before + h, before:before + w].copy()
+
+    def src(n, length):
+        idx = np.arange(n) - before
+        # half-sample symmetric reflection, period 2*length
+        idx = np.mod(idx, 2 * length)
+        return np.where(idx < length, idx, 2 * length - 1 - idx)
+
+    ri = src(gp.shape[0], h)
+    ci = src(gp.shape[1], w)
+    tmp = np.zeros((h, gp.shape[1]))
+    np.add.at(tmp, ri, gp)
+    out = np.zeros((h, w))
+    np.add.at(out.T, ci, tmp.T)
+    return out
+
+
+def ssim_map_backward(x, y, grad_map: np.ndarray, p: SSIMParams | None = None,
+                      term: str = "ssim") -> np.ndarray:
+    """dL/dy for L = sum_p grad_map(p) * T(p), T = Q (term='ssim') or cs
+    (term='cs').
+
+    With A1 = 2 mu_x mu_y + C1, B1 = mu_x^2 + mu_y^2 + C1, A2 = 2 s_xy + C2,
+    B2 = s_xx + s_yy + C2 and the raw moments mu_y, E[xy], E[y^2]:
+      dQ/dmu_y  = cs (2 mu_x - 2 mu_y l)/B1 + l (2 mu_y cs - 2 mu_x)/B2
+      dQ/dE[xy] = 2 l / B2,   dQ/dE[y^2] = -Q / B2
+      dcs/dmu_y = (2 mu_y cs - 2 mu_x)/B2, dcs/dE[xy] = 2/B2, dcs/dE[y^2] = -cs/B2
+    and dL/dy(q) = sum_p w(q - s p) [a(p) + b(p) x(q) + 2 c(p) y(q)], the
+    transposed window correlation, followed by the border adjoint.
+    """
+    p = p or SSIMParams()
+    xp = pad_image(_as_f64(x), p.k, p.padding)
+    yp = pad_image(_as_f64(y), p.k, p.padding)
+    w2 = window_2d(p.window, p.k, p.sigma)
+    mu_x, mu_y, exx, eyy, exy = moments_direct(xp, yp, w2, p.stride)
+    l, cs, q, (sxx, syy, sxy) = ssim_terms(mu_x, mu_y, exx, eyy, exy, p.C1, p.C2)
+    b1 = mu_x * mu_x + mu_y * mu_y + p.C1
+    b2 = sxx + syy + p.C2
+    g = np.asarray(grad_map, dtype=np.float64)
+    if term == "ssim":
+        a = g * (cs * (2 * mu_x - 2 * mu_y * l) / b1 + l * (2 * mu_y * cs - 2 * mu_x) / b2)
+        b = g * 2 * l / b2
+        c = -g * q / b2
+    elif term == "cs":
+        a = g * (2 * mu_y * cs - 2 * mu_x) / b2
+        b = g * 2 / b2
+        c = -g * cs / b2
+    else:
+        raise ValueError(term)
+    ho, wo = q.shape
+    s = p.stride
+    gp = np.zeros_like(yp)
+    for m in range(p.k):
+        for n in range(p.k):
+            sl = (slice(m, m + s * (ho - 1) + 1, s), slice(n, n + s * (wo - 1) + 1, s))
+            gp[sl] += w2[m, n] * (a + b * xp[sl] + 2.0 * c * yp[sl])
+    return _unpad_adjoint(gp, np.asarray(y).shape, p.k, p.padding)
+
+
+def ssim_pooled_backward(x, y, grad_score: float = 1.0, p: SSIMParams | None = None) -> np.ndarray:
+    """dL/dy for L = grad_score * mean(Q)."""
+    p = p or SSIMParams()
+    ho, wo = map_shape(np.asarray(x).shape[0], np.asarray(x).shape[1], p.k, p.stride, p.padding)
+    g = np.full((ho, wo), grad_score / (ho * wo))
+    return ssim_map_backward(x, y, g, p, "ssim")
+
+
+def _downsample_adjoint(gc: np.ndarray, fine_shape) -> np.ndarray:
+    """Transpose of downsample2x2: each coarse value sends 1/4 to its four
+    parents; a dropped odd row/column receives zero."""
+    out = np.zeros(fine_shape)
+    h2, w2 = gc.shape
+    q = 0.25 * gc
+    out[0:2 * h2:2, 0:2 * w2:2] += q
+    out[0:2 * h2:2, 1:2 * w2:2] += q
+    out[1:2 * h2:2, 0:2 * w2:2] += q
+    out[1:2 * h2:2, 1:2 * w2:2] += q
+    return out
+
+
+def msssim_backward(x, y, grad_score: float = 1.0, p: SSIMParams | None = None,
+                    weights=MS_WEIGHTS, n_scales: int = 5, renorm: bool = False,
+                    cs_clamp: bool = False) -> np.ndarray:
+    """dL/dy for L = grad_score * MS-SSIM(x, y), by the chain rule through the
+    weighted product and the 2x2 pyramid, coarse to fine."""
+    p = p or SSIMParams()
+    fwd = msssim(x, y, p, weights, n_scales, renorm, cs_clamp)
+    w = fwd["weights"]
+    ms = fwd["score"]
+    xs = pyramid(_as_f64(x), n_scales)
+    ys = pyramid(_as_f64(y), n_scales)
+    g_next = None
+    for j in range(n_scales - 1, -1, -1):
+        ho, wo = map_shape(xs[j].shape[0], xs[j].shape[1], p.k, p.stride, p.padding)
+        if j == n_scales - 1:
+            val, term = fwd["s_M"], "ssim"
+        else:
+            val, term = fwd["cs"][j], "cs"
+        if cs_clamp and val <= 0:
+            dval = 0.0
+        else:
+            dval = grad_score * ms * w[j] / val
+        gm = np.full((ho, wo), dval / (ho * wo))
+        gj = ssim_map_backward(xs[j], ys[j], gm, p, term)
+        if g_next is not None:
+            gj = gj + _downsample_adjoint(g_next, xs[j].shape)
+        g_next = gj
+    return g_next
+
+
+# --------------------------------------------------------------------------
+# Colour to luma for the differentiable-loss workload.  The paper prints the
+# BT.709 matrix (Channel-wise SSIM subsection); the training workload uses
+# BT.601 luma weights.
+# --------------------------------------------------------------------------
+BT601 = (0.299, 0.587, 0.114)
+
+
+def rgb_to_y_bt601(rgb: np.ndarray) -> np.ndarray:
+    """Y = 0.299 R + 0.587 G + 0.114 B over a leading channel axis of 3."""
+    rgb = np.asarray(rgb, dtype=np.float64)
+    return BT601[0] * rgb[0] + BT601[1] * rgb[1] + BT601[2] * rgb[2]
+
+
+def y_grad_to_rgb_bt601(gy: np.ndarray) -> np.ndarray:
+    gy = np.asarray(gy, dtype=np.float64)
+    return np.stack([BT601[0] * gy, BT601[1] * gy, BT601[2] * gy])
