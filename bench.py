@@ -1,0 +1,214 @@
+"""Benchmark of the SSIM hot path on one MI355X.
+
+Workload (one step): 64 frames of 1920x1080 uint8 luma (smooth fields with a
+per-frame translation, 8x8 block-DCT quantisation with step 16..48), SSIM with
+an 11x11 Gaussian window (sigma 1.5), K1=0.01, K2=0.03, L=255, valid, stride 1:
+forward (quality map + pooled score per frame) followed by the pooled
+backward (gradient with respect to the distorted frames).  Inputs are resident
+in HBM before the timed region.
+
+Prints ONE JSON line.  Throughput counts full-resolution input pixels (one
+per reference/distorted pair).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FP32 flop/clk (packed FMA)
+# Textbook separable 5-moment Gaussian SSIM, per output map pixel: 5 maps x 11
+# taps x 2 passes x 2 flop + 3 products + ~17 flop of luminance/cs/Q terms.
+ALG_FLOP_PER_OUT_PX = 5 * 11 * 2 * 2 + 3 + 17
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--fwd-only", action="store_true", help="time the forward alone (profiling)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2101_06354_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(x, y, frames_sample: int, with_bwd: bool):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload,
+    single-threaded."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        lim = None
+    p = O.SSIMParams()
+    t0 = time.perf_counter()
+    for f in range(frames_sample):
+        r = O.ssim_map(x[f], y[f], p)
+        O.mean_pool(r["map"])
+        if with_bwd:
+            O.ssim_pooled_backward(x[f], y[f], 1.0, p)
+    dt = time.perf_counter() - t0
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    px = frames_sample * x.shape[1] * x.shape[2]
+    return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"{frames_sample} of the {x.shape[0]} 1080p frames, FP64 numpy, "
+                      f"{'forward+backward' if with_bwd else 'forward'}, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the SSIM path is measured on a single MI355X "
+              "(frames shard across GPUs with no communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2101_06354_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    x, y = synth.config1(frames=a.frames)
+    B, H, W = x.shape
+    xt = torch.from_numpy(x).to(dev)
+    yt = torch.from_numpy(y).to(dev)
+    cfg = P.SSIMConfig()
+    ho, wo = P.map_shape(cfg, H, W)
+    stream = torch.cuda.current_stream(dev)
+
+    # probe the backward once; a build without it times the forward alone
+    with_bwd = not a.fwd_only
+    if with_bwd:
+        try:
+            P.ssim_backward(xt[:1], yt[:1], torch.ones(1, device=dev), cfg)
+        except P._lib.SSIMXError as e:
+            if e.status != P._lib.ENOTSUP:
+                raise
+            with_bwd = False
+
+    # preallocated outputs / workspaces (outside the timed region)
+    import ctypes
+    L = P._lib
+    pc = cfg.to_c()
+    xi, yi = P.ops._image(xt), P.ops._image(yt)
+    qmap = torch.empty((B, ho, wo), dtype=torch.float32, device=dev)
+    score = torch.empty(B, dtype=torch.float32, device=dev)
+    ws_f = torch.empty(P.workspace_size(cfg, L.OP_MAP, L.U8, H, W, B), dtype=torch.uint8, device=dev)
+    grad = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+    gscore = torch.full((B,), 1.0, dtype=torch.float32, device=dev)
+    ws_b = None
+    if with_bwd:
+        ws_b = torch.empty(P.workspace_size(cfg, L.OP_POOLED_BACKWARD, L.U8, H, W, B), dtype=torch.uint8,
+                           device=dev)
+
+    def fwd():
+        L.check(L.lib.ssim_map(ctypes.byref(pc), ctypes.byref(xi), ctypes.byref(yi), B, qmap.data_ptr(), wo,
+                               ho * wo, score.data_ptr(), ws_f.data_ptr(), ws_f.numel(), stream.cuda_stream),
+                "ssim_map")
+
+    def bwd():
+        L.check(L.lib.ssim_pooled_backward(ctypes.byref(pc), ctypes.byref(xi), ctypes.byref(yi), B,
+                                           gscore.data_ptr(), grad.data_ptr(), W, H * W, ws_b.data_ptr(),
+                                           ws_b.numel(), stream.cuda_stream), "ssim_pooled_backward")
+
+    for _ in range(a.warmup):
+        fwd()
+        if with_bwd:
+            bwd()
+    torch.cuda.synchronize()
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        ev[s][0].record(stream)
+        fwd()
+        ev[s][1].record(stream)
+        if with_bwd:
+            bwd()
+        ev[s][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    fwd_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(a.steps)]
+    bwd_ms = [ev[s][1].elapsed_time(ev[s][2]) for s in range(a.steps)]
+    step_ms = wall * 1e3 / a.steps
+    px = B * H * W
+    value = px / (step_ms * 1e-3) / 1e6
+    fwd_avg = float(np.mean(fwd_ms))
+    out_px = B * ho * wo
+
+    alg_bytes = px * 2 + out_px * 4 + B * 4          # read x, y; write map and scores
+    alg_flop = out_px * ALG_FLOP_PER_OUT_PX
+    achieved_tflops = alg_flop / (fwd_avg * 1e-3) / 1e12
+    achieved_gbs = alg_bytes / (fwd_avg * 1e-3) / 1e9
+    traffic = measured_traffic("sep_fwd_kernel<u8>")
+    res = {
+        "metric": "SSIM Mpixel/s fwd & fwd+bwd (1080p luma, Gaussian 11x11); % HBM roofline",
+        "value": value,
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8 in, f32 accumulate",
+        "data": "synthetic",
+        "config": {"workload": f"{B}x1080p u8 luma pairs, SSIM Gaussian 11x11 sigma 1.5, valid, stride 1, "
+                               f"{'forward (map+score) + pooled backward' if with_bwd else 'forward (map+score)'}",
+                   "frames": B, "height": H, "width": W, "window": "gaussian", "k": 11, "stride": 1},
+        "fwd_mpixel_s": px / (fwd_avg * 1e-3) / 1e6,
+        "fwd_ms": fwd_avg,
+        "fwd_bwd_mpixel_s": value if with_bwd else None,
+        "bwd_ms": float(np.mean(bwd_ms)) if with_bwd else None,
+        "roofline": {"bound": "alu", "kernel": "sep_fwd_kernel<u8> (+finalize)", "achieved": achieved_tflops,
+                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / FP32_VALU_PEAK_TFLOPS,
+                     "traffic": traffic},
+        "hbm_roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
+    }
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(x, y, 2 if with_bwd else 4, with_bwd)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

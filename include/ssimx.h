@@ -1,0 +1,231 @@
+/*
+ * ssimx.h -- C-ABI of the MI355X (gfx950) SSIM / MS-SSIM library.
+ *
+ * Operations follow "A Hitchhiker's Guide to Structural Similarity"
+ * (Venkataramanan et al., arXiv 2101.06354):
+ *   - local statistics, luminance / contrast-structure terms and the quality
+ *     map: Background section, equations local_means .. local_corr, lum_term,
+ *     the cs form with C3 = C2/2, and the mean-SSIM pooling;
+ *   - C1 = (K1 L)^2, C2 = (K2 L)^2: Background section;
+ *   - rectangular windows through window sums / integral images:
+ *     Performance-Efficiency subsection, equations integral_image_start ..
+ *     corr_from_sum;
+ *   - stride: "Effect of stride" subsection;
+ *   - border handling (valid / zero / reflection): table of implementation
+ *     features (tab:ssim_implementation_details);
+ *   - MS-SSIM with 2x2 average-pooling pyramids, cs at every scale, luminance
+ *     at the coarsest, exponentially weighted product and exponent
+ *     renormalisation when fewer scales are used: Introduction and the
+ *     MS-SSIM implementation list of the "Versions of SSIM" section.
+ * The backward calls are the adjoint of those definitions with respect to the
+ * distorted plane (the paper mentions MS-SSIM as a training objective only).
+ *
+ * Conventions shared by every call:
+ *   - All data pointers are DEVICE pointers unless the comment says "host".
+ *     The caller owns every buffer (inputs, outputs, workspace).  Compute
+ *     calls allocate no device memory.  Only a batch plan owns memory, which
+ *     ssimx_plan_destroy releases.
+ *   - `stream` is a hipStream_t handle passed as void* (NULL = the null
+ *     stream).  Compute calls are asynchronous on it; results are valid after
+ *     the stream has been synchronised.
+ *   - Planes are row-major.  `pitch` = elements between rows (>= width),
+ *     `batch_stride` = elements between frames.  Planes of one call all have
+ *     the same width and height.
+ *   - Argument errors are detected on the host before any launch and return
+ *     a negative ssimx_status; nothing is launched then.  A failed launch
+ *     returns SSIMX_EHIP and ssimx_last_hip_error() gives the hipError_t.
+ *     Faults inside kernels surface at the caller's next synchronisation.
+ *   - NaN/Inf in inputs propagate to outputs.
+ *   - Map outputs are float32, of size map_shape().  Accumulation is float32;
+ *     pooled scores use a fixed-order compensated reduction (deterministic).
+ */
+#ifndef SSIMX_H
+#define SSIMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSIMX_VERSION 100
+
+typedef enum {
+  SSIMX_OK = 0,
+  SSIMX_EINVAL = -1,     /* bad argument (null pointer, k < 1, even Gaussian k, sigma <= 0, stride < 1, C1/C2 < 0, ...) */
+  SSIMX_EDTYPE = -2,     /* unsupported dtype for this operation */
+  SSIMX_ETOOSMALL = -3,  /* map would be empty, or an MS-SSIM scale is smaller than the window */
+  SSIMX_EWORKSPACE = -4, /* ws is NULL or ws_bytes below ssimx_workspace_size() */
+  SSIMX_EHIP = -5,       /* a HIP runtime call failed; see ssimx_last_hip_error() */
+  SSIMX_ENOTSUP = -6,    /* valid but unsupported combination */
+  SSIMX_ENOMEM = -7      /* plan creation could not allocate */
+} ssimx_status;
+
+typedef enum { SSIMX_U8 = 0, SSIMX_U16 = 1, SSIMX_F32 = 2, SSIMX_BF16 = 3 } ssimx_dtype;
+
+/* Window shape (Background section): Gaussian taps g_t ~ exp(-(t-c)^2 /
+ * (2 sigma^2)), c = (k-1)/2, normalised to sum 1, 2-D weight g_m g_n; or the
+ * rectangular window with weight 1/k^2. */
+typedef enum { SSIMX_WIN_GAUSSIAN = 0, SSIMX_WIN_BOX = 1 } ssimx_window;
+
+/* Rectangular windows on integer planes: AUTO/SEPARABLE = tile-local exact
+ * integer window sums; INTEGRAL_IMAGE = the paper's five summed-area tables
+ * (uint32, wrap-around) and the four-corner formula.  Both give the same
+ * integer sums.  Ignored for Gaussian windows. */
+typedef enum { SSIMX_ALGO_AUTO = 0, SSIMX_ALGO_SEPARABLE = 1, SSIMX_ALGO_INTEGRAL_IMAGE = 2 } ssimx_algo;
+
+/* VALID: windows fully inside the plane.  ZERO / REFLECT: the plane is
+ * extended by floor((k-1)/2) before and ceil((k-1)/2) after, with zeros or by
+ * half-sample symmetric reflection (x[-1] = x[0]). */
+typedef enum { SSIMX_PAD_VALID = 0, SSIMX_PAD_ZERO = 1, SSIMX_PAD_REFLECT = 2 } ssimx_pad;
+
+typedef struct {
+  int window;    /* ssimx_window */
+  int k;         /* window size, 1..41 for Gaussian (odd), 1..64 for box */
+  float sigma;   /* Gaussian standard deviation (> 0); ignored for box */
+  double C1;     /* (K1 L)^2 >= 0 */
+  double C2;     /* (K2 L)^2 >= 0 */
+  int stride;    /* >= 1; windows anchored at (stride*i, stride*j) */
+  int padding;   /* ssimx_pad */
+  int algo;      /* ssimx_algo */
+} ssimx_params;
+
+typedef struct {
+  const void* data;     /* device pointer to frame 0, row 0 */
+  int dtype;            /* ssimx_dtype */
+  int width, height;
+  int64_t pitch;        /* elements between rows */
+  int64_t batch_stride; /* elements between frames */
+} ssimx_image;
+
+/* MS-SSIM flags. */
+#define SSIMX_MS_RENORM 1   /* divide the n_scales weights by their sum */
+#define SSIMX_MS_CS_CLAMP 2 /* use max(CS_j, 0) (and max(S_M, 0)); default lets a
+                               negative value with a fractional exponent give NaN */
+
+/* Operation selector for ssimx_workspace_size(). */
+typedef enum {
+  SSIMX_OP_MAP = 0, SSIMX_OP_POOLED = 1, SSIMX_OP_MSSSIM = 2,
+  SSIMX_OP_MAP_BACKWARD = 3, SSIMX_OP_POOLED_BACKWARD = 4, SSIMX_OP_MSSSIM_BACKWARD = 5
+} ssimx_op;
+
+/* Host only.  Map size: floor((H' - k)/stride) + 1 per axis with H' = H
+ * (valid) or H + k - 1 (zero, reflect).  Returns ETOOSMALL when empty. */
+ssimx_status ssimx_map_shape(const ssimx_params* p, int width, int height, int* width_out, int* height_out);
+
+/* Host only.  Device workspace bytes needed by `op` for `batch` frames of
+ * width x height (n_scales is used by the MS-SSIM ops only). */
+ssimx_status ssimx_workspace_size(const ssimx_params* p, int op, int dtype, int width, int height,
+                                  int batch, int n_scales, size_t* bytes);
+
+/* SSIM quality map Q(i,j) = l * cs of each frame pair (Background section).
+ * map_out: float32 [batch][map_h][map_pitch] with frame stride
+ * map_batch_stride (elements).  score_out (nullable): float32 [batch] mean of
+ * each map.  ref and dis must have equal sizes and dtypes. */
+ssimx_status ssim_map(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                      float* map_out, int64_t map_pitch, int64_t map_batch_stride, float* score_out,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Mean SSIM per frame pair, without writing the map.  score_out: float32 [batch]. */
+ssimx_status ssim_pooled(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                         float* score_out, void* ws, size_t ws_bytes, void* stream);
+
+/* MS-SSIM over n_scales (1..8) dyadic scales built by 2x2 averaging (odd
+ * sizes floored).  weights: HOST float [n_scales] exponents.
+ * score_out: float32 [batch] = S_M^{w_M} prod_{j<M} CS_j^{w_j}.
+ * cs_out (nullable): float32 [batch][n_scales]; entries 0..M-2 hold CS_j (mean
+ * cs map), entry M-1 holds S_M (mean l*cs at the coarsest scale).
+ * Every scale must hold at least one window (else ETOOSMALL). */
+ssimx_status msssim(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                    const ssimx_image* ref, const ssimx_image* dis, int batch,
+                    float* score_out, float* cs_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of ssim_map with respect to dis:
+ *   grad_dis(q) = sum_p grad_map(p) dQ(p)/d dis(q).
+ * grad_map: float32 in the map layout (map_pitch, map_batch_stride).
+ * grad_dis: float32 [batch][height][grad_pitch], frame stride
+ * grad_batch_stride; fully overwritten.  Moments are recomputed, not stored. */
+ssimx_status ssim_map_backward(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis,
+                               int batch, const float* grad_map, int64_t map_pitch, int64_t map_batch_stride,
+                               float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of ssim_pooled: grad_score float32 [batch] (dL/dscore). */
+ssimx_status ssim_pooled_backward(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis,
+                                  int batch, const float* grad_score,
+                                  float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of msssim (same weights / flags): grad_score float32 [batch].
+ * The pyramid and per-scale terms are recomputed. */
+ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                             const ssimx_image* ref, const ssimx_image* dis, int batch,
+                             const float* grad_score,
+                             float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Exact integer window sums of a rectangular k x k window (Performance-
+ * Efficiency subsection): sums_out int32 [5][batch][map_h][map_w] holding
+ * S1x, S1y, S2x, S2y, S12 in that order (x = ref, y = dis), valid windows at
+ * stride `stride`.  Integer dtypes only; every sum must fit in int32
+ * (k^2 * maxval^2 < 2^31). */
+ssimx_status ssimx_box_sums(int k, int stride, int algo, const ssimx_image* ref, const ssimx_image* dis,
+                            int batch, int32_t* sums_out, void* ws, size_t ws_bytes, void* stream);
+
+/* The five integral images of eq. integral_image_start and the four after it:
+ * sat_out uint32 [5][batch][height+1][width+1] (zero first row and column,
+ * entry (i,j) = sum over rows < i and cols < j of x, y, x^2, y^2, x*y,
+ * modulo 2^32).  Integer dtypes only. */
+ssimx_status ssimx_integral_images(const ssimx_image* ref, const ssimx_image* dis, int batch,
+                                   uint32_t* sat_out, void* stream);
+
+/* ---------------- ragged batches ------------------------------------------
+ * A plan covers n independent pairs, each with its own size and params.  It
+ * owns a device descriptor table, a partial-sum buffer and an instantiated
+ * hipGraph of one persistent launch plus a per-pair finalise.  Pair buffers
+ * must stay valid (same addresses) for the plan's lifetime. */
+typedef struct {
+  ssimx_image ref, dis;  /* single frame each */
+  ssimx_params p;
+  float* map_out;        /* nullable: map of this pair */
+  int64_t map_pitch;
+} ssimx_pair;
+
+typedef struct ssimx_plan ssimx_plan;
+
+/* pairs: HOST array [n].  tile shapes come from the autotune cache when an
+ * entry exists (see ssimx_autotune), else from built-in defaults. */
+ssimx_status ssimx_plan_create(const ssimx_pair* pairs, int n, void* stream, ssimx_plan** out);
+/* scores_out: float32 [n] device; one graph launch on `stream`. */
+ssimx_status ssimx_plan_run(ssimx_plan* plan, float* scores_out, void* stream);
+/* Same work as ssimx_plan_run, but one ordinary launch sequence per pair
+ * (the unbatched baseline). */
+ssimx_status ssimx_plan_run_unbatched(ssimx_plan* plan, float* scores_out, void* stream);
+ssimx_status ssimx_plan_destroy(ssimx_plan* plan);
+/* Host: number of (pair, tile) work items and persistent blocks of a plan. */
+ssimx_status ssimx_plan_info(const ssimx_plan* plan, int* n_items, int* n_blocks);
+
+/* ---------------- autotuning ----------------------------------------------
+ * Times the candidate tile shapes of the forward kernel for (params, dtype,
+ * width, height, batch) on `stream` (allocating and freeing its own scratch
+ * frames) and records the fastest in the process-wide cache.  The cache is
+ * read by every later call and plan.  Mutex-guarded. */
+ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int height, int batch, void* stream,
+                            int* best_tile_out);
+/* Load / save the cache as JSON (path: host string). */
+ssimx_status ssimx_tune_cache_load(const char* path);
+ssimx_status ssimx_tune_cache_save(const char* path);
+/* Force a tile configuration index for later calls (-1 = automatic). */
+ssimx_status ssimx_set_tile_override(int tile);
+/* Number of tile configurations known to the forward kernel. */
+int ssimx_num_tile_configs(void);
+
+const char* ssimx_strerror(int status);
+int ssimx_last_hip_error(void);
+int ssimx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSIMX_H */

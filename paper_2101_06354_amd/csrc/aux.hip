@@ -1,0 +1,124 @@
+// Pooling finalisation, 2x2 pyramid and the MS-SSIM product.
+#include "ssimx_internal.hpp"
+
+namespace ssimx {
+
+// Mean of each frame's tile partials (mean SSIM of the Background section),
+// summed in a fixed order with a compensated (TwoSum) tree so the result is
+// deterministic and carries about twice float32 precision.
+__global__ __launch_bounds__(BLOCK) void finalize_kernel(const float* partial, int tiles, float inv_count, float* out,
+                                                         int64_t out_stride) {
+  __shared__ float hs[BLOCK], ls[BLOCK];
+  const int frame = blockIdx.x;
+  const float* p = partial + (int64_t)frame * tiles;
+  float s = 0.f, c = 0.f;
+  for (int i = threadIdx.x; i < tiles; i += BLOCK) {
+    float e;
+    two_sum(s, p[i], s, e);
+    c += e;
+  }
+  hs[threadIdx.x] = s;
+  ls[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = BLOCK / 2; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      float e, t;
+      two_sum(hs[threadIdx.x], hs[threadIdx.x + w], t, e);
+      hs[threadIdx.x] = t;
+      ls[threadIdx.x] += ls[threadIdx.x + w] + e;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // (hi + lo) * inv_count with the low part kept through the product
+    const float hi = hs[0], lo = ls[0];
+    const float ph = hi * inv_count;
+    const float pe = fmaf(hi, inv_count, -ph);
+    out[(int64_t)frame * out_stride] = ph + (pe + lo * inv_count);
+  }
+}
+
+int launch_finalize(const float* partial, int tiles, int batch, int count_per_frame, float /*scale*/, float* out,
+                    int64_t out_stride, hipStream_t st) {
+  const float inv = (float)(1.0 / (double)count_per_frame);
+  hipLaunchKernelGGL(finalize_kernel, dim3(batch), dim3(BLOCK), 0, st, partial, tiles, inv, out, out_stride);
+  return (int)hipGetLastError();
+}
+
+// 2x2 average of aligned blocks (odd last row / column dropped), written as
+// float32 [batch][H/2][W/2].  For integer planes the result is exact.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void downsample_kernel(PlaneArg xa, PlaneArg ya, int W2, int H2, float* ox,
+                                                           float* oy) {
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= W2 * H2) return;
+  const int frame = blockIdx.y;
+  const int r = idx / W2, c = idx - r * W2;
+  const int64_t o = (int64_t)frame * W2 * H2 + idx;
+  {
+    const T* X = (const T*)xa.data + (int64_t)frame * xa.bstride + (int64_t)(2 * r) * xa.pitch + 2 * c;
+    const float a = to_f32<T>(X[0]), b = to_f32<T>(X[1]), d = to_f32<T>(X[xa.pitch]), e = to_f32<T>(X[xa.pitch + 1]);
+    ox[o] = 0.25f * (((a + b) + d) + e);
+  }
+  {
+    const T* Y = (const T*)ya.data + (int64_t)frame * ya.bstride + (int64_t)(2 * r) * ya.pitch + 2 * c;
+    const float a = to_f32<T>(Y[0]), b = to_f32<T>(Y[1]), d = to_f32<T>(Y[ya.pitch]), e = to_f32<T>(Y[ya.pitch + 1]);
+    oy[o] = 0.25f * (((a + b) + d) + e);
+  }
+}
+
+int launch_downsample(int dtype, PlaneArg in, int W, int H, float* outx, float* outy, PlaneArg iny, int batch,
+                      hipStream_t st) {
+  const int W2 = W / 2, H2 = H / 2;
+  if (W2 < 1 || H2 < 1) return (int)hipErrorInvalidValue;
+  dim3 grid((W2 * H2 + BLOCK - 1) / BLOCK, batch);
+  switch (dtype) {
+    case SSIMX_U8:
+      hipLaunchKernelGGL(downsample_kernel<uint8_t>, grid, dim3(BLOCK), 0, st, in, iny, W2, H2, outx, outy);
+      break;
+    case SSIMX_U16:
+      hipLaunchKernelGGL(downsample_kernel<uint16_t>, grid, dim3(BLOCK), 0, st, in, iny, W2, H2, outx, outy);
+      break;
+    case SSIMX_F32:
+      hipLaunchKernelGGL(downsample_kernel<float>, grid, dim3(BLOCK), 0, st, in, iny, W2, H2, outx, outy);
+      break;
+    case SSIMX_BF16:
+      hipLaunchKernelGGL(downsample_kernel<bf16_t>, grid, dim3(BLOCK), 0, st, in, iny, W2, H2, outx, outy);
+      break;
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+struct MsWeights {
+  float w[MAX_SCALES];
+};
+
+// score = S_M^{w_M} * prod_{j<M} CS_j^{w_j}; vals[frame][j] holds CS_j for
+// j < M-1 and S_M at M-1.  powf of a negative base with a fractional exponent
+// is NaN, which propagates unless clamping is asked for.
+__global__ void ms_combine_kernel(const float* vals, int n_scales, int batch, MsWeights w, int clamp,
+                                  float* score_out, float* cs_out) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= batch) return;
+  float score = 1.f;
+  for (int j = 0; j < n_scales; ++j) {
+    float v = vals[(int64_t)f * n_scales + j];
+    if (cs_out) cs_out[(int64_t)f * n_scales + j] = v;
+    if (clamp) v = fmaxf(v, 0.f);
+    score *= powf(v, w.w[j]);
+  }
+  score_out[f] = score;
+}
+
+int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w, int flags, float* score_out,
+                      float* cs_out, hipStream_t st) {
+  MsWeights mw{};
+  for (int j = 0; j < n_scales && j < MAX_SCALES; ++j) mw.w[j] = w[j];
+  hipLaunchKernelGGL(ms_combine_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, vals, n_scales, batch, mw,
+                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, score_out, cs_out);
+  return (int)hipGetLastError();
+}
+
+}  // namespace ssimx

@@ -1,0 +1,455 @@
+// Host side of the C-ABI: argument validation, geometry, workspace layout and
+// dispatch of the forward calls (ssim_map, ssim_pooled, msssim, box sums,
+// integral images).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "host_common.hpp"
+#include "ssimx_internal.hpp"
+
+namespace ssimx {
+
+thread_local int g_last_hip = 0;
+
+ssimx_status hip_status(int err) {
+  if (err != (int)hipSuccess) {
+    g_last_hip = err;
+    return SSIMX_EHIP;
+  }
+  return SSIMX_OK;
+}
+
+// ---------------------------------------------------------------- validation
+ssimx_status check_params(const ssimx_params* p) {
+  if (!p) return SSIMX_EINVAL;
+  if (p->window != SSIMX_WIN_GAUSSIAN && p->window != SSIMX_WIN_BOX) return SSIMX_EINVAL;
+  if (p->k < 1) return SSIMX_EINVAL;
+  if (p->window == SSIMX_WIN_GAUSSIAN) {
+    if ((p->k & 1) == 0 || p->k > KMAX_GAUSS) return SSIMX_EINVAL;
+    if (!(p->sigma > 0.f) || !isfinite(p->sigma)) return SSIMX_EINVAL;
+  } else if (p->k > KMAX_BOX) {
+    return SSIMX_EINVAL;
+  }
+  if (!(p->C1 >= 0.0) || !(p->C2 >= 0.0) || !isfinite(p->C1) || !isfinite(p->C2)) return SSIMX_EINVAL;
+  if (p->stride < 1) return SSIMX_EINVAL;
+  if (p->padding < SSIMX_PAD_VALID || p->padding > SSIMX_PAD_REFLECT) return SSIMX_EINVAL;
+  if (p->algo < SSIMX_ALGO_AUTO || p->algo > SSIMX_ALGO_INTEGRAL_IMAGE) return SSIMX_EINVAL;
+  return SSIMX_OK;
+}
+
+ssimx_status check_images(const ssimx_image* a, const ssimx_image* b, int batch) {
+  if (!a || !b || batch < 1) return SSIMX_EINVAL;
+  for (const ssimx_image* im : {a, b}) {
+    if (!im->data) return SSIMX_EINVAL;
+    if (im->dtype < SSIMX_U8 || im->dtype > SSIMX_BF16) return SSIMX_EDTYPE;
+    if (im->width < 1 || im->height < 1) return SSIMX_ETOOSMALL;
+    if (im->pitch < im->width) return SSIMX_EINVAL;
+    if (batch > 1 && im->batch_stride < im->pitch * (int64_t)im->height) return SSIMX_EINVAL;
+  }
+  if (a->width != b->width || a->height != b->height || a->dtype != b->dtype) return SSIMX_EINVAL;
+  return SSIMX_OK;
+}
+
+bool is_integer(int dtype) { return dtype == SSIMX_U8 || dtype == SSIMX_U16; }
+
+// Which kernel family computes the statistics.
+Path choose_path(const ssimx_params* p, int dtype) {
+  if (p->window == SSIMX_WIN_BOX && is_integer(dtype))
+    return p->algo == SSIMX_ALGO_INTEGRAL_IMAGE ? Path::kSat : Path::kBox;
+  return Path::kSep;
+}
+
+ssimx_status check_path(const ssimx_params* p, int dtype) {
+  const Path path = choose_path(p, dtype);
+  if (path == Path::kSep && p->k > KMAX_GAUSS) return SSIMX_ENOTSUP;  // float box wider than the tap table
+  if (path == Path::kSat && p->padding != SSIMX_PAD_VALID) return SSIMX_ENOTSUP;
+  if (p->algo == SSIMX_ALGO_INTEGRAL_IMAGE && p->window == SSIMX_WIN_BOX && !is_integer(dtype)) return SSIMX_EDTYPE;
+  return SSIMX_OK;
+}
+
+// ---------------------------------------------------------------- geometry
+static const TileCfg kTiles[] = {{32, 32}, {64, 16}, {64, 32}, {32, 16}, {128, 8}, {16, 32}};
+
+int num_tile_cfgs() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
+TileCfg tile_cfg(int idx) { return kTiles[(idx >= 0 && idx < num_tile_cfgs()) ? idx : 0]; }
+
+void map_dims(const ssimx_params* p, int W, int H, int& Wo, int& Ho) {
+  const int Wp = p->padding == SSIMX_PAD_VALID ? W : W + p->k - 1;
+  const int Hp = p->padding == SSIMX_PAD_VALID ? H : H + p->k - 1;
+  Wo = Wp >= p->k ? (Wp - p->k) / p->stride + 1 : 0;
+  Ho = Hp >= p->k ? (Hp - p->k) / p->stride + 1 : 0;
+}
+
+static Geom geom_with(const ssimx_params* p, int W, int H, int tw, int th) {
+  Geom g{};
+  g.W = W;
+  g.H = H;
+  g.k = p->k;
+  g.s = p->stride;
+  g.pad = p->padding;
+  g.before = p->padding == SSIMX_PAD_VALID ? 0 : (p->k - 1) / 2;
+  g.Wp = p->padding == SSIMX_PAD_VALID ? W : W + p->k - 1;
+  g.Hp = p->padding == SSIMX_PAD_VALID ? H : H + p->k - 1;
+  map_dims(p, W, H, g.Wo, g.Ho);
+  g.TW = std::max(1, std::min(tw, g.Wo));
+  g.TH = std::max(1, std::min(th, g.Ho));
+  g.IW = (g.TW - 1) * g.s + g.k;
+  g.IH = (g.TH - 1) * g.s + g.k;
+  g.tiles_x = (g.Wo + g.TW - 1) / g.TW;
+  g.tiles_y = (g.Ho + g.TH - 1) / g.TH;
+  return g;
+}
+
+size_t path_lds_bytes(Path path, int dtype, const Geom& g) {
+  if (path == Path::kSep) return sep_lds_bytes(g);
+  if (path == Path::kBox) {
+    const size_t acc = dtype == SSIMX_U8 ? 4 : 8;
+    return acc * 5 * (size_t)g.IH * g.TW + 8 * (size_t)g.IH * g.IW + 4 * (BLOCK / 64);
+  }
+  return 0;
+}
+
+Geom make_geom_path(const ssimx_params* p, int dtype, int W, int H, int tile_idx) {
+  const TileCfg t = tile_cfg(tile_idx);
+  int tw = std::max(1, t.tw / p->stride), th = std::max(1, t.th / p->stride);
+  const Path path = choose_path(p, dtype);
+  Geom g = geom_with(p, W, H, tw, th);
+  while (path_lds_bytes(path, dtype, g) > kLdsLimit && (th > 1 || tw > 1)) {
+    if (th >= tw && th > 1)
+      th = std::max(1, th / 2);
+    else
+      tw = std::max(1, tw / 2);
+    g = geom_with(p, W, H, tw, th);
+  }
+  return g;
+}
+
+Geom make_geom(const ssimx_params* p, int W, int H, int tile_idx) {
+  return make_geom_path(p, SSIMX_U8, W, H, tile_idx);
+}
+
+// Worst-case number of pooling partials per frame over every tile config.
+int max_partials(const ssimx_params* p, int dtype, int W, int H) {
+  const Path path = choose_path(p, dtype);
+  int Wo, Ho;
+  map_dims(p, W, H, Wo, Ho);
+  if (path == Path::kSat) return (Wo * Ho + BLOCK - 1) / BLOCK;
+  int m = 1;
+  for (int i = 0; i < num_tile_cfgs(); ++i) {
+    const Geom g = make_geom_path(p, dtype, W, H, i);
+    m = std::max(m, g.tiles_x * g.tiles_y);
+  }
+  return m;
+}
+
+void gaussian_taps_f32(int window, int k, float sigma, float* out) {
+  if (window == SSIMX_WIN_BOX) {
+    for (int t = 0; t < k; ++t) out[t] = (float)(1.0 / k);
+    return;
+  }
+  double g[KMAX_GAUSS], sum = 0.0;
+  const double c = (k - 1) / 2.0;
+  for (int t = 0; t < k; ++t) {
+    const double d = t - c;
+    g[t] = exp(-(d * d) / (2.0 * (double)sigma * (double)sigma));
+  }
+  // sum the small tails first
+  for (int t = 0; t < k / 2; ++t) sum += g[t] + g[k - 1 - t];
+  if (k & 1) sum += g[k / 2];
+  for (int t = 0; t < k; ++t) out[t] = (float)(g[t] / sum);
+}
+
+// ---------------------------------------------------------------- workspace
+size_t Ws::take(size_t bytes) {
+  const size_t off = used;
+  used += (bytes + 255) & ~(size_t)255;
+  return off;
+}
+
+size_t fwd_ws_bytes(const ssimx_params* p, int dtype, int W, int H, int batch) {
+  Ws ws;
+  ws.take(sizeof(float) * (size_t)batch * max_partials(p, dtype, W, H));
+  if (choose_path(p, dtype) == Path::kSat) ws.take(sizeof(uint32_t) * 5 * (size_t)batch * (W + 1) * (size_t)(H + 1));
+  return ws.used;
+}
+
+// Per-scale sizes of the MS-SSIM pyramid.
+void scale_dims(int W, int H, int n_scales, int* Ws_, int* Hs_) {
+  Ws_[0] = W;
+  Hs_[0] = H;
+  for (int j = 1; j < n_scales; ++j) {
+    Ws_[j] = Ws_[j - 1] / 2;
+    Hs_[j] = Hs_[j - 1] / 2;
+  }
+}
+
+MsLayout ms_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int n_scales) {
+  MsLayout L{};
+  Ws ws;
+  scale_dims(W, H, n_scales, L.W, L.H);
+  for (int j = 0; j < n_scales; ++j) {
+    const int dt = j == 0 ? dtype : SSIMX_F32;
+    L.partial_off[j] = ws.take(sizeof(float) * (size_t)batch * max_partials(p, dt, L.W[j], L.H[j]));
+    if (j > 0) {
+      L.lvl_x_off[j] = ws.take(sizeof(float) * (size_t)batch * L.W[j] * L.H[j]);
+      L.lvl_y_off[j] = ws.take(sizeof(float) * (size_t)batch * L.W[j] * L.H[j]);
+    }
+  }
+  L.vals_off = ws.take(sizeof(float) * (size_t)batch * n_scales);
+  L.total = ws.used;
+  return L;
+}
+
+ssimx_status check_ms(const ssimx_params* p, const float* weights, int n_scales, int W, int H) {
+  if (!weights || n_scales < 1 || n_scales > MAX_SCALES) return SSIMX_EINVAL;
+  for (int j = 0; j < n_scales; ++j)
+    if (!isfinite(weights[j])) return SSIMX_EINVAL;
+  int Wj[MAX_SCALES], Hj[MAX_SCALES];
+  scale_dims(W, H, n_scales, Wj, Hj);
+  for (int j = 0; j < n_scales; ++j) {
+    int Wo, Ho;
+    if (Wj[j] < 1 || Hj[j] < 1) return SSIMX_ETOOSMALL;
+    map_dims(p, Wj[j], Hj[j], Wo, Ho);
+    if (Wo < 1 || Ho < 1) return SSIMX_ETOOSMALL;
+  }
+  return SSIMX_OK;
+}
+
+void ms_weights(const float* weights, int n_scales, int flags, float* w) {
+  double sum = 0.0;
+  for (int j = 0; j < n_scales; ++j) sum += weights[j];
+  for (int j = 0; j < n_scales; ++j) w[j] = (flags & SSIMX_MS_RENORM) ? (float)(weights[j] / sum) : weights[j];
+}
+
+// ---------------------------------------------------------------- forward core
+// One windowed pass over a batch of plane pairs: map (nullable), and the mean
+// of the pooled term written to out[frame * out_stride].
+ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, int mode,
+                      float* map, int64_t map_pitch, int64_t map_bstride, float* out, int64_t out_stride,
+                      float* partial, uint32_t* sat, int tile_idx, hipStream_t st) {
+  const Path path = choose_path(p, dtype);
+  const float C1 = (float)p->C1, C2 = (float)p->C2;
+  int err = 0, tiles = 0;
+  Geom g = make_geom_path(p, dtype, W, H, tile_idx);
+  if (path == Path::kSep) {
+    SepArgs a{};
+    a.x = x;
+    a.y = y;
+    a.g = g;
+    a.C1 = C1;
+    a.C2 = C2;
+    a.mode = mode;
+    a.map = map;
+    a.map_pitch = map_pitch;
+    a.map_bstride = map_bstride;
+    a.partial = partial;
+    gaussian_taps_f32(p->window, p->k, p->sigma, a.taps);
+    err = launch_sep_fwd(dtype, a, batch, sep_lds_bytes(g), st);
+    tiles = g.tiles_x * g.tiles_y;
+  } else if (path == Path::kBox) {
+    BoxArgs a{};
+    a.x = x;
+    a.y = y;
+    a.g = g;
+    a.C1 = C1;
+    a.C2 = C2;
+    a.mode = mode;
+    a.map = map;
+    a.map_pitch = map_pitch;
+    a.map_bstride = map_bstride;
+    a.partial = partial;
+    a.batch = batch;
+    err = launch_box_fwd(dtype, a, batch, st);
+    tiles = g.tiles_x * g.tiles_y;
+  } else {
+    err = launch_sat(dtype, x, y, W, H, batch, sat, st);
+    if (err) return hip_status(err);
+    err = launch_sat_ssim(sat, g, batch, C1, C2, mode, map, map_pitch, map_bstride, partial, nullptr, st);
+    tiles = (g.Wo * g.Ho + BLOCK - 1) / BLOCK;
+  }
+  if (err) return hip_status(err);
+  if (out) {
+    err = launch_finalize(partial, tiles, batch, g.Wo * g.Ho, 1.f, out, out_stride, st);
+    if (err) return hip_status(err);
+  }
+  return SSIMX_OK;
+}
+
+static ssimx_status fwd_entry(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                              float* map, int64_t map_pitch, int64_t map_bstride, float* score, void* ws,
+                              size_t ws_bytes, void* stream) {
+  ssimx_status s;
+  if ((s = check_params(p)) != SSIMX_OK) return s;
+  if ((s = check_images(ref, dis, batch)) != SSIMX_OK) return s;
+  if ((s = check_path(p, ref->dtype)) != SSIMX_OK) return s;
+  int Wo, Ho;
+  map_dims(p, ref->width, ref->height, Wo, Ho);
+  if (Wo < 1 || Ho < 1) return SSIMX_ETOOSMALL;
+  if (map && (map_pitch < Wo || (batch > 1 && map_bstride < map_pitch * (int64_t)Ho))) return SSIMX_EINVAL;
+  const size_t need = fwd_ws_bytes(p, ref->dtype, ref->width, ref->height, batch);
+  if (!ws || ws_bytes < need) return SSIMX_EWORKSPACE;
+  Ws lay;
+  float* partial = (float*)((char*)ws + lay.take(sizeof(float) * (size_t)batch *
+                                                 max_partials(p, ref->dtype, ref->width, ref->height)));
+  uint32_t* sat = nullptr;
+  if (choose_path(p, ref->dtype) == Path::kSat)
+    sat = (uint32_t*)((char*)ws + lay.take(sizeof(uint32_t) * 5 * (size_t)batch * (ref->width + 1) *
+                                           (size_t)(ref->height + 1)));
+  PlaneArg x{ref->data, ref->pitch, ref->batch_stride}, y{dis->data, dis->pitch, dis->batch_stride};
+  const int tile = pick_tile(p, ref->dtype, ref->width, ref->height, batch);
+  return fwd_pass(p, ref->dtype, x, y, ref->width, ref->height, batch, 0, map, map_pitch, map_bstride, score, 1,
+                  partial, sat, tile, (hipStream_t)stream);
+}
+
+ssimx_status ms_forward(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
+                        const ssimx_image* dis, int batch, float* score_out, float* cs_out, void* ws,
+                        const MsLayout& L, hipStream_t st) {
+  char* base = (char*)ws;
+  float* vals = (float*)(base + L.vals_off);
+  for (int j = 0; j < n_scales; ++j) {
+    PlaneArg x, y;
+    int dt;
+    if (j == 0) {
+      x = PlaneArg{ref->data, ref->pitch, ref->batch_stride};
+      y = PlaneArg{dis->data, dis->pitch, dis->batch_stride};
+      dt = ref->dtype;
+    } else {
+      x = PlaneArg{base + L.lvl_x_off[j], L.W[j], (int64_t)L.W[j] * L.H[j]};
+      y = PlaneArg{base + L.lvl_y_off[j], L.W[j], (int64_t)L.W[j] * L.H[j]};
+      dt = SSIMX_F32;
+    }
+    if (j + 1 < n_scales) {
+      const int err = launch_downsample(dt, x, L.W[j], L.H[j], (float*)(base + L.lvl_x_off[j + 1]),
+                                        (float*)(base + L.lvl_y_off[j + 1]), y, batch, st);
+      if (err) return hip_status(err);
+    }
+    const int mode = (j + 1 < n_scales) ? 1 : 0;
+    const int tile = pick_tile(p, dt, L.W[j], L.H[j], batch);
+    ssimx_status s = fwd_pass(p, dt, x, y, L.W[j], L.H[j], batch, mode, nullptr, 0, 0, vals + j, n_scales,
+                              (float*)(base + L.partial_off[j]), nullptr, tile, st);
+    if (s != SSIMX_OK) return s;
+  }
+  if (score_out) {
+    const int err = launch_ms_combine(vals, n_scales, batch, w, flags, score_out, cs_out, st);
+    if (err) return hip_status(err);
+  }
+  return SSIMX_OK;
+}
+
+}  // namespace ssimx
+
+using namespace ssimx;
+
+extern "C" {
+
+ssimx_status ssimx_map_shape(const ssimx_params* p, int width, int height, int* width_out, int* height_out) {
+  ssimx_status s = check_params(p);
+  if (s != SSIMX_OK) return s;
+  if (!width_out || !height_out || width < 1 || height < 1) return SSIMX_EINVAL;
+  map_dims(p, width, height, *width_out, *height_out);
+  if (*width_out < 1 || *height_out < 1) {
+    *width_out = std::max(0, *width_out);
+    *height_out = std::max(0, *height_out);
+    return SSIMX_ETOOSMALL;
+  }
+  return SSIMX_OK;
+}
+
+ssimx_status ssim_map(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                      float* map_out, int64_t map_pitch, int64_t map_batch_stride, float* score_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!map_out) return SSIMX_EINVAL;
+  return fwd_entry(p, ref, dis, batch, map_out, map_pitch, map_batch_stride, score_out, ws, ws_bytes, stream);
+}
+
+ssimx_status ssim_pooled(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                         float* score_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!score_out) return SSIMX_EINVAL;
+  return fwd_entry(p, ref, dis, batch, nullptr, 0, 0, score_out, ws, ws_bytes, stream);
+}
+
+ssimx_status msssim(const ssimx_params* p, const float* weights, int n_scales, int flags, const ssimx_image* ref,
+                    const ssimx_image* dis, int batch, float* score_out, float* cs_out, void* ws, size_t ws_bytes,
+                    void* stream) {
+  ssimx_status s;
+  if ((s = check_params(p)) != SSIMX_OK) return s;
+  if ((s = check_images(ref, dis, batch)) != SSIMX_OK) return s;
+  if (!score_out) return SSIMX_EINVAL;
+  if ((s = check_ms(p, weights, n_scales, ref->width, ref->height)) != SSIMX_OK) return s;
+  if ((s = check_path(p, ref->dtype)) != SSIMX_OK) return s;
+  if ((s = check_path(p, SSIMX_F32)) != SSIMX_OK) return s;
+  const MsLayout L = ms_layout(p, ref->dtype, ref->width, ref->height, batch, n_scales);
+  if (!ws || ws_bytes < L.total) return SSIMX_EWORKSPACE;
+  float w[MAX_SCALES];
+  ms_weights(weights, n_scales, flags, w);
+  return ms_forward(p, w, n_scales, flags, ref, dis, batch, score_out, cs_out, ws, L, (hipStream_t)stream);
+}
+
+ssimx_status ssimx_box_sums(int k, int stride, int algo, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                            int32_t* sums_out, void* ws, size_t ws_bytes, void* stream) {
+  ssimx_params p{};
+  p.window = SSIMX_WIN_BOX;
+  p.k = k;
+  p.sigma = 1.f;
+  p.stride = stride;
+  p.padding = SSIMX_PAD_VALID;
+  p.algo = algo;
+  ssimx_status s;
+  if ((s = check_params(&p)) != SSIMX_OK) return s;
+  if ((s = check_images(ref, dis, batch)) != SSIMX_OK) return s;
+  if (!is_integer(ref->dtype)) return SSIMX_EDTYPE;
+  if (!sums_out) return SSIMX_EINVAL;
+  int Wo, Ho;
+  map_dims(&p, ref->width, ref->height, Wo, Ho);
+  if (Wo < 1 || Ho < 1) return SSIMX_ETOOSMALL;
+  PlaneArg x{ref->data, ref->pitch, ref->batch_stride}, y{dis->data, dis->pitch, dis->batch_stride};
+  hipStream_t st = (hipStream_t)stream;
+  if (algo == SSIMX_ALGO_INTEGRAL_IMAGE) {
+    const size_t need = sizeof(uint32_t) * 5 * (size_t)batch * (ref->width + 1) * (size_t)(ref->height + 1);
+    if (!ws || ws_bytes < need) return SSIMX_EWORKSPACE;
+    const Geom g = make_geom_path(&p, ref->dtype, ref->width, ref->height, 0);
+    int err = launch_sat(ref->dtype, x, y, ref->width, ref->height, batch, (uint32_t*)ws, st);
+    if (!err) err = launch_sat_ssim((uint32_t*)ws, g, batch, 0.f, 0.f, 2, nullptr, 0, 0, nullptr, sums_out, st);
+    return hip_status(err);
+  }
+  BoxArgs a{};
+  a.x = x;
+  a.y = y;
+  a.g = make_geom_path(&p, ref->dtype, ref->width, ref->height, 0);
+  a.mode = 2;
+  a.sums = sums_out;
+  a.batch = batch;
+  return hip_status(launch_box_fwd(ref->dtype, a, batch, st));
+}
+
+ssimx_status ssimx_integral_images(const ssimx_image* ref, const ssimx_image* dis, int batch, uint32_t* sat_out,
+                                   void* stream) {
+  ssimx_status s;
+  if ((s = check_images(ref, dis, batch)) != SSIMX_OK) return s;
+  if (!is_integer(ref->dtype)) return SSIMX_EDTYPE;
+  if (!sat_out) return SSIMX_EINVAL;
+  PlaneArg x{ref->data, ref->pitch, ref->batch_stride}, y{dis->data, dis->pitch, dis->batch_stride};
+  return hip_status(launch_sat(ref->dtype, x, y, ref->width, ref->height, batch, sat_out, (hipStream_t)stream));
+}
+
+const char* ssimx_strerror(int status) {
+  switch (status) {
+    case SSIMX_OK: return "ok";
+    case SSIMX_EINVAL: return "invalid argument";
+    case SSIMX_EDTYPE: return "unsupported dtype";
+    case SSIMX_ETOOSMALL: return "input smaller than the window";
+    case SSIMX_EWORKSPACE: return "workspace missing or too small";
+    case SSIMX_EHIP: return "HIP runtime error";
+    case SSIMX_ENOTSUP: return "unsupported parameter combination";
+    case SSIMX_ENOMEM: return "out of memory";
+    default: return "unknown status";
+  }
+}
+
+int ssimx_last_hip_error(void) { return g_last_hip; }
+int ssimx_version(void) { return SSIMX_VERSION; }
+
+}  // extern "C"

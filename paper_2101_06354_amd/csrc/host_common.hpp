@@ -1,0 +1,58 @@
+// Host-only helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ssimx_internal.hpp"
+
+namespace ssimx {
+
+constexpr size_t kLdsLimit = 64 * 1024;  // dynamic LDS per block used by the tiled kernels
+
+enum class Path { kSep, kBox, kSat };
+
+extern thread_local int g_last_hip;
+ssimx_status hip_status(int err);
+
+ssimx_status check_params(const ssimx_params* p);
+ssimx_status check_images(const ssimx_image* a, const ssimx_image* b, int batch);
+ssimx_status check_path(const ssimx_params* p, int dtype);
+ssimx_status check_ms(const ssimx_params* p, const float* weights, int n_scales, int W, int H);
+bool is_integer(int dtype);
+Path choose_path(const ssimx_params* p, int dtype);
+void map_dims(const ssimx_params* p, int W, int H, int& Wo, int& Ho);
+Geom make_geom_path(const ssimx_params* p, int dtype, int W, int H, int tile_idx);
+int max_partials(const ssimx_params* p, int dtype, int W, int H);
+size_t path_lds_bytes(Path path, int dtype, const Geom& g);
+void scale_dims(int W, int H, int n_scales, int* Ws_, int* Hs_);
+void ms_weights(const float* weights, int n_scales, int flags, float* w);
+size_t fwd_ws_bytes(const ssimx_params* p, int dtype, int W, int H, int batch);
+
+// Bump allocator over a caller workspace (256-byte aligned slices).
+struct Ws {
+  size_t used = 0;
+  size_t take(size_t bytes);
+};
+
+struct MsLayout {
+  int W[MAX_SCALES], H[MAX_SCALES];
+  size_t partial_off[MAX_SCALES];
+  size_t lvl_x_off[MAX_SCALES], lvl_y_off[MAX_SCALES];
+  size_t vals_off;
+  size_t total;
+};
+MsLayout ms_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int n_scales);
+
+ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, int mode,
+                      float* map, int64_t map_pitch, int64_t map_bstride, float* out, int64_t out_stride,
+                      float* partial, uint32_t* sat, int tile_idx, hipStream_t st);
+ssimx_status ms_forward(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
+                        const ssimx_image* dis, int batch, float* score_out, float* cs_out, void* ws,
+                        const MsLayout& L, hipStream_t st);
+
+// Tile configuration for a call: explicit override, else the autotune cache,
+// else the default (index 0).
+int pick_tile(const ssimx_params* p, int dtype, int W, int H, int batch);
+
+}  // namespace ssimx

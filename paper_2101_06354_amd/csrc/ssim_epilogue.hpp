@@ -1,0 +1,58 @@
+// Per-position SSIM terms from local statistics, in the sum/difference basis
+// u = x + y, v = x - y used by the float kernels.
+//
+// With mu_x = (mu_u + mu_v)/2 and mu_y = (mu_u - mu_v)/2 the Background-section
+// terms become
+//   2 mu_x mu_y          = (mu_u^2 - mu_v^2) / 2
+//   mu_x^2 + mu_y^2      = (mu_u^2 + mu_v^2) / 2
+//   2 sigma_xy           = (var_u - var_v) / 2
+//   sigma_x^2+sigma_y^2  = (var_u + var_v) / 2
+// so the numerator and denominator of l (and of cs) differ by exactly
+// mu_v^2 (and var_v).  When x == y, mu_v = var_v = 0 and both are formed by the
+// same operations, so Q == 1.0f exactly; swapping x and y only flips the sign
+// of v, so Q is bitwise symmetric.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ssimx {
+
+struct SsimTerms {
+  float A1, B1, A2, B2;
+};
+
+__device__ __forceinline__ SsimTerms ssim_terms_uv(float mean_u, float mean_v, float var_u, float var_v, float C1,
+                                                   float C2) {
+  SsimTerms t;
+  const float P = (0.5f * mean_u) * mean_u;
+  const float R = (0.5f * mean_v) * mean_v;
+  t.A1 = (P - R) + C1;
+  t.B1 = (P + R) + C1;
+  t.A2 = 0.5f * (var_u - var_v) + C2;
+  t.B2 = 0.5f * (var_u + var_v) + C2;
+  return t;
+}
+
+// mode 0: Q = l*cs ; mode 1: cs
+__device__ __forceinline__ float ssim_value(const SsimTerms& t, int mode) {
+  if (mode == 1) return t.A2 / t.B2;
+  return (t.A1 * t.A2) / (t.B1 * t.B2);
+}
+
+// Same terms from exact integer window sums of a k x k rectangular window
+// (the statistics of the integral-image method): every numerator below is an
+// exact integer and is rounded to float once.
+__device__ __forceinline__ SsimTerms ssim_terms_box(int64_t sx, int64_t sy, int64_t sxx, int64_t syy, int64_t sxy,
+                                                    int64_t kk, float k4, float C1, float C2) {
+  const int64_t nxx = kk * sxx - sx * sx;
+  const int64_t nyy = kk * syy - sy * sy;
+  const int64_t nxy = kk * sxy - sx * sy;
+  SsimTerms t;
+  t.A1 = (float)(2 * sx * sy) / k4 + C1;
+  t.B1 = (float)(sx * sx + sy * sy) / k4 + C1;
+  t.A2 = (float)(2 * nxy) / k4 + C2;
+  t.B2 = (float)(nxx + nyy) / k4 + C2;
+  return t;
+}
+
+}  // namespace ssimx

@@ -1,0 +1,160 @@
+// Internal declarations shared by the HIP translation units of libssimx.
+// Not part of the public ABI (include/ssimx.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ssimx.h"
+
+namespace ssimx {
+
+constexpr int KMAX_GAUSS = 41;  // largest Gaussian window (odd)
+constexpr int KMAX_BOX = 64;    // largest rectangular window
+constexpr int BLOCK = 256;      // threads per block of the tiled kernels
+constexpr int MAX_SCALES = 8;
+
+struct bf16_t {
+  uint16_t bits;
+};
+
+// ---------------------------------------------------------------- scalars
+template <typename T>
+__device__ __forceinline__ float to_f32(T v);
+template <>
+__device__ __forceinline__ float to_f32<uint8_t>(uint8_t v) { return (float)v; }
+template <>
+__device__ __forceinline__ float to_f32<uint16_t>(uint16_t v) { return (float)v; }
+template <>
+__device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f32<bf16_t>(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+
+template <typename T>
+__device__ __forceinline__ int32_t to_i32(T v) { return (int32_t)v; }
+
+// Half-sample symmetric reflection of index i into [0, n) (period 2n).
+__device__ __forceinline__ int reflect_index(int i, int n) {
+  const int p = 2 * n;
+  int m = i % p;
+  if (m < 0) m += p;
+  return m < n ? m : p - 1 - m;
+}
+
+// Source pixel of padded coordinate (py, px); returns false for zero padding
+// outside the plane and for coordinates past the padded extent.
+__device__ __forceinline__ bool padded_source(int py, int px, int H, int W, int pad, int before, int Hp, int Wp,
+                                              int& sy, int& sx) {
+  if (py >= Hp || px >= Wp) return false;
+  if (pad == SSIMX_PAD_VALID) {
+    sy = py;
+    sx = px;
+    return true;
+  }
+  int yy = py - before, xx = px - before;
+  if (pad == SSIMX_PAD_ZERO) {
+    if (yy < 0 || yy >= H || xx < 0 || xx >= W) return false;
+    sy = yy;
+    sx = xx;
+    return true;
+  }
+  sy = reflect_index(yy, H);
+  sx = reflect_index(xx, W);
+  return true;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Error-free transformation a + b = s + e.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Deterministic block sum of one float per thread (fixed shuffle order, then
+// fixed order across waves).  Result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ float block_sum(float v, float* lds_scratch) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds_scratch[wid] = v;
+  __syncthreads();
+  float r = 0.f;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) r += lds_scratch[w];
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- arguments
+struct PlaneArg {
+  const void* data;
+  int64_t pitch, bstride;
+};
+
+// Geometry of a windowed pass over one plane pair.
+struct Geom {
+  int W, H;        // unpadded plane
+  int Wp, Hp;      // padded extent (== W, H for valid)
+  int Wo, Ho;      // map
+  int k, s, pad, before;
+  int TW, TH;      // outputs per tile
+  int IW, IH;      // input footprint of a tile
+  int tiles_x, tiles_y;
+};
+
+struct SepArgs {
+  PlaneArg x, y;
+  Geom g;
+  float C1, C2;
+  int mode;            // 0: Q = l*cs, 1: cs only
+  float* map;          // nullable
+  int64_t map_pitch, map_bstride;
+  float* partial;      // [batch][tiles] tile sums of the pooled term
+  float taps[KMAX_GAUSS];
+};
+
+struct BoxArgs {
+  PlaneArg x, y;
+  Geom g;
+  float C1, C2;
+  int mode;            // 0: Q, 1: cs, 2: emit the five sums
+  float* map;
+  int64_t map_pitch, map_bstride;
+  float* partial;
+  int32_t* sums;       // mode 2: [5][batch][Ho][Wo]
+  int batch;
+};
+
+// Host helpers (defined in host.hip) --------------------------------------
+struct TileCfg {
+  int tw, th;  // outputs per tile at stride 1 (scaled for larger strides)
+};
+int num_tile_cfgs();
+TileCfg tile_cfg(int idx);
+Geom make_geom(const ssimx_params* p, int W, int H, int tile_idx);
+void gaussian_taps_f32(int window, int k, float sigma, float* out);
+
+// Launchers (return hipError_t as int) ------------------------------------
+int launch_sep_fwd(int dtype, const SepArgs& a, int batch, size_t lds_bytes, hipStream_t st);
+int launch_box_fwd(int dtype, const BoxArgs& a, int batch, hipStream_t st);
+int launch_finalize(const float* partial, int tiles, int batch, int count_per_frame, float scale, float* out,
+                    int64_t out_stride, hipStream_t st);
+int launch_downsample(int dtype, PlaneArg in, int W, int H, float* outx, float* outy, PlaneArg iny,
+                      int batch, hipStream_t st);
+int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w, int flags, float* score_out,
+                      float* cs_out, hipStream_t st);
+int launch_sat(int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, uint32_t* sat, hipStream_t st);
+int launch_sat_ssim(const uint32_t* sat, const Geom& g, int batch, float C1, float C2, int mode, float* map,
+                    int64_t map_pitch, int64_t map_bstride, float* partial, int32_t* sums, hipStream_t st);
+
+size_t sep_lds_bytes(const Geom& g);
+
+}  // namespace ssimx

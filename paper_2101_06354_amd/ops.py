@@ -1,0 +1,317 @@
+"""Python binding of libssimx: argument marshalling for torch device tensors.
+
+PyTorch supplies device memory (outputs and workspace) and the current HIP
+stream only; every step of SSIM / MS-SSIM runs in the library's kernels.
+Planes are (H, W) or (B, H, W) tensors whose last dimension is contiguous:
+uint8, uint16, float32 or bfloat16.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+MS_WEIGHTS = (0.0448, 0.2856, 0.3001, 0.2363, 0.1333)
+
+_DTYPES = {torch.uint8: L.U8, torch.float32: L.F32, torch.bfloat16: L.BF16}
+if hasattr(torch, "uint16"):
+    _DTYPES[torch.uint16] = L.U16
+_WINDOWS = {"gaussian": L.WIN_GAUSSIAN, "box": L.WIN_BOX}
+_PADS = {"valid": L.PAD_VALID, "zero": L.PAD_ZERO, "reflect": L.PAD_REFLECT}
+_ALGOS = {"auto": L.ALGO_AUTO, "separable": L.ALGO_SEPARABLE, "integral": L.ALGO_INTEGRAL_IMAGE,
+          "integral_image": L.ALGO_INTEGRAL_IMAGE}
+
+
+@dataclass
+class SSIMConfig:
+    """Window type, size and sigma, C1 = (K1 L)^2, C2 = (K2 L)^2, stride,
+    border handling and (rectangular windows on integer planes) algorithm."""
+    window: str = "gaussian"
+    k: int = 11
+    sigma: float = 1.5
+    K1: float = 0.01
+    K2: float = 0.03
+    L: float = 255.0
+    C1: float | None = None
+    C2: float | None = None
+    stride: int = 1
+    padding: str = "valid"
+    algo: str = "auto"
+
+    def c1(self) -> float:
+        return (self.K1 * self.L) ** 2 if self.C1 is None else float(self.C1)
+
+    def c2(self) -> float:
+        return (self.K2 * self.L) ** 2 if self.C2 is None else float(self.C2)
+
+    def to_c(self) -> L.Params:
+        try:
+            return L.Params(_WINDOWS[self.window], int(self.k), float(self.sigma), self.c1(), self.c2(),
+                            int(self.stride), _PADS[self.padding], _ALGOS[self.algo])
+        except KeyError as e:
+            raise ValueError(f"unknown option {e}") from None
+
+
+def _cfg(cfg: SSIMConfig | None, kw: dict) -> SSIMConfig:
+    if cfg is not None and kw:
+        raise ValueError("pass either cfg or keyword options")
+    return cfg if cfg is not None else SSIMConfig(**kw)
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _as3(t: torch.Tensor) -> torch.Tensor:
+    if t.dim() == 2:
+        return t.unsqueeze(0)
+    if t.dim() != 3:
+        raise ValueError("planes must be (H, W) or (B, H, W)")
+    return t
+
+
+def _image(t: torch.Tensor) -> L.Image:
+    if not t.is_cuda:
+        raise ValueError("libssimx needs device tensors (no CPU fallback)")
+    if t.dtype not in _DTYPES:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    t3 = _as3(t)
+    if t3.stride(2) != 1:
+        raise ValueError("the last dimension must be contiguous")
+    b, h, w = t3.shape
+    return L.Image(t3.data_ptr(), _DTYPES[t.dtype], w, h, t3.stride(1), t3.stride(0) if b > 1 else t3.stride(1) * h)
+
+
+def _pair(x: torch.Tensor, y: torch.Tensor):
+    if x.shape != y.shape or x.dtype != y.dtype or x.device != y.device:
+        raise ValueError("ref and dis must have the same shape, dtype and device")
+    return _image(x), _image(y), _as3(x).shape[0]
+
+
+def map_shape(cfg: SSIMConfig, h: int, w: int) -> tuple[int, int]:
+    wo, ho = ctypes.c_int(), ctypes.c_int()
+    st = L.lib.ssimx_map_shape(ctypes.byref(cfg.to_c()), w, h, ctypes.byref(wo), ctypes.byref(ho))
+    L.check(st, "ssimx_map_shape")
+    return ho.value, wo.value
+
+
+def workspace_size(cfg: SSIMConfig, op: int, dtype: int, h: int, w: int, batch: int, n_scales: int = 1) -> int:
+    n = ctypes.c_size_t()
+    st = L.lib.ssimx_workspace_size(ctypes.byref(cfg.to_c()), op, dtype, w, h, batch, n_scales, ctypes.byref(n))
+    L.check(st, "ssimx_workspace_size")
+    return n.value
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(1, nbytes), dtype=torch.uint8, device=device)
+
+
+def ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, return_map: bool = False, **kw):
+    """Mean SSIM per frame (float32 [B]); with return_map also the float32
+    [B, Ho, Wo] quality map."""
+    cfg = _cfg(cfg, kw)
+    xi, yi, b = _pair(x, y)
+    p = cfg.to_c()
+    ho, wo = map_shape(cfg, xi.height, xi.width)
+    ws = _workspace(workspace_size(cfg, L.OP_MAP, xi.dtype, xi.height, xi.width, b), x.device)
+    score = torch.empty(b, dtype=torch.float32, device=x.device)
+    if return_map:
+        m = torch.empty((b, ho, wo), dtype=torch.float32, device=x.device)
+        st = L.lib.ssim_map(ctypes.byref(p), ctypes.byref(xi), ctypes.byref(yi), b, m.data_ptr(), wo, ho * wo,
+                            score.data_ptr(), ws.data_ptr(), ws.numel(), _stream(x))
+        L.check(st, "ssim_map")
+        return score, m
+    st = L.lib.ssim_pooled(ctypes.byref(p), ctypes.byref(xi), ctypes.byref(yi), b, score.data_ptr(),
+                           ws.data_ptr(), ws.numel(), _stream(x))
+    L.check(st, "ssim_pooled")
+    return score
+
+
+def _weights(weights, n_scales):
+    if len(weights) < n_scales:
+        raise ValueError("need one weight per scale")
+    return (ctypes.c_float * n_scales)(*[float(v) for v in weights[:n_scales]])
+
+
+def ms_ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, weights=MS_WEIGHTS,
+            n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, return_cs: bool = False, **kw):
+    """MS-SSIM per frame (float32 [B]); with return_cs also [B, n_scales]
+    holding CS_1..CS_{M-1} and S_M."""
+    cfg = _cfg(cfg, kw)
+    xi, yi, b = _pair(x, y)
+    p = cfg.to_c()
+    flags = (L.MS_RENORM if renorm else 0) | (L.MS_CS_CLAMP if cs_clamp else 0)
+    ws = _workspace(workspace_size(cfg, L.OP_MSSSIM, xi.dtype, xi.height, xi.width, b, n_scales), x.device)
+    score = torch.empty(b, dtype=torch.float32, device=x.device)
+    cs = torch.empty((b, n_scales), dtype=torch.float32, device=x.device) if return_cs else None
+    st = L.lib.msssim(ctypes.byref(p), _weights(weights, n_scales), n_scales, flags, ctypes.byref(xi),
+                      ctypes.byref(yi), b, score.data_ptr(), cs.data_ptr() if cs is not None else None,
+                      ws.data_ptr(), ws.numel(), _stream(x))
+    L.check(st, "msssim")
+    return (score, cs) if return_cs else score
+
+
+def ssim_backward(x: torch.Tensor, y: torch.Tensor, grad_score: torch.Tensor, cfg: SSIMConfig | None = None, **kw):
+    """d(sum_b grad_score[b] * SSIM_b)/dy, float32 shaped like y."""
+    cfg = _cfg(cfg, kw)
+    xi, yi, b = _pair(x, y)
+    p = cfg.to_c()
+    g = grad_score.to(device=x.device, dtype=torch.float32).reshape(b).contiguous()
+    out = torch.empty(_as3(y).shape, dtype=torch.float32, device=x.device)
+    ws = _workspace(workspace_size(cfg, L.OP_POOLED_BACKWARD, xi.dtype, xi.height, xi.width, b), x.device)
+    st = L.lib.ssim_pooled_backward(ctypes.byref(p), ctypes.byref(xi), ctypes.byref(yi), b, g.data_ptr(),
+                                    out.data_ptr(), out.stride(1), out.stride(0), ws.data_ptr(), ws.numel(),
+                                    _stream(x))
+    L.check(st, "ssim_pooled_backward")
+    return out.reshape(y.shape)
+
+
+def ssim_map_backward(x: torch.Tensor, y: torch.Tensor, grad_map: torch.Tensor, cfg: SSIMConfig | None = None,
+                      **kw):
+    """sum_p grad_map(p) dQ(p)/dy, float32 shaped like y."""
+    cfg = _cfg(cfg, kw)
+    xi, yi, b = _pair(x, y)
+    p = cfg.to_c()
+    gm = _as3(grad_map.to(device=x.device, dtype=torch.float32)).contiguous()
+    out = torch.empty(_as3(y).shape, dtype=torch.float32, device=x.device)
+    ws = _workspace(workspace_size(cfg, L.OP_MAP_BACKWARD, xi.dtype, xi.height, xi.width, b), x.device)
+    st = L.lib.ssim_map_backward(ctypes.byref(p), ctypes.byref(xi), ctypes.byref(yi), b, gm.data_ptr(),
+                                 gm.stride(1), gm.stride(0), out.data_ptr(), out.stride(1), out.stride(0),
+                                 ws.data_ptr(), ws.numel(), _stream(x))
+    L.check(st, "ssim_map_backward")
+    return out.reshape(y.shape)
+
+
+def ms_ssim_backward(x: torch.Tensor, y: torch.Tensor, grad_score: torch.Tensor, cfg: SSIMConfig | None = None,
+                     weights=MS_WEIGHTS, n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, **kw):
+    cfg = _cfg(cfg, kw)
+    xi, yi, b = _pair(x, y)
+    p = cfg.to_c()
+    flags = (L.MS_RENORM if renorm else 0) | (L.MS_CS_CLAMP if cs_clamp else 0)
+    g = grad_score.to(device=x.device, dtype=torch.float32).reshape(b).contiguous()
+    out = torch.empty(_as3(y).shape, dtype=torch.float32, device=x.device)
+    ws = _workspace(workspace_size(cfg, L.OP_MSSSIM_BACKWARD, xi.dtype, xi.height, xi.width, b, n_scales),
+                    x.device)
+    st = L.lib.msssim_backward(ctypes.byref(p), _weights(weights, n_scales), n_scales, flags, ctypes.byref(xi),
+                               ctypes.byref(yi), b, g.data_ptr(), out.data_ptr(), out.stride(1), out.stride(0),
+                               ws.data_ptr(), ws.numel(), _stream(x))
+    L.check(st, "msssim_backward")
+    return out.reshape(y.shape)
+
+
+def box_sums(x: torch.Tensor, y: torch.Tensor, k: int, stride: int = 1, algo: str = "auto") -> torch.Tensor:
+    """int32 [5, B, Ho, Wo]: S1x, S1y, S2x, S2y, S12 of every k x k window."""
+    xi, yi, b = _pair(x, y)
+    cfg = SSIMConfig(window="box", k=k, stride=stride)
+    ho, wo = map_shape(cfg, xi.height, xi.width)
+    out = torch.empty((5, b, ho, wo), dtype=torch.int32, device=x.device)
+    a = _ALGOS[algo]
+    nws = 5 * b * (xi.width + 1) * (xi.height + 1) * 4 if a == L.ALGO_INTEGRAL_IMAGE else 0
+    ws = _workspace(nws, x.device)
+    st = L.lib.ssimx_box_sums(k, stride, a, ctypes.byref(xi), ctypes.byref(yi), b, out.data_ptr(), ws.data_ptr(),
+                              ws.numel(), _stream(x))
+    L.check(st, "ssimx_box_sums")
+    return out
+
+
+def integral_images(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """The five uint32 integral images as int32 bits [5, B, H+1, W+1]."""
+    xi, yi, b = _pair(x, y)
+    out = torch.empty((5, b, xi.height + 1, xi.width + 1), dtype=torch.int32, device=x.device)
+    st = L.lib.ssimx_integral_images(ctypes.byref(xi), ctypes.byref(yi), b, out.data_ptr(), _stream(x))
+    L.check(st, "ssimx_integral_images")
+    return out
+
+
+def autotune(cfg: SSIMConfig, dtype, h: int, w: int, batch: int = 1, device="cuda") -> int:
+    best = ctypes.c_int(-1)
+    dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    st = L.lib.ssimx_autotune(ctypes.byref(cfg.to_c()), dt, w, h, batch,
+                              torch.cuda.current_stream(torch.device(device)).cuda_stream, ctypes.byref(best))
+    L.check(st, "ssimx_autotune")
+    return best.value
+
+
+def tune_cache_save(path: str) -> None:
+    L.check(L.lib.ssimx_tune_cache_save(path.encode()), "ssimx_tune_cache_save")
+
+
+def tune_cache_load(path: str) -> None:
+    L.check(L.lib.ssimx_tune_cache_load(path.encode()), "ssimx_tune_cache_load")
+
+
+def set_tile_override(tile: int) -> None:
+    L.check(L.lib.ssimx_set_tile_override(int(tile)), "ssimx_set_tile_override")
+
+
+def num_tile_configs() -> int:
+    return L.lib.ssimx_num_tile_configs()
+
+
+class BatchPlan:
+    """Ragged batch of independent pairs: one persistent, graph-captured
+    launch per run().  pairs: list of dicts {ref, dis, cfg (SSIMConfig),
+    map (optional float32 [Ho, Wo] output)}; the tensors are kept alive by
+    the plan."""
+
+    def __init__(self, pairs, device=None):
+        self._keep = []
+        arr = (L.Pair * len(pairs))()
+        dev = None
+        for i, pr in enumerate(pairs):
+            x, y = pr["ref"], pr["dis"]
+            if x.dim() != 2:
+                raise ValueError("batch-plan pairs are single (H, W) planes")
+            xi, yi, _ = _pair(x, y)
+            cfg = pr.get("cfg") or SSIMConfig()
+            m = pr.get("map")
+            arr[i].ref = xi
+            arr[i].dis = yi
+            arr[i].p = cfg.to_c()
+            arr[i].map_out = m.data_ptr() if m is not None else None
+            arr[i].map_pitch = m.stride(0) if m is not None else 0
+            self._keep += [x, y, m]
+            dev = x.device
+        self.device = device or dev
+        self.n = len(pairs)
+        self._h = ctypes.c_void_p()
+        st = L.lib.ssimx_plan_create(arr, self.n, torch.cuda.current_stream(self.device).cuda_stream,
+                                     ctypes.byref(self._h))
+        L.check(st, "ssimx_plan_create")
+
+    def info(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        L.check(L.lib.ssimx_plan_info(self._h, ctypes.byref(a), ctypes.byref(b)), "ssimx_plan_info")
+        return a.value, b.value
+
+    def run(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = out if out is not None else torch.empty(self.n, dtype=torch.float32, device=self.device)
+        st = L.lib.ssimx_plan_run(self._h, out.data_ptr(), torch.cuda.current_stream(self.device).cuda_stream)
+        L.check(st, "ssimx_plan_run")
+        return out
+
+    def run_unbatched(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = out if out is not None else torch.empty(self.n, dtype=torch.float32, device=self.device)
+        st = L.lib.ssimx_plan_run_unbatched(self._h, out.data_ptr(),
+                                            torch.cuda.current_stream(self.device).cuda_stream)
+        L.check(st, "ssimx_plan_run_unbatched")
+        return out
+
+    def close(self):
+        if self._h:
+            L.lib.ssimx_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _unused():
+    return math

@@ -1,0 +1,205 @@
+"""GPU parity of the forward path (ssim_map / ssim_pooled / msssim / box sums /
+integral images) against the FP64 oracle, through the C-ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from _helpers import MAP_TOL, SCORE_TOL, bf16_round, device, oparams, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2101_06354_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def _gpu_map(P, x, y, cfg, dev):
+    s, m = P.ssim(to_dev(x, dev), to_dev(y, dev), cfg, return_map=True)
+    torch.cuda.synchronize()
+    return s.cpu().numpy().astype(np.float64), m.cpu().numpy().astype(np.float64)
+
+
+def _check_map(P, x, y, cfg, dev, xo=None, yo=None, tol=MAP_TOL):
+    s, m = _gpu_map(P, x, y, cfg, dev)
+    ref = O.ssim_map(x if xo is None else xo, y if yo is None else yo, oparams(cfg))["map"]
+    assert m.shape[1:] == ref.shape
+    err = np.abs(m[0] - ref).max()
+    assert err <= tol, f"map error {err}"
+    serr = abs(s[0] - O.mean_pool(ref))
+    assert serr <= SCORE_TOL, f"score error {serr}"
+    return m[0], ref
+
+
+def test_config0_gaussian_parity(P, dev):
+    x, y = synth.config0()
+    cfg = P.SSIMConfig()
+    m, ref = _check_map(P, x, y, cfg, dev)
+    assert m.shape == (246, 246)
+
+
+@pytest.mark.parametrize("case", sorted(synth.stress_pairs().keys()))
+@pytest.mark.parametrize("window,k,stride", [("gaussian", 11, 1), ("gaussian", 11, 4), ("box", 8, 1), ("box", 8, 4),
+                                             ("gaussian", 7, 3)])
+def test_stress_parity(P, dev, case, window, k, stride):
+    x, y = synth.stress_pairs()[case]
+    sig = 1.5 if k == 11 else 1.0
+    _check_map(P, x, y, P.SSIMConfig(window=window, k=k, sigma=sig, stride=stride), dev)
+
+
+@pytest.mark.parametrize("padding", ["zero", "reflect"])
+@pytest.mark.parametrize("window,k,stride", [("gaussian", 11, 1), ("box", 8, 1), ("gaussian", 5, 2), ("box", 3, 3)])
+def test_padding_parity(P, dev, padding, window, k, stride):
+    rng = np.random.default_rng(3)
+    x = synth.smooth_field(rng, 61, 77, 16, 235).round().astype(np.uint8)
+    y = np.clip(x + rng.normal(0, 12, x.shape).round(), 0, 255).astype(np.uint8)
+    sig = 1.5 if k == 11 else 1.0
+    m, ref = _check_map(P, x, y, P.SSIMConfig(window=window, k=k, sigma=sig, stride=stride, padding=padding), dev)
+    if stride == 1:
+        assert m.shape == x.shape
+
+
+@pytest.mark.parametrize("h,w", [(11, 11), (11, 12), (12, 11), (45, 300), (300, 45), (129, 257)])
+def test_ragged_and_minimal_sizes(P, dev, h, w):
+    rng = np.random.default_rng(h * 1000 + w)
+    x = rng.integers(0, 256, (h, w)).astype(np.uint8)
+    y = rng.integers(0, 256, (h, w)).astype(np.uint8)
+    for window, k in (("gaussian", 11), ("box", 8)):
+        _check_map(P, x, y, P.SSIMConfig(window=window, k=k), dev)
+
+
+def test_identity_exact_and_bitwise_symmetry(P, dev):
+    x, y = synth.config0()
+    for cfg in (P.SSIMConfig(), P.SSIMConfig(window="box", k=8), P.SSIMConfig(stride=4, padding="reflect")):
+        _, mxx = _gpu_map(P, x, x, cfg, dev)
+        assert np.all(mxx == 1.0)
+        _, mxy = _gpu_map(P, x, y, cfg, dev)
+        _, myx = _gpu_map(P, y, x, cfg, dev)
+        np.testing.assert_array_equal(mxy, myx)
+        assert np.all(np.abs(mxy) <= 1.0)
+
+
+def test_u16_ten_bit(P, dev):
+    x, y = synth.config2(frames=1, h=150, w=203)
+    cfg = P.SSIMConfig(L=1023.0)
+    _check_map(P, x[0], y[0], cfg, dev)
+    _check_map(P, x[0], y[0], P.SSIMConfig(L=1023.0, window="box", k=8), dev)
+
+
+def test_float32_and_bf16_planes(P, dev):
+    r, d = synth.config4(batch=1, h=96, w=120)
+    x, y = r[0, 1], d[0, 1]
+    cfg = P.SSIMConfig(L=1.0)
+    _check_map(P, x, y, cfg, dev)
+    _check_map(P, x, y, P.SSIMConfig(L=1.0, window="box", k=8), dev)
+    xb, yb = bf16_round(x), bf16_round(y)
+    s, m = P.ssim(to_dev(x, dev).bfloat16(), to_dev(y, dev).bfloat16(), cfg, return_map=True)
+    ref = O.ssim_map(xb, yb, oparams(cfg))["map"]
+    assert np.abs(m[0].cpu().numpy() - ref).max() <= MAP_TOL
+    assert abs(float(s[0]) - O.mean_pool(ref)) <= SCORE_TOL
+
+
+def test_batch_with_pitch_and_frame_stride(P, dev):
+    rng = np.random.default_rng(5)
+    big = rng.integers(0, 256, (3, 70, 100)).astype(np.uint8)
+    big2 = np.clip(big + rng.integers(-20, 21, big.shape), 0, 255).astype(np.uint8)
+    xt, yt = to_dev(big, dev)[:, 3:63, 5:90], to_dev(big2, dev)[:, 3:63, 5:90]
+    cfg = P.SSIMConfig()
+    s, m = P.ssim(xt, yt, cfg, return_map=True)
+    for f in range(3):
+        ref = O.ssim_map(big[f, 3:63, 5:90], big2[f, 3:63, 5:90], oparams(cfg))["map"]
+        assert np.abs(m[f].cpu().numpy() - ref).max() <= MAP_TOL
+        assert abs(float(s[f]) - O.mean_pool(ref)) <= SCORE_TOL
+
+
+@pytest.mark.parametrize("k,stride", [(8, 1), (8, 4), (11, 1), (3, 2)])
+@pytest.mark.parametrize("algo", ["separable", "integral"])
+def test_box_sums_bit_exact(P, dev, k, stride, algo):
+    rng = np.random.default_rng(7)
+    x = rng.integers(0, 256, (2, 53, 71)).astype(np.uint8)
+    y = rng.integers(0, 256, (2, 53, 71)).astype(np.uint8)
+    got = P.box_sums(to_dev(x, dev), to_dev(y, dev), k, stride, algo).cpu().numpy()
+    for f in range(2):
+        want = O.box_sums_direct(x[f], y[f], k, stride)
+        for q in range(5):
+            np.testing.assert_array_equal(got[q, f], want[q])
+
+
+def test_integral_images_bit_exact_with_wraparound(P, dev):
+    rng = np.random.default_rng(8)
+    x = rng.integers(200, 256, (1, 300, 311)).astype(np.uint8)   # sum x^2 over the frame > 2^32
+    y = rng.integers(0, 256, (1, 300, 311)).astype(np.uint8)
+    got = P.integral_images(to_dev(x, dev), to_dev(y, dev)).cpu().numpy().view(np.uint32)
+    want = O.integral_images(x[0], y[0])
+    assert int(want[2][-1, -1]) != int(np.sum(x.astype(np.int64) ** 2))  # wrapped
+    for q in range(5):
+        np.testing.assert_array_equal(got[q, 0], want[q])
+
+
+@pytest.mark.parametrize("algo", ["separable", "integral"])
+@pytest.mark.parametrize("stride", [1, 4])
+def test_box_window_ssim_both_algorithms(P, dev, algo, stride):
+    x, y = synth.config1(frames=1, h=120, w=200)
+    _check_map(P, x[0], y[0], P.SSIMConfig(window="box", k=8, stride=stride, algo=algo), dev)
+
+
+def test_u16_box_sums_integral(P, dev):
+    x, y = synth.config2(frames=1, h=64, w=80)
+    got = P.box_sums(to_dev(x, dev), to_dev(y, dev), 8, 1, "integral").cpu().numpy()
+    want = O.box_sums_direct(x[0], y[0], 8, 1)
+    for q in range(5):
+        np.testing.assert_array_equal(got[q, 0], want[q])
+
+
+@pytest.mark.parametrize("n_scales,renorm", [(5, False), (3, True), (1, False)])
+def test_msssim_u16_parity(P, dev, n_scales, renorm):
+    x, y = synth.config2(frames=2, h=270, w=480)
+    cfg = P.SSIMConfig(L=1023.0)
+    w = P.MS_WEIGHTS if n_scales > 1 else (1.0,)
+    s, cs = P.ms_ssim(to_dev(x, dev), to_dev(y, dev), cfg, weights=w, n_scales=n_scales, renorm=renorm,
+                      return_cs=True)
+    s, cs = s.cpu().numpy(), cs.cpu().numpy()
+    for f in range(2):
+        r = O.msssim(x[f], y[f], oparams(cfg), w, n_scales, renorm)
+        assert abs(s[f] - r["score"]) <= SCORE_TOL
+        np.testing.assert_allclose(cs[f, :-1], r["cs"], rtol=0, atol=SCORE_TOL)
+        assert abs(cs[f, -1] - r["s_M"]) <= SCORE_TOL
+
+
+def test_msssim_float_rgb_luma_planes(P, dev):
+    r, d = synth.config4(batch=2, h=128, w=160)
+    x = (0.299 * r[:, 0] + 0.587 * r[:, 1] + 0.114 * r[:, 2]).astype(np.float32)
+    y = (0.299 * d[:, 0] + 0.587 * d[:, 1] + 0.114 * d[:, 2]).astype(np.float32)
+    cfg = P.SSIMConfig(L=1.0)
+    s = P.ms_ssim(to_dev(x, dev), to_dev(y, dev), cfg, n_scales=3, renorm=True).cpu().numpy()
+    for f in range(2):
+        assert abs(s[f] - O.msssim(x[f], y[f], oparams(cfg), n_scales=3, renorm=True)["score"]) <= SCORE_TOL
+
+
+def test_msssim_identity_and_clamp(P, dev):
+    x, _ = synth.config0()
+    cfg = P.SSIMConfig()
+    s = P.ms_ssim(to_dev(x, dev), to_dev(x, dev), cfg, n_scales=4, renorm=True)
+    assert float(s[0]) == 1.0
+    xx = (((np.mgrid[0:120, 0:120][0] // 3) % 2) * 255).astype(np.uint8)
+    yy = (255 - xx).astype(np.uint8)
+    s = P.ms_ssim(to_dev(xx, dev), to_dev(yy, dev), cfg, n_scales=2)
+    assert np.isnan(float(s[0]))
+    s = P.ms_ssim(to_dev(xx, dev), to_dev(yy, dev), cfg, n_scales=2, cs_clamp=True)
+    assert float(s[0]) == 0.0
+
+
+def test_deterministic(P, dev):
+    x, y = synth.config1(frames=2, h=200, w=300)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    a = P.ssim(xt, yt, P.SSIMConfig(), return_map=True)
+    b = P.ssim(xt, yt, P.SSIMConfig(), return_map=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
