@@ -180,6 +180,20 @@ ssimx_status ssimx_box_sums(int k, int stride, int algo, const ssimx_image* ref,
 ssimx_status ssimx_integral_images(const ssimx_image* ref, const ssimx_image* dis, int batch,
                                    uint32_t* sat_out, void* stream);
 
+/* Colour front end of the differentiable-loss workload: BT.601 luma
+ * Y = 0.299 R + 0.587 G + 0.114 B of planar RGB (the paper's Channel-wise SSIM
+ * subsection prints the BT.709 matrix; BT.601 weights are used here).
+ * rgb: float32 or bfloat16 planes, element (b, c, r, col) at
+ * b*batch_stride + c*channel_stride + r*pitch + col.
+ * y_out: float32 [batch][height][width], contiguous. */
+ssimx_status ssimx_rgb_to_luma(const void* rgb, int dtype, int width, int height, int64_t pitch,
+                               int64_t channel_stride, int64_t batch_stride, int batch, float* y_out, void* stream);
+/* Adjoint: grad_rgb(b, c, r, col) = weight_c * grad_y(b, r, col) (overwrites).
+ * grad_y: float32 [batch][height][width] contiguous; grad_rgb: float32 with
+ * the given strides. */
+ssimx_status ssimx_luma_grad_to_rgb(const float* grad_y, int width, int height, int batch, float* grad_rgb,
+                                    int64_t pitch, int64_t channel_stride, int64_t batch_stride, void* stream);
+
 /* ---------------- ragged batches ------------------------------------------
  * A plan covers n independent pairs, each with its own size and params.  It
  * owns a device descriptor table, a partial-sum buffer and an instantiated

@@ -73,6 +73,10 @@ _SIGS = {
                                 c_void_p, c_size_t, c_void_p]),
     "ssimx_box_sums": (c_int, [c_int, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ssimx_integral_images": (c_int, [_I, _I, c_int, c_void_p, c_void_p]),
+    "ssimx_rgb_to_luma": (c_int, [c_void_p, c_int, c_int, c_int, c_int64, c_int64, c_int64, c_int, c_void_p,
+                                  c_void_p]),
+    "ssimx_luma_grad_to_rgb": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int64, c_int64, c_int64,
+                                       c_void_p]),
     "ssimx_plan_create": (c_int, [POINTER(Pair), c_int, c_void_p, POINTER(c_void_p)]),
     "ssimx_plan_run": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ssimx_plan_run_unbatched": (c_int, [c_void_p, c_void_p, c_void_p]),

@@ -1,0 +1,78 @@
+"""torch.autograd wrappers: SSIM and MS-SSIM as differentiable functions of the
+distorted plane (the reference plane gets no gradient), and the BT.601 luma
+front end.  Forward and backward both run in libssimx; the backward
+recomputes the window moments instead of saving them."""
+from __future__ import annotations
+
+import torch
+
+from . import ops
+
+
+class SSIMFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, y, cfg):
+        ctx.save_for_backward(x, y)
+        ctx.cfg = cfg
+        return ops.ssim(x, y, cfg)
+
+    @staticmethod
+    def backward(ctx, g):
+        x, y = ctx.saved_tensors
+        gy = ops.ssim_backward(x, y, g, ctx.cfg) if ctx.needs_input_grad[1] else None
+        return None, (gy.to(y.dtype) if gy is not None else None), None
+
+
+class MSSSIMFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, y, cfg, weights, n_scales, renorm, cs_clamp):
+        ctx.save_for_backward(x, y)
+        ctx.args = (cfg, tuple(weights), n_scales, renorm, cs_clamp)
+        return ops.ms_ssim(x, y, cfg, weights=weights, n_scales=n_scales, renorm=renorm, cs_clamp=cs_clamp)
+
+    @staticmethod
+    def backward(ctx, g):
+        x, y = ctx.saved_tensors
+        cfg, weights, n_scales, renorm, cs_clamp = ctx.args
+        gy = None
+        if ctx.needs_input_grad[1]:
+            gy = ops.ms_ssim_backward(x, y, g, cfg, weights=weights, n_scales=n_scales, renorm=renorm,
+                                      cs_clamp=cs_clamp).to(y.dtype)
+        return None, gy, None, None, None, None, None
+
+
+class LumaFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rgb):
+        ctx.in_dtype = rgb.dtype
+        return ops.rgb_to_luma(rgb)
+
+    @staticmethod
+    def backward(ctx, gy):
+        return ops.luma_grad_to_rgb(gy).to(ctx.in_dtype)
+
+
+def ssim(x, y, cfg: ops.SSIMConfig | None = None, **kw):
+    """Differentiable mean SSIM per frame, float32 [B]."""
+    return SSIMFunction.apply(x, y, ops._cfg(cfg, kw))
+
+
+def ms_ssim(x, y, cfg: ops.SSIMConfig | None = None, weights=ops.MS_WEIGHTS, n_scales: int = 5,
+            renorm: bool = False, cs_clamp: bool = False, **kw):
+    """Differentiable MS-SSIM per frame, float32 [B]."""
+    return MSSSIMFunction.apply(x, y, ops._cfg(cfg, kw), tuple(weights), n_scales, renorm, cs_clamp)
+
+
+def luma(rgb):
+    """Differentiable BT.601 luma of (B, 3, H, W) planes."""
+    return LumaFunction.apply(rgb)
+
+
+def ms_ssim_loss_rgb(ref_rgb, dis_rgb, cfg: ops.SSIMConfig | None = None, n_scales: int = 3, renorm: bool = True,
+                     **kw):
+    """1 - MS-SSIM on BT.601 luma, averaged over the batch (the training loss
+    of the differentiable workload); gradients flow to dis_rgb."""
+    cfg = ops._cfg(cfg, kw)
+    yr = ops.rgb_to_luma(ref_rgb)
+    yd = luma(dis_rgb)
+    return (1.0 - ms_ssim(yr, yd, cfg, n_scales=n_scales, renorm=renorm)).mean()

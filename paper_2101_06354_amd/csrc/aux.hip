@@ -1,4 +1,5 @@
 // Pooling finalisation, 2x2 pyramid and the MS-SSIM product.
+#include "host_common.hpp"
 #include "ssimx_internal.hpp"
 
 namespace ssimx {
@@ -121,4 +122,68 @@ int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w
   return (int)hipGetLastError();
 }
 
+// BT.601 luma of planar RGB and its adjoint.
+constexpr float kBt601R = 0.299f, kBt601G = 0.587f, kBt601B = 0.114f;
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void rgb_to_luma_kernel(const T* rgb, int W, int H, int64_t pitch, int64_t cstride,
+                                                            int64_t bstride, float* y) {
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= W * H) return;
+  const int b = blockIdx.y;
+  const int r = idx / W, c = idx - r * W;
+  const T* p = rgb + (int64_t)b * bstride + (int64_t)r * pitch + c;
+  const float R = to_f32<T>(p[0]), G = to_f32<T>(p[cstride]), B = to_f32<T>(p[2 * cstride]);
+  y[(int64_t)b * W * H + idx] = fmaf(kBt601R, R, fmaf(kBt601G, G, kBt601B * B));
+}
+
+__global__ __launch_bounds__(BLOCK) void luma_grad_to_rgb_kernel(const float* gy, int W, int H, float* g,
+                                                                 int64_t pitch, int64_t cstride, int64_t bstride) {
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= W * H) return;
+  const int b = blockIdx.y;
+  const int r = idx / W, c = idx - r * W;
+  const float v = gy[(int64_t)b * W * H + idx];
+  float* p = g + (int64_t)b * bstride + (int64_t)r * pitch + c;
+  p[0] = kBt601R * v;
+  p[cstride] = kBt601G * v;
+  p[2 * cstride] = kBt601B * v;
+}
+
 }  // namespace ssimx
+
+using namespace ssimx;
+
+extern "C" {
+
+ssimx_status ssimx_rgb_to_luma(const void* rgb, int dtype, int width, int height, int64_t pitch,
+                               int64_t channel_stride, int64_t batch_stride, int batch, float* y_out,
+                               void* stream) {
+  if (!rgb || !y_out || width < 1 || height < 1 || batch < 1 || pitch < width) return SSIMX_EINVAL;
+  if (channel_stride < pitch * (int64_t)height || (batch > 1 && batch_stride < 3 * channel_stride))
+    return SSIMX_EINVAL;
+  dim3 grid((width * height + BLOCK - 1) / BLOCK, batch);
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == SSIMX_F32)
+    hipLaunchKernelGGL(rgb_to_luma_kernel<float>, grid, dim3(BLOCK), 0, st, (const float*)rgb, width, height, pitch,
+                       channel_stride, batch_stride, y_out);
+  else if (dtype == SSIMX_BF16)
+    hipLaunchKernelGGL(rgb_to_luma_kernel<bf16_t>, grid, dim3(BLOCK), 0, st, (const bf16_t*)rgb, width, height,
+                       pitch, channel_stride, batch_stride, y_out);
+  else
+    return SSIMX_EDTYPE;
+  return hip_status((int)hipGetLastError());
+}
+
+ssimx_status ssimx_luma_grad_to_rgb(const float* grad_y, int width, int height, int batch, float* grad_rgb,
+                                    int64_t pitch, int64_t channel_stride, int64_t batch_stride, void* stream) {
+  if (!grad_y || !grad_rgb || width < 1 || height < 1 || batch < 1 || pitch < width) return SSIMX_EINVAL;
+  if (channel_stride < pitch * (int64_t)height || (batch > 1 && batch_stride < 3 * channel_stride))
+    return SSIMX_EINVAL;
+  dim3 grid((width * height + BLOCK - 1) / BLOCK, batch);
+  hipLaunchKernelGGL(luma_grad_to_rgb_kernel, grid, dim3(BLOCK), 0, (hipStream_t)stream, grad_y, width, height,
+                     grad_rgb, pitch, channel_stride, batch_stride);
+  return hip_status((int)hipGetLastError());
+}
+
+}  // extern "C"

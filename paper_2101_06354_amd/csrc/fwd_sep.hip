@@ -17,95 +17,34 @@
 // Every rounding error is then relative to local deviations, not to |u|, so
 // flat regions far from any global shift stay exact.  For integer planes the
 // row-pass differences and squares are exact integers in float32.
+#include "sep_tile.hpp"
 #include "ssim_epilogue.hpp"
 #include "ssimx_internal.hpp"
 
 namespace ssimx {
 
 size_t sep_lds_bytes(const Geom& g) {
-  return sizeof(float) * (2 * (size_t)g.IH * g.IW + 4 * (size_t)g.IH * g.TW + BLOCK / 64);
+  return sizeof(float) * (sep_tile_lds_floats(g.IH, g.IW, g.TW) + BLOCK / 64);
 }
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void sep_fwd_kernel(SepArgs a) {
   extern __shared__ float lds[];
-  const int IW = a.g.IW, IH = a.g.IH, TW = a.g.TW, TH = a.g.TH, k = a.g.k, s = a.g.s;
   const int frame = blockIdx.y;
   const int tile = blockIdx.x;
   const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
-  const int ox0 = txi * TW, oy0 = tyi * TH;
-  const int px0 = ox0 * s, py0 = oy0 * s;
+  const int ox0 = txi * a.g.TW, oy0 = tyi * a.g.TH;
+  float* red = lds + sep_tile_lds_floats(a.g.IH, a.g.IW, a.g.TW);
 
-  float* U = lds;
-  float* V = U + IH * IW;
-  float* HU = V + IH * IW;
-  float* HV = HU + IH * TW;
-  float* VU = HV + IH * TW;
-  float* VV = VU + IH * TW;
-  float* red = VV + IH * TW;
+  sep_tile_rows<T>(a.g, a.taps, a.x, a.y, frame, ox0, oy0, lds);
 
-  const T* X = (const T*)a.x.data + (int64_t)frame * a.x.bstride;
-  const T* Y = (const T*)a.y.data + (int64_t)frame * a.y.bstride;
-
-  // 1. footprint of the tile -> u, v in LDS (zeros past the padded extent,
-  //    which no valid output reads)
-  for (int idx = threadIdx.x; idx < IH * IW; idx += BLOCK) {
-    const int r = idx / IW, c = idx - r * IW;
-    int sy, sx;
-    float xv = 0.f, yv = 0.f;
-    if (padded_source(py0 + r, px0 + c, a.g.H, a.g.W, a.g.pad, a.g.before, a.g.Hp, a.g.Wp, sy, sx)) {
-      xv = to_f32<T>(X[(int64_t)sy * a.x.pitch + sx]);
-      yv = to_f32<T>(Y[(int64_t)sy * a.y.pitch + sx]);
-    }
-    U[idx] = xv + yv;
-    V[idx] = xv - yv;
-  }
-  __syncthreads();
-
-  // 2. row pass at the tile's output columns, for every footprint row
-  const int kc = k >> 1;
-  for (int idx = threadIdx.x; idx < IH * TW; idx += BLOCK) {
-    const int r = idx / TW, j = idx - r * TW;
-    const float* ur = U + r * IW + j * s;
-    const float* vr = V + r * IW + j * s;
-    const float tu = ur[kc], tv = vr[kc];
-    float au = 0.f, av = 0.f, qu = 0.f, qv = 0.f;
-    for (int t = 0; t < k; ++t) {
-      const float w = a.taps[t];
-      const float du = ur[t] - tu, dv = vr[t] - tv;
-      const float wdu = w * du, wdv = w * dv;
-      au += wdu;
-      av += wdv;
-      qu = fmaf(wdu, du, qu);
-      qv = fmaf(wdv, dv, qv);
-    }
-    HU[idx] = tu + au;
-    HV[idx] = tv + av;
-    VU[idx] = qu - au * au;
-    VV[idx] = qv - av * av;
-  }
-  __syncthreads();
-
-  // 3. column pass, SSIM terms, map store and pooling
   float acc = 0.f;
-  for (int idx = threadIdx.x; idx < TH * TW; idx += BLOCK) {
-    const int i = idx / TW, j = idx - i * TW;
+  for (int idx = threadIdx.x; idx < a.g.TH * a.g.TW; idx += BLOCK) {
+    const int i = idx / a.g.TW, j = idx - i * a.g.TW;
     const int oi = oy0 + i, oj = ox0 + j;
     if (oi >= a.g.Ho || oj >= a.g.Wo) continue;
-    const int r0 = i * s;
-    const float Tu = HU[(r0 + kc) * TW + j], Tv = HV[(r0 + kc) * TW + j];
-    float mu = 0.f, mv = 0.f, su = 0.f, sv = 0.f;
-    for (int m = 0; m < k; ++m) {
-      const float w = a.taps[m];
-      const int o = (r0 + m) * TW + j;
-      const float du = HU[o] - Tu, dv = HV[o] - Tv;
-      const float wdu = w * du, wdv = w * dv;
-      mu += wdu;
-      mv += wdv;
-      su = fmaf(wdu, du, fmaf(w, VU[o], su));
-      sv = fmaf(wdv, dv, fmaf(w, VV[o], sv));
-    }
-    const SsimTerms t = ssim_terms_uv(Tu + mu, Tv + mv, su - mu * mu, sv - mv * mv, a.C1, a.C2);
+    const TileStats st = sep_tile_column(a.g, a.taps, lds, i, j);
+    const SsimTerms t = ssim_terms_uv(st.mean_u, st.mean_v, st.var_u, st.var_v, a.C1, a.C2);
     const float val = ssim_value(t, a.mode);
     if (a.map) a.map[(int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + oj] = val;
     acc += val;

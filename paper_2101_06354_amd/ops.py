@@ -227,6 +227,34 @@ def integral_images(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def rgb_to_luma(rgb: torch.Tensor) -> torch.Tensor:
+    """BT.601 luma of planar RGB (B, 3, H, W) or (3, H, W), float32/bfloat16
+    -> float32 (B, H, W)."""
+    t = rgb.unsqueeze(0) if rgb.dim() == 3 else rgb
+    if t.dim() != 4 or t.shape[1] != 3 or t.stride(3) != 1 or not t.is_cuda:
+        raise ValueError("rgb must be a device tensor (B, 3, H, W) with contiguous rows")
+    dt = {torch.float32: L.F32, torch.bfloat16: L.BF16}.get(t.dtype)
+    if dt is None:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    b, _, h, w = t.shape
+    out = torch.empty((b, h, w), dtype=torch.float32, device=t.device)
+    st = L.lib.ssimx_rgb_to_luma(t.data_ptr(), dt, w, h, t.stride(2), t.stride(1), t.stride(0), b, out.data_ptr(),
+                                 _stream(t))
+    L.check(st, "ssimx_rgb_to_luma")
+    return out
+
+
+def luma_grad_to_rgb(gy: torch.Tensor) -> torch.Tensor:
+    """Adjoint of rgb_to_luma: float32 (B, H, W) -> float32 (B, 3, H, W)."""
+    g = _as3(gy.to(torch.float32)).contiguous()
+    b, h, w = g.shape
+    out = torch.empty((b, 3, h, w), dtype=torch.float32, device=g.device)
+    st = L.lib.ssimx_luma_grad_to_rgb(g.data_ptr(), w, h, b, out.data_ptr(), out.stride(2), out.stride(1),
+                                      out.stride(0), _stream(g))
+    L.check(st, "ssimx_luma_grad_to_rgb")
+    return out
+
+
 def autotune(cfg: SSIMConfig, dtype, h: int, w: int, batch: int = 1, device="cuda") -> int:
     best = ctypes.c_int(-1)
     dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)

@@ -1,0 +1,167 @@
+"""GPU parity of the adjoint kernels (ssim_map_backward, ssim_pooled_backward,
+msssim_backward, luma front end) against the FP64 oracle gradient, plus the
+differentiable-loss workload (batch 16 of 3x512x512 RGB) checked against the
+FP64 gradient and FP64 central differences."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from _helpers import bf16_round, device, oparams, to_dev
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-4      # ||g - g*|| / ||g*||
+PIX_REL = 1e-3     # max |g - g*| / max |g*|
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2101_06354_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def _cmp(g, gref, what=""):
+    g = np.asarray(g, dtype=np.float64)
+    rel = np.linalg.norm(g - gref) / max(np.linalg.norm(gref), 1e-300)
+    pix = np.abs(g - gref).max() / max(np.abs(gref).max(), 1e-300)
+    assert rel <= REL_L2 and pix <= PIX_REL, f"{what}: rel L2 {rel:.3g}, max pix {pix:.3g}"
+
+
+def test_pooled_backward_config0(P, dev):
+    x, y = synth.config0()
+    cfg = P.SSIMConfig()
+    g = P.ssim_backward(to_dev(x, dev), to_dev(y, dev), torch.tensor([1.0], device=dev), cfg)
+    _cmp(g.cpu().numpy(), O.ssim_pooled_backward(x, y, 1.0, oparams(cfg)), "config0")
+
+
+@pytest.mark.parametrize("window,k,stride,padding", [("gaussian", 11, 1, "valid"), ("gaussian", 11, 4, "valid"),
+                                                     ("gaussian", 7, 2, "zero"), ("gaussian", 11, 1, "reflect"),
+                                                     ("box", 8, 1, "valid"), ("box", 8, 4, "reflect"),
+                                                     ("gaussian", 5, 3, "reflect")])
+def test_map_backward_random_upstream(P, dev, window, k, stride, padding):
+    rng = np.random.default_rng(k * 10 + stride)
+    x = synth.smooth_field(rng, 67, 93, 16, 235).round().astype(np.uint8)
+    y = np.clip(x + rng.normal(0, 10, x.shape).round(), 0, 255).astype(np.uint8)
+    cfg = P.SSIMConfig(window=window, k=k, sigma=1.5 if k == 11 else 1.0, stride=stride, padding=padding)
+    ho, wo = P.map_shape(cfg, 67, 93)
+    up = rng.normal(size=(ho, wo))
+    g = P.ssim_map_backward(to_dev(x, dev), to_dev(y, dev), to_dev(up.astype(np.float32), dev), cfg)
+    gref = O.ssim_map_backward(x, y, up.astype(np.float32).astype(np.float64), oparams(cfg))
+    _cmp(g.cpu().numpy(), gref, f"{window}{k}/s{stride}/{padding}")
+
+
+def test_pooled_backward_batch_and_scaling(P, dev):
+    x, y = synth.config1(frames=3, h=120, w=160)
+    cfg = P.SSIMConfig()
+    gs = np.array([1.0, -2.5, 0.25], dtype=np.float32)
+    g = P.ssim_backward(to_dev(x, dev), to_dev(y, dev), to_dev(gs, dev), cfg).cpu().numpy()
+    for f in range(3):
+        _cmp(g[f], O.ssim_pooled_backward(x[f], y[f], float(gs[f]), oparams(cfg)), f"frame {f}")
+
+
+def test_gradient_vanishes_at_identity(P, dev):
+    x, _ = synth.config0()
+    cfg = P.SSIMConfig()
+    g = P.ssim_backward(to_dev(x, dev), to_dev(x, dev), torch.tensor([1.0], device=dev), cfg)
+    assert float(g.abs().max()) == 0.0
+    xf = synth.config4(batch=1, h=64, w=64)[0][0, 0]
+    g = P.ms_ssim_backward(to_dev(xf, dev), to_dev(xf, dev), torch.tensor([1.0], device=dev), P.SSIMConfig(L=1.0),
+                           n_scales=3, renorm=True)
+    assert float(g.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("n_scales,padding", [(3, "valid"), (5, "valid"), (2, "reflect")])
+def test_msssim_backward_u16(P, dev, n_scales, padding):
+    x, y = synth.config2(frames=2, h=200, w=260)
+    cfg = P.SSIMConfig(L=1023.0, padding=padding)
+    g = P.ms_ssim_backward(to_dev(x, dev), to_dev(y, dev), torch.tensor([1.0, 0.5], device=dev), cfg,
+                           n_scales=n_scales, renorm=n_scales < 5).cpu().numpy()
+    for f, gs in enumerate((1.0, 0.5)):
+        gref = O.msssim_backward(x[f], y[f], gs, oparams(cfg), n_scales=n_scales, renorm=n_scales < 5)
+        _cmp(g[f], gref, f"frame {f}")
+
+
+def test_luma_kernels(P, dev):
+    r, _ = synth.config4(batch=2, h=40, w=56)
+    yv = P.rgb_to_luma(to_dev(r, dev)).cpu().numpy()
+    for b in range(2):
+        np.testing.assert_allclose(yv[b], O.rgb_to_y_bt601(r[b]), rtol=0, atol=2e-7)
+    gy = np.random.default_rng(1).normal(size=(2, 40, 56)).astype(np.float32)
+    grgb = P.luma_grad_to_rgb(to_dev(gy, dev)).cpu().numpy()
+    for b in range(2):
+        np.testing.assert_allclose(grgb[b], O.y_grad_to_rgb_bt601(gy[b]), rtol=1e-7, atol=0)
+
+
+def test_autograd_matches_direct_calls(P, dev):
+    x, y = synth.config0()
+    xt, yt = to_dev(x.astype(np.float32), dev), to_dev(y.astype(np.float32), dev).requires_grad_(True)
+    cfg = P.SSIMConfig()
+    s = P.autograd.ssim(xt, yt, cfg)
+    (2.0 * s.sum()).backward()
+    g = P.ssim_backward(xt, yt.detach(), torch.tensor([2.0], device=dev), cfg)
+    assert torch.equal(yt.grad, g)
+
+
+def _loss_grad_oracle(r, d, cfg, B):
+    """FP64 gradient of mean_b(1 - MS(Y(r_b), Y(d_b))) with respect to d."""
+    out = np.empty(d.shape)
+    for b in range(len(d)):
+        yr, yd = O.rgb_to_y_bt601(r[b]), O.rgb_to_y_bt601(d[b])
+        gy = O.msssim_backward(yr, yd, -1.0 / B, cfg, n_scales=3, renorm=True)
+        out[b] = O.y_grad_to_rgb_bt601(gy)
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_differentiable_loss_workload_full_size(P, dev, storage):
+    """Batch 16 of 3x512x512 RGB, loss = mean(1 - MS-SSIM) on BT.601 luma,
+    3 scales with renormalised weights, C1=(0.01)^2, C2=(0.03)^2."""
+    B = 16
+    r, d = synth.config4(batch=B)
+    if storage == "bf16":
+        rt = to_dev(r, dev).bfloat16()
+        dt = to_dev(d, dev).bfloat16().requires_grad_(True)
+        r64, d64 = bf16_round(r), bf16_round(d)
+    else:
+        rt, dt = to_dev(r, dev), to_dev(d, dev).requires_grad_(True)
+        r64, d64 = r.astype(np.float64), d.astype(np.float64)
+    cfg = P.SSIMConfig(L=1.0)
+    loss = P.autograd.ms_ssim_loss_rgb(rt, dt, cfg, n_scales=3, renorm=True)
+    loss.backward()
+    g = dt.grad.float().cpu().numpy()
+    ocfg = oparams(cfg)
+    # loss value
+    ms = [O.msssim(O.rgb_to_y_bt601(r64[b]), O.rgb_to_y_bt601(d64[b]), ocfg, n_scales=3, renorm=True)["score"]
+          for b in range(B)]
+    assert abs(float(loss.detach()) - np.mean([1 - m for m in ms])) <= 1e-6
+    # FP64 analytic gradient on 4 frames (bf16 storage: the gradient is returned in bf16)
+    gref = _loss_grad_oracle(r64[:4], d64[:4], ocfg, B)
+    if storage == "f32":
+        _cmp(g[:4], gref, "loss grad")
+    else:
+        rel = np.linalg.norm(g[:4] - gref) / np.linalg.norm(gref)
+        assert rel <= 1e-2, rel  # bf16 rounding of the returned gradient
+    # FP64 central differences (h = 1e-3) of the oracle loss at 64 random pixels
+    rng = np.random.default_rng(64)
+    fd_frames = 2
+    for _ in range(64 if storage == "f32" else 16):
+        b = int(rng.integers(0, fd_frames))
+        c, i, j = int(rng.integers(0, 3)), int(rng.integers(0, 512)), int(rng.integers(0, 512))
+
+        def loss_b(dd):
+            return (1 - O.msssim(O.rgb_to_y_bt601(r64[b]), O.rgb_to_y_bt601(dd), ocfg, n_scales=3,
+                                 renorm=True)["score"]) / B
+        dp, dm = d64[b].copy(), d64[b].copy()
+        dp[c, i, j] += 1e-3
+        dm[c, i, j] -= 1e-3
+        fd = (loss_b(dp) - loss_b(dm)) / 2e-3
+        scale = np.abs(gref[b]).max()
+        tol = 1e-3 * scale if storage == "f32" else 1e-2 * scale
+        assert abs(g[b, c, i, j] - fd) <= tol, (b, c, i, j, g[b, c, i, j], fd)
