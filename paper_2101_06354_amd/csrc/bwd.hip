@@ -20,6 +20,7 @@
 
 #include <algorithm>
 
+#include "fast_tile.hpp"
 #include "host_common.hpp"
 #include "sep_tile.hpp"
 #include "ssim_epilogue.hpp"
@@ -279,35 +280,69 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
   pf.algo = SSIMX_ALGO_SEPARABLE;
   // statistics through the float separable path (box windows use taps 1/k)
   Geom g = make_geom_path(&pf, SSIMX_F32, lv.W, lv.H, 0);
-  CoefArgs ca{};
-  ca.x = lv.x;
-  ca.y = lv.y;
-  ca.g = g;
-  ca.C1 = (float)p->C1;
-  ca.C2 = (float)p->C2;
-  ca.mode = mode;
-  ca.grad_map = grad_map;
-  ca.gm_pitch = gm_pitch;
-  ca.gm_bstride = gm_bstride;
-  ca.gscale = gscale;
-  ca.gscale_stride = gscale_stride;
-  ca.gmul = gmul;
-  ca.tu = shift_guess(p);
-  ca.tv = 0.f;
-  ca.coef = coef;
-  ca.batch = batch;
-  gaussian_taps_f32(p->window, p->k, p->sigma, ca.taps);
-  const size_t lds1 = sizeof(float) * sep_tile_lds_floats(g.IH, g.IW, g.TW);
-  dim3 grid1(g.tiles_x * g.tiles_y, batch);
-  switch (lv.dtype) {
-    case SSIMX_U8: hipLaunchKernelGGL(bwd_coef_kernel<uint8_t>, grid1, dim3(BLOCK), lds1, st, ca); break;
-    case SSIMX_U16: hipLaunchKernelGGL(bwd_coef_kernel<uint16_t>, grid1, dim3(BLOCK), lds1, st, ca); break;
-    case SSIMX_F32: hipLaunchKernelGGL(bwd_coef_kernel<float>, grid1, dim3(BLOCK), lds1, st, ca); break;
-    case SSIMX_BF16: hipLaunchKernelGGL(bwd_coef_kernel<bf16_t>, grid1, dim3(BLOCK), lds1, st, ca); break;
-    default: return SSIMX_EDTYPE;
+  const bool valid = p->padding == SSIMX_PAD_VALID;
+  const bool fast = use_fast(&pf, SSIMX_F32);
+  const float tu = shift_guess(p), tv = 0.f;
+  int err = 0;
+  FastArgs fa{};
+  if (fast) {
+    fill_fast_common(fa, &pf, lv.dtype, lv.x, lv.y, fast_geom(&pf, lv.W, lv.H, 0));
+    fa.mode = mode;
+    fa.grad_map = grad_map;
+    fa.gm_pitch = gm_pitch;
+    fa.gm_bstride = gm_bstride;
+    fa.gscale = gscale;
+    fa.gscale_stride = gscale_stride;
+    fa.gmul = gmul;
+    fa.tu = tu;
+    fa.tv = tv;
+    fa.coef = coef;
+    fa.batch = batch;
+    err = launch_fast_stats(lv.dtype, 1, fa, batch, st);
+    if (err) return hip_status(err);
+  } else {
+    CoefArgs ca{};
+    ca.x = lv.x;
+    ca.y = lv.y;
+    ca.g = g;
+    ca.C1 = (float)p->C1;
+    ca.C2 = (float)p->C2;
+    ca.mode = mode;
+    ca.grad_map = grad_map;
+    ca.gm_pitch = gm_pitch;
+    ca.gm_bstride = gm_bstride;
+    ca.gscale = gscale;
+    ca.gscale_stride = gscale_stride;
+    ca.gmul = gmul;
+    ca.tu = tu;
+    ca.tv = tv;
+    ca.coef = coef;
+    ca.batch = batch;
+    gaussian_taps_f32(p->window, p->k, p->sigma, ca.taps);
+    const size_t lds1 = sizeof(float) * sep_tile_lds_floats(g.IH, g.IW, g.TW);
+    dim3 grid1(g.tiles_x * g.tiles_y, batch);
+    switch (lv.dtype) {
+      case SSIMX_U8: hipLaunchKernelGGL(bwd_coef_kernel<uint8_t>, grid1, dim3(BLOCK), lds1, st, ca); break;
+      case SSIMX_U16: hipLaunchKernelGGL(bwd_coef_kernel<uint16_t>, grid1, dim3(BLOCK), lds1, st, ca); break;
+      case SSIMX_F32: hipLaunchKernelGGL(bwd_coef_kernel<float>, grid1, dim3(BLOCK), lds1, st, ca); break;
+      case SSIMX_BF16: hipLaunchKernelGGL(bwd_coef_kernel<bf16_t>, grid1, dim3(BLOCK), lds1, st, ca); break;
+      default: return SSIMX_EDTYPE;
+    }
+    err = (int)hipGetLastError();
+    if (err) return hip_status(err);
   }
-  int err = (int)hipGetLastError();
-  if (err) return hip_status(err);
+  if (fast && valid) {
+    fa.QH = 128;
+    fa.qtiles_x = (lv.W + 63) / 64;
+    fa.qtiles_y = (lv.H + fa.QH - 1) / fa.QH;
+    fa.out = out;
+    fa.out_pitch = out_pitch;
+    fa.out_bstride = out_bstride;
+    fa.coarse = coarse;
+    fa.Wc = Wc;
+    fa.Hc = Hc;
+    return hip_status(launch_fast_adjoint(lv.dtype, fa, batch, st));
+  }
 
   ScatArgs sa{};
   sa.x = lv.x;
@@ -315,12 +350,11 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
   sa.g = g;
   sa.coef = coef;
   sa.batch = batch;
-  sa.tu = ca.tu;
-  sa.tv = ca.tv;
+  sa.tu = tu;
+  sa.tv = tv;
   int qtx, qty;
   scat_geom_fit(g, sa.QW, sa.QH, sa.MR, sa.MC, qtx, qty);
   sa.qtiles_x = qtx;
-  const bool valid = p->padding == SSIMX_PAD_VALID;
   if (valid) {
     sa.out = out;
     sa.out_pitch = out_pitch;
@@ -333,7 +367,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     sa.out_pitch = g.Wp;
     sa.out_bstride = (int64_t)g.Wp * g.Hp;
   }
-  memcpy(sa.taps, ca.taps, sizeof(sa.taps));
+  gaussian_taps_f32(p->window, p->k, p->sigma, sa.taps);
   const size_t lds2 = sizeof(float) * (4 * (size_t)sa.MR * sa.MC + 4 * (size_t)sa.MR * sa.QW);
   dim3 grid2(qtx * qty, batch);
   switch (lv.dtype) {

@@ -1,0 +1,476 @@
+// Stride-1 tiled kernels with a compile-time window size K.
+//
+// A block owns a 64-column tile of the map and marches down it in chunks of
+// 32 output rows.  Per chunk the footprint rows are staged in LDS, the row
+// pass writes four row-statistics maps (row mean and row variance of u and
+// v) into an LDS band of 32 + K - 1 rows, and the column pass consumes it.
+// The K - 1 band rows shared with the next chunk are moved to the top of the
+// band instead of being recomputed, so the row pass costs (32 n + K - 1) /
+// (32 n) per output row for an n-chunk tile instead of (32 + K - 1) / 32.
+//
+// Register blocking: a row-pass item computes 4 adjacent outputs of one row
+// and a column-pass item 4 adjacent outputs of one column.  The 4 outputs of
+// an item share the centring value (the input at window offset K/2 + 1 of
+// the first output, i.e. offsets K/2+1 .. K/2-2 of the four windows), so the
+// centred differences and their squares are formed once per input and then
+// consumed by 4 FMAs per tap and output.  Sharing keeps every rounding error
+// bounded by the local deviations: the shared value lies inside each window
+// with weight g_t, and sum g (z - t)^2 <= V (1 + 1/g_t).
+//
+// Kernels:
+//   fast_stats_kernel<K, T, EPI>  EPI = 0: SSIM / cs map + pooled partials
+//                                 EPI = 1: the four adjoint coefficient maps
+//   fast_adjoint_kernel<K, T>     transposed window over the coefficient
+//                                 maps and the per-pixel combine (valid
+//                                 borders), optionally adding the 2x2
+//                                 transpose of a coarser-scale gradient.
+#include "fast_tile.hpp"
+#include "ssim_epilogue.hpp"
+#include "ssimx_internal.hpp"
+
+namespace ssimx {
+
+namespace {
+
+constexpr int kTW = 64;   // map columns per tile
+constexpr int kCH = 32;   // output rows per chunk
+constexpr int kNT = 256;  // threads per block
+
+template <int K>
+struct Shape {
+  static constexpr int HALO = K - 1;
+  static constexpr int NREAD = (K + 3 + 3) / 4;        // float4 reads per row-pass item
+  static constexpr int IWP = kTW - 4 + 4 * NREAD;      // LDS row length of the footprint
+  static constexpr int NQ = IWP / 4;                   // float4 quads per footprint row
+  static constexpr int BAND = kCH + HALO;              // rows of the row-statistics band
+  static constexpr int SHIFT = K / 2 + 1;              // centring offset of an item
+  static_assert(IWP >= kTW + K - 1, "footprint row too short");
+  static_assert(kCH >= HALO, "band copy needs CH >= K - 1");
+  static_assert(SHIFT - 3 >= 0 && SHIFT < K, "shared centring value must lie in all 4 windows");
+};
+
+// Four consecutive elements of the padded plane (zeros outside), as floats.
+template <typename T>
+__device__ __forceinline__ void load4(const T* P, int64_t pitch, const Geom& g, int vec_ok, int py, int px,
+                                      float* o) {
+  if (vec_ok && g.pad == SSIMX_PAD_VALID && py < g.H && px + 3 < g.W) {
+    const T* s = P + (int64_t)py * pitch + px;
+    if constexpr (sizeof(T) == 1) {
+      const uint32_t w = *(const uint32_t*)s;
+      o[0] = (float)(w & 0xffu);
+      o[1] = (float)((w >> 8) & 0xffu);
+      o[2] = (float)((w >> 16) & 0xffu);
+      o[3] = (float)(w >> 24);
+    } else if constexpr (sizeof(T) == 2) {
+      const uint2 w = *(const uint2*)s;
+      const T* e = (const T*)&w;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = to_f32<T>(e[i]);
+    } else {
+      const float4 w = *(const float4*)s;
+      o[0] = w.x;
+      o[1] = w.y;
+      o[2] = w.z;
+      o[3] = w.w;
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int sy, sx;
+    o[i] = padded_source(py, px + i, g.H, g.W, g.pad, g.before, g.Hp, g.Wp, sy, sx)
+               ? to_f32<T>(P[(int64_t)sy * pitch + sx])
+               : 0.f;
+  }
+}
+
+// Stage `nrows` footprint rows starting at padded row py0 into U, V (u = x+y,
+// v = x-y).
+template <int K, typename T>
+__device__ __forceinline__ void stage_rows(const FastArgs& a, const T* X, const T* Y, int py0, int px0, int nrows,
+                                           float* U, float* V) {
+  using S = Shape<K>;
+  for (int it = threadIdx.x; it < nrows * S::NQ; it += kNT) {
+    const int r = it / S::NQ, q = it - r * S::NQ;
+    float xv[4], yv[4];
+    load4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, xv);
+    load4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, yv);
+    *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
+    *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
+  }
+}
+
+// Row pass over `nrows` staged rows into band rows [band0, band0 + nrows).
+template <int K>
+__device__ __forceinline__ void row_pass(const float* taps, const float* U, const float* V, int nrows, float* HM,
+                                         int band0) {
+  using S = Shape<K>;
+  constexpr int NG = kTW / 4;
+  constexpr int PL = S::BAND * kTW;  // one statistics map in the band
+  for (int it = threadIdx.x; it < nrows * NG; it += kNT) {
+    const int r = it / NG, gq = it - r * NG;
+    float u[4 * S::NREAD], v[4 * S::NREAD];
+#pragma unroll
+    for (int n = 0; n < S::NREAD; ++n) {
+      *(float4*)&u[4 * n] = *(const float4*)&U[r * S::IWP + 4 * gq + 4 * n];
+      *(float4*)&v[4 * n] = *(const float4*)&V[r * S::IWP + 4 * gq + 4 * n];
+    }
+    const float tu = u[S::SHIFT], tv = v[S::SHIFT];
+    float du[K + 3], dv[K + 3], pu[K + 3], pv[K + 3];
+#pragma unroll
+    for (int n = 0; n < K + 3; ++n) {
+      du[n] = u[n] - tu;
+      dv[n] = v[n] - tv;
+      pu[n] = du[n] * du[n];
+      pv[n] = dv[n] * dv[n];
+    }
+    float hu[4], hv[4], vu[4], vv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float au = 0.f, av = 0.f, qu = 0.f, qv = 0.f;
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const float w = taps[t];
+        au = fmaf(w, du[j + t], au);
+        av = fmaf(w, dv[j + t], av);
+        qu = fmaf(w, pu[j + t], qu);
+        qv = fmaf(w, pv[j + t], qv);
+      }
+      hu[j] = tu + au;
+      hv[j] = tv + av;
+      vu[j] = fmaf(-au, au, qu);
+      vv[j] = fmaf(-av, av, qv);
+    }
+    const int o = (band0 + r) * kTW + 4 * gq;
+    *(float4*)&HM[o] = make_float4(hu[0], hu[1], hu[2], hu[3]);
+    *(float4*)&HM[PL + o] = make_float4(hv[0], hv[1], hv[2], hv[3]);
+    *(float4*)&HM[2 * PL + o] = make_float4(vu[0], vu[1], vu[2], vu[3]);
+    *(float4*)&HM[3 * PL + o] = make_float4(vv[0], vv[1], vv[2], vv[3]);
+  }
+}
+
+// Move band rows [CH, CH + HALO) to [0, HALO).
+template <int K>
+__device__ __forceinline__ void band_shift(float* HM) {
+  using S = Shape<K>;
+  constexpr int PL = S::BAND * kTW;
+  constexpr int NV = S::HALO * kTW / 4;  // float4 per map
+  for (int it = threadIdx.x; it < 4 * NV; it += kNT) {
+    const int m = it / NV, e = it - m * NV;
+    *(float4*)&HM[m * PL + 4 * e] = *(const float4*)&HM[m * PL + kCH * kTW + 4 * e];
+  }
+}
+
+}  // namespace
+
+template <int K, typename T, int EPI>
+__global__ __launch_bounds__(kNT, 2) void fast_stats_kernel(FastArgs a) {
+  using S = Shape<K>;
+  __shared__ __align__(16) float U[kCH * S::IWP];
+  __shared__ __align__(16) float V[kCH * S::IWP];
+  __shared__ __align__(16) float HM[4 * S::BAND * kTW];
+  __shared__ float red[kNT / 64];
+  constexpr int PL = S::BAND * kTW;
+
+  const int frame = blockIdx.y;
+  const int tile = blockIdx.x;
+  const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
+  const int ox0 = txi * kTW, oy0 = tyi * a.g.TH;
+  const T* X = (const T*)a.x.data + (int64_t)frame * a.x.bstride;
+  const T* Y = (const T*)a.y.data + (int64_t)frame * a.y.bstride;
+  float taps[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) taps[t] = a.taps[t];
+
+  // prologue: the first K-1 footprint rows
+  stage_rows<K, T>(a, X, Y, oy0, ox0, S::HALO, U, V);
+  __syncthreads();
+  row_pass<K>(taps, U, V, S::HALO, HM, 0);
+
+  const int64_t plane = (int64_t)a.g.Ho * a.g.Wo;
+  const int64_t qstride = plane * a.batch;
+  const float gframe = (EPI == 1 && !a.grad_map) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
+  float acc = 0.f;
+  const int oy_end = min(a.g.Ho, oy0 + a.g.TH);
+  for (int cy = oy0; cy < oy_end; cy += kCH) {
+    __syncthreads();  // U, V free; band rows [0, HALO) ready
+    stage_rows<K, T>(a, X, Y, cy + S::HALO, ox0, kCH, U, V);
+    __syncthreads();
+    row_pass<K>(taps, U, V, kCH, HM, S::HALO);
+    __syncthreads();
+    // column pass: item = (4 output rows, 1 column)
+    for (int it = threadIdx.x; it < (kCH / 4) * kTW; it += kNT) {
+      const int gr = it / kTW, c = it - gr * kTW;
+      const int oj = ox0 + c;
+      const float* hu_ = HM + 4 * gr * kTW + c;
+      const float Tu = hu_[S::SHIFT * kTW], Tv = hu_[PL + S::SHIFT * kTW];
+      float Mu[4] = {0.f, 0.f, 0.f, 0.f}, Mv[4] = {0.f, 0.f, 0.f, 0.f};
+      float Su[4] = {0.f, 0.f, 0.f, 0.f}, Sv[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m = 0; m < K + 3; ++m) {
+        const float du = hu_[m * kTW] - Tu, dv = hu_[PL + m * kTW] - Tv;
+        const float su = fmaf(du, du, hu_[2 * PL + m * kTW]);
+        const float sv = fmaf(dv, dv, hu_[3 * PL + m * kTW]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int t = m - j;
+          if (t >= 0 && t < K) {
+            const float w = taps[t];
+            Mu[j] = fmaf(w, du, Mu[j]);
+            Mv[j] = fmaf(w, dv, Mv[j]);
+            Su[j] = fmaf(w, su, Su[j]);
+            Sv[j] = fmaf(w, sv, Sv[j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int oi = cy + 4 * gr + j;
+        if (oi >= oy_end || oj >= a.g.Wo) continue;
+        const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
+        const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
+        const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
+        if constexpr (EPI == 0) {
+          const float val = ssim_value(t, a.mode);
+          if (a.map) a.map[(int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + oj] = val;
+          acc += val;
+        } else {
+          const float g = a.grad_map ? a.grad_map[(int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch + oj]
+                                     : gframe;
+          const float ib2 = 1.f / t.B2;
+          const float dcs_du = 0.5f * var_v * ib2 * ib2;
+          const float dcs_dv = -0.5f * (t.A2 + t.B2) * ib2 * ib2;
+          float au = 0.f, av = 0.f, bu, bv;
+          if (a.mode == 0) {
+            const float ib1 = 1.f / t.B1;
+            const float l = t.A1 * ib1, cs = t.A2 * ib2;
+            au = cs * mean_u * (mean_v * mean_v) * ib1 * ib1;
+            av = -cs * mean_v * (t.A1 + t.B1) * ib1 * ib1;
+            bu = l * dcs_du;
+            bv = l * dcs_dv;
+          } else {
+            bu = dcs_du;
+            bv = dcs_dv;
+          }
+          const int64_t o = (int64_t)frame * plane + (int64_t)oi * a.g.Wo + oj;
+          a.coef[o] = g * (au - 2.f * bu * (mean_u - a.tu));
+          a.coef[qstride + o] = 2.f * g * bu;
+          a.coef[2 * qstride + o] = g * (av - 2.f * bv * (mean_v - a.tv));
+          a.coef[3 * qstride + o] = 2.f * g * bv;
+        }
+      }
+    }
+    __syncthreads();
+    band_shift<K>(HM);
+  }
+  if constexpr (EPI == 0) {
+    const float tot = block_sum<kNT>(acc, red);
+    if (threadIdx.x == 0) a.partial[(int64_t)frame * gridDim.x + tile] = tot;
+  }
+}
+
+// ---------------------------------------------------------------- adjoint
+// Transposed window over the four coefficient maps (valid borders, stride 1):
+// G_q(y) = sum_{p in map, y - p in [0, K)} w(y - p) C_q(p), a plain K x K
+// correlation of the zero-extended maps with the (symmetric) window.
+namespace {
+
+template <int K>
+struct AShape {
+  static constexpr int HALO = K - 1;
+  static constexpr int NREAD = (K + 3 + 3) / 4;
+  static constexpr int IWP = kTW - 4 + 4 * NREAD;
+  static constexpr int NQ = IWP / 4;
+  static constexpr int CH = 16;                     // pixel rows per chunk
+  static constexpr int BAND = CH + HALO;
+  static_assert(CH >= HALO, "band copy needs CH >= K - 1");
+};
+
+template <int K>
+__device__ __forceinline__ void stage_coef(const FastArgs& a, int frame, int r0, int c0, int nrows, float* C) {
+  using S = AShape<K>;
+  constexpr int PLC = S::CH * S::IWP;
+  const int64_t plane = (int64_t)a.g.Ho * a.g.Wo;
+  const int64_t qstride = plane * a.batch;
+  for (int it = threadIdx.x; it < nrows * S::NQ; it += kNT) {
+    const int r = it / S::NQ, q = it - r * S::NQ;
+    const int pr = r0 + r, pc = c0 + 4 * q;
+    const bool rowin = pr >= 0 && pr < a.g.Ho;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float e[4];
+      const float* src = a.coef + m * qstride + (int64_t)frame * plane + (int64_t)pr * a.g.Wo;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) e[i] = (rowin && pc + i >= 0 && pc + i < a.g.Wo) ? src[pc + i] : 0.f;
+      *(float4*)&C[m * PLC + r * S::IWP + 4 * q] = make_float4(e[0], e[1], e[2], e[3]);
+    }
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void coef_row_pass(const float* taps, const float* C, int nrows, float* HM, int band0) {
+  using S = AShape<K>;
+  constexpr int PLC = S::CH * S::IWP;
+  constexpr int PL = S::BAND * kTW;
+  constexpr int NG = kTW / 4;
+  for (int it = threadIdx.x; it < nrows * NG; it += kNT) {
+    const int r = it / NG, gq = it - r * NG;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float z[4 * S::NREAD];
+#pragma unroll
+      for (int n = 0; n < S::NREAD; ++n)
+        *(float4*)&z[4 * n] = *(const float4*)&C[m * PLC + r * S::IWP + 4 * gq + 4 * n];
+      float h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float s = 0.f;
+#pragma unroll
+        for (int t = 0; t < K; ++t) s = fmaf(taps[t], z[j + t], s);
+        h[j] = s;
+      }
+      *(float4*)&HM[m * PL + (band0 + r) * kTW + 4 * gq] = make_float4(h[0], h[1], h[2], h[3]);
+    }
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void coef_band_shift(float* HM) {
+  using S = AShape<K>;
+  constexpr int PL = S::BAND * kTW;
+  constexpr int NV = S::HALO * kTW / 4;
+  for (int it = threadIdx.x; it < 4 * NV; it += kNT) {
+    const int m = it / NV, e = it - m * NV;
+    *(float4*)&HM[m * PL + 4 * e] = *(const float4*)&HM[m * PL + S::CH * kTW + 4 * e];
+  }
+}
+
+}  // namespace
+
+template <int K, typename T>
+__global__ __launch_bounds__(kNT, 2) void fast_adjoint_kernel(FastArgs a) {
+  using S = AShape<K>;
+  __shared__ __align__(16) float C[4 * S::CH * S::IWP];
+  __shared__ __align__(16) float HM[4 * S::BAND * kTW];
+  constexpr int PL = S::BAND * kTW;
+  const int frame = blockIdx.y;
+  const int tile = blockIdx.x;
+  const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
+  const int qx0 = txi * kTW, qy0 = tyi * a.QH;
+  float taps[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) taps[t] = a.taps[t];
+  const T* X = (const T*)a.x.data + (int64_t)frame * a.x.bstride;
+  const T* Y = (const T*)a.y.data + (int64_t)frame * a.y.bstride;
+
+  // pixel row y reads map rows y-K+1 .. y; prologue = the first K-1 of them
+  stage_coef<K>(a, frame, qy0 - S::HALO, qx0 - S::HALO, S::HALO, C);
+  __syncthreads();
+  coef_row_pass<K>(taps, C, S::HALO, HM, 0);
+  const int qy_end = min(a.g.H, qy0 + a.QH);
+  for (int cy = qy0; cy < qy_end; cy += S::CH) {
+    __syncthreads();
+    stage_coef<K>(a, frame, cy, qx0 - S::HALO, S::CH, C);
+    __syncthreads();
+    coef_row_pass<K>(taps, C, S::CH, HM, S::HALO);
+    __syncthreads();
+    for (int it = threadIdx.x; it < (S::CH / 4) * kTW; it += kNT) {
+      const int gr = it / kTW, c = it - gr * kTW;
+      const int px = qx0 + c;
+      float G[4][4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) G[m][j] = 0.f;
+#pragma unroll
+      for (int r = 0; r < K + 3; ++r) {
+        float h[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) h[m] = HM[m * PL + (4 * gr + r) * kTW + c];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int t = r - j;
+          if (t >= 0 && t < K) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) G[m][j] = fmaf(taps[t], h[m], G[m][j]);
+          }
+        }
+      }
+      if (px >= a.g.W) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int py = cy + 4 * gr + j;
+        if (py >= qy_end) continue;
+        const float xv = to_f32<T>(X[(int64_t)py * a.x.pitch + px]);
+        const float yv = to_f32<T>(Y[(int64_t)py * a.y.pitch + px]);
+        const float du = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]);
+        const float dv = fmaf((xv - yv) - a.tv, G[3][j], G[2][j]);
+        float gy = du - dv;
+        if (a.coarse) {
+          const int cyy = py >> 1, cxx = px >> 1;
+          if (cyy < a.Hc && cxx < a.Wc) gy += 0.25f * a.coarse[((int64_t)frame * a.Hc + cyy) * a.Wc + cxx];
+        }
+        a.out[(int64_t)frame * a.out_bstride + (int64_t)py * a.out_pitch + px] = gy;
+      }
+    }
+    __syncthreads();
+    coef_band_shift<K>(HM);
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+bool fast_supported(int k, int stride) {
+  return stride == 1 && (k == 7 || k == 9 || k == 11 || k == 13);
+}
+
+template <int K, int EPI>
+static int launch_stats_k(int dtype, const FastArgs& a, dim3 grid, hipStream_t st) {
+  switch (dtype) {
+    case SSIMX_U8: hipLaunchKernelGGL((fast_stats_kernel<K, uint8_t, EPI>), grid, dim3(kNT), 0, st, a); break;
+    case SSIMX_U16: hipLaunchKernelGGL((fast_stats_kernel<K, uint16_t, EPI>), grid, dim3(kNT), 0, st, a); break;
+    case SSIMX_F32: hipLaunchKernelGGL((fast_stats_kernel<K, float, EPI>), grid, dim3(kNT), 0, st, a); break;
+    case SSIMX_BF16: hipLaunchKernelGGL((fast_stats_kernel<K, bf16_t, EPI>), grid, dim3(kNT), 0, st, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStream_t st) {
+  dim3 grid(a.g.tiles_x * a.g.tiles_y, batch);
+#define SSIMX_K(KK)                                                                          \
+  case KK:                                                                                   \
+    return epi == 0 ? launch_stats_k<KK, 0>(dtype, a, grid, st) : launch_stats_k<KK, 1>(dtype, a, grid, st);
+  switch (a.g.k) {
+    SSIMX_K(7)
+    SSIMX_K(9)
+    SSIMX_K(11)
+    SSIMX_K(13)
+    default: return (int)hipErrorInvalidValue;
+  }
+#undef SSIMX_K
+}
+
+template <int K>
+static int launch_adj_k(int dtype, const FastArgs& a, dim3 grid, hipStream_t st) {
+  switch (dtype) {
+    case SSIMX_U8: hipLaunchKernelGGL((fast_adjoint_kernel<K, uint8_t>), grid, dim3(kNT), 0, st, a); break;
+    case SSIMX_U16: hipLaunchKernelGGL((fast_adjoint_kernel<K, uint16_t>), grid, dim3(kNT), 0, st, a); break;
+    case SSIMX_F32: hipLaunchKernelGGL((fast_adjoint_kernel<K, float>), grid, dim3(kNT), 0, st, a); break;
+    case SSIMX_BF16: hipLaunchKernelGGL((fast_adjoint_kernel<K, bf16_t>), grid, dim3(kNT), 0, st, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st) {
+  dim3 grid(a.qtiles_x * a.qtiles_y, batch);
+  switch (a.g.k) {
+    case 7: return launch_adj_k<7>(dtype, a, grid, st);
+    case 9: return launch_adj_k<9>(dtype, a, grid, st);
+    case 11: return launch_adj_k<11>(dtype, a, grid, st);
+    case 13: return launch_adj_k<13>(dtype, a, grid, st);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ssimx

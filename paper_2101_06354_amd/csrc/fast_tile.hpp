@@ -1,0 +1,41 @@
+// Arguments of the stride-1, compile-time-K tiled kernels (fast_tile.hip).
+#pragma once
+
+#include "ssimx_internal.hpp"
+
+namespace ssimx {
+
+struct FastArgs {
+  PlaneArg x, y;
+  Geom g;            // TW fixed at 64; TH = output rows per tile (multiple of 32)
+  float C1, C2;
+  int mode;          // 0: Q = l*cs, 1: cs
+  int vec_ok;        // 4-element vector loads allowed for interior footprint rows
+  // forward epilogue
+  float* map;
+  int64_t map_pitch, map_bstride;
+  float* partial;
+  // coefficient epilogue
+  const float* grad_map;
+  int64_t gm_pitch, gm_bstride;
+  const float* gscale;
+  int gscale_stride;
+  float gmul;
+  float tu, tv;
+  float* coef;       // [4][batch][Ho][Wo]
+  int batch;
+  // adjoint (transposed window) pass
+  int QH, qtiles_x, qtiles_y;
+  float* out;
+  int64_t out_pitch, out_bstride;
+  const float* coarse;
+  int Wc, Hc;
+  float taps[KMAX_GAUSS];
+};
+
+bool fast_supported(int k, int stride);
+int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStream_t st);
+int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st);
+int fast_chunks(int tile_idx);   // 32-row chunks per tile of the fast kernels
+
+}  // namespace ssimx

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "fast_tile.hpp"
 #include "host_common.hpp"
 #include "ssimx_internal.hpp"
 
@@ -73,7 +74,11 @@ ssimx_status check_path(const ssimx_params* p, int dtype) {
 // ---------------------------------------------------------------- geometry
 static const TileCfg kTiles[] = {{32, 32}, {64, 16}, {64, 32}, {32, 16}, {128, 8}, {16, 32}};
 
+// 32-row chunks per tile of the stride-1 fast kernels, for the same index
+static const int kFastChunks[] = {4, 2, 8, 1, 16, 34};
+
 int num_tile_cfgs() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
+int fast_chunks(int idx) { return kFastChunks[(idx >= 0 && idx < num_tile_cfgs()) ? idx : 0]; }
 TileCfg tile_cfg(int idx) { return kTiles[(idx >= 0 && idx < num_tile_cfgs()) ? idx : 0]; }
 
 void map_dims(const ssimx_params* p, int W, int H, int& Wo, int& Ho) {
@@ -101,6 +106,45 @@ static Geom geom_with(const ssimx_params* p, int W, int H, int tw, int th) {
   g.tiles_x = (g.Wo + g.TW - 1) / g.TW;
   g.tiles_y = (g.Ho + g.TH - 1) / g.TH;
   return g;
+}
+
+static bool aligned_vec(const void* p, int64_t pitch, int64_t bstride, int esize) {
+  return ((uintptr_t)p % (4 * esize)) == 0 && pitch % 4 == 0 && bstride % 4 == 0;
+}
+
+int dtype_size(int dtype) { return dtype == SSIMX_U8 ? 1 : dtype == SSIMX_F32 ? 4 : 2; }
+
+Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx) {
+  Geom g = geom_with(p, W, H, 64, 32 * fast_chunks(tile_idx));
+  g.TW = 64;
+  g.TH = 32 * fast_chunks(tile_idx);
+  g.tiles_x = (g.Wo + 63) / 64;
+  g.tiles_y = (g.Ho + g.TH - 1) / g.TH;
+  return g;
+}
+
+// The fast kernels share one centring value among 4 adjacent windows; it sits
+// at window offsets k/2-2 .. k/2+1.  Their weights bound the rounding error
+// (sum g (z - t)^2 <= V (1 + 1/g_t)), so windows whose taps there are small
+// go to the generic kernel, which centres every window on its middle tap.
+bool use_fast(const ssimx_params* p, int dtype) {
+  if (choose_path(p, dtype) != Path::kSep || !fast_supported(p->k, p->stride)) return false;
+  float taps[KMAX_GAUSS];
+  gaussian_taps_f32(p->window, p->k, p->sigma, taps);
+  for (int t = p->k / 2 - 2; t <= p->k / 2 + 1; ++t)
+    if (taps[t] < 0.04f) return false;
+  return true;
+}
+
+void fill_fast_common(FastArgs& a, const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, const Geom& g) {
+  a.x = x;
+  a.y = y;
+  a.g = g;
+  a.C1 = (float)p->C1;
+  a.C2 = (float)p->C2;
+  a.vec_ok = aligned_vec(x.data, x.pitch, x.bstride, dtype_size(dtype)) &&
+             aligned_vec(y.data, y.pitch, y.bstride, dtype_size(dtype));
+  gaussian_taps_f32(p->window, p->k, p->sigma, a.taps);
 }
 
 size_t path_lds_bytes(Path path, int dtype, const Geom& g) {
@@ -141,6 +185,10 @@ int max_partials(const ssimx_params* p, int dtype, int W, int H) {
   for (int i = 0; i < num_tile_cfgs(); ++i) {
     const Geom g = make_geom_path(p, dtype, W, H, i);
     m = std::max(m, g.tiles_x * g.tiles_y);
+    if (use_fast(p, dtype)) {
+      const Geom f = fast_geom(p, W, H, i);
+      m = std::max(m, f.tiles_x * f.tiles_y);
+    }
   }
   return m;
 }
@@ -234,7 +282,19 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
   const float C1 = (float)p->C1, C2 = (float)p->C2;
   int err = 0, tiles = 0;
   Geom g = make_geom_path(p, dtype, W, H, tile_idx);
-  if (path == Path::kSep) {
+  if (use_fast(p, dtype)) {
+    FastArgs a{};
+    g = fast_geom(p, W, H, tile_idx);
+    fill_fast_common(a, p, dtype, x, y, g);
+    a.mode = mode;
+    a.map = map;
+    a.map_pitch = map_pitch;
+    a.map_bstride = map_bstride;
+    a.partial = partial;
+    a.batch = batch;
+    err = launch_fast_stats(dtype, 0, a, batch, st);
+    tiles = g.tiles_x * g.tiles_y;
+  } else if (path == Path::kSep) {
     SepArgs a{};
     a.x = x;
     a.y = y;

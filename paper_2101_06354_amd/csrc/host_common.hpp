@@ -29,6 +29,12 @@ void scale_dims(int W, int H, int n_scales, int* Ws_, int* Hs_);
 void ms_weights(const float* weights, int n_scales, int flags, float* w);
 size_t fwd_ws_bytes(const ssimx_params* p, int dtype, int W, int H, int batch);
 
+struct FastArgs;
+int dtype_size(int dtype);
+Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx);
+bool use_fast(const ssimx_params* p, int dtype);
+void fill_fast_common(FastArgs& a, const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, const Geom& g);
+
 // Bump allocator over a caller workspace (256-byte aligned slices).
 struct Ws {
   size_t used = 0;

@@ -57,8 +57,6 @@ ssimx_status ssimx_set_tile_override(int tile) {
   return SSIMX_OK;
 }
 
-static size_t dtype_size(int dt) { return dt == SSIMX_U8 ? 1 : dt == SSIMX_F32 ? 4 : 2; }
-
 ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int height, int batch, void* stream,
                             int* best_tile_out) {
   ssimx_status s = check_params(p);
@@ -69,7 +67,7 @@ ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int hei
   map_dims(p, width, height, Wo, Ho);
   if (Wo < 1 || Ho < 1) return SSIMX_ETOOSMALL;
   hipStream_t st = (hipStream_t)stream;
-  const size_t plane = (size_t)width * height * batch * dtype_size(dtype);
+  const size_t plane = (size_t)width * height * batch * ssimx::dtype_size(dtype);
   const size_t wsb = fwd_ws_bytes(p, dtype, width, height, batch);
   void *x = nullptr, *y = nullptr, *ws = nullptr, *score = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -90,17 +88,17 @@ ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int hei
     for (int t = 0; t < ncfg && s == SSIMX_OK; ++t) {
       std::vector<float> times;
       for (int rep = 0; rep < 7 && s == SSIMX_OK; ++rep) {
-        hipEventRecord(e0, st);
+        (void)hipEventRecord(e0, st);
         s = fwd_pass(p, dtype, xa, ya, width, height, batch, 0, nullptr, 0, 0, (float*)score, 1, (float*)ws,
                      path == Path::kSat ? (uint32_t*)((char*)ws + ((sizeof(float) * batch *
                                                                     max_partials(p, dtype, width, height) + 255) &
                                                                    ~(size_t)255))
                                         : nullptr,
                      t, st);
-        hipEventRecord(e1, st);
-        hipEventSynchronize(e1);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
         if (rep >= 2) times.push_back(ms);
       }
       if (s != SSIMX_OK) break;
@@ -112,12 +110,12 @@ ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int hei
       }
     }
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  if (x) hipFree(x);
-  if (y) hipFree(y);
-  if (ws) hipFree(ws);
-  if (score) hipFree(score);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (x) (void)hipFree(x);
+  if (y) (void)hipFree(y);
+  if (ws) (void)hipFree(ws);
+  if (score) (void)hipFree(score);
   if (err) return hip_status(err);
   if (s != SSIMX_OK) return s;
   {

@@ -165,3 +165,14 @@ def test_differentiable_loss_workload_full_size(P, dev, storage):
         scale = np.abs(gref[b]).max()
         tol = 1e-3 * scale if storage == "f32" else 1e-2 * scale
         assert abs(g[b, c, i, j] - fd) <= tol, (b, c, i, j, g[b, c, i, j], fd)
+
+
+@pytest.mark.parametrize("k,sigma", [(7, 1.0), (9, 1.5), (13, 2.0)])
+@pytest.mark.parametrize("h,w", [(150, 203), (40, 300)])
+def test_band_adjoint_window_sizes(P, dev, k, sigma, h, w):
+    rng = np.random.default_rng(k + h)
+    x = synth.smooth_field(rng, h, w, 16, 235).round().astype(np.uint8)
+    y = np.clip(x + rng.normal(0, 10, x.shape).round(), 0, 255).astype(np.uint8)
+    cfg = P.SSIMConfig(k=k, sigma=sigma)
+    g = P.ssim_backward(to_dev(x, dev), to_dev(y, dev), torch.tensor([1.0], device=dev), cfg)
+    _cmp(g.cpu().numpy(), O.ssim_pooled_backward(x, y, 1.0, oparams(cfg)), f"k{k}")

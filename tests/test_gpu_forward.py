@@ -203,3 +203,64 @@ def test_deterministic(P, dev):
     a = P.ssim(xt, yt, P.SSIMConfig(), return_map=True)
     b = P.ssim(xt, yt, P.SSIMConfig(), return_map=True)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("k,sigma", [(7, 1.0), (9, 1.5), (13, 2.0), (11, 1.5)])
+@pytest.mark.parametrize("padding", ["valid", "reflect", "zero"])
+@pytest.mark.parametrize("h,w", [(150, 203), (45, 64), (300, 77)])
+def test_stride1_band_kernel_window_sizes(P, dev, k, sigma, padding, h, w):
+    rng = np.random.default_rng(k * 7 + h)
+    x = synth.smooth_field(rng, h, w, 16, 235).round().astype(np.uint8)
+    y = np.clip(x + rng.normal(0, 15, x.shape).round(), 0, 255).astype(np.uint8)
+    _check_map(P, x, y, P.SSIMConfig(k=k, sigma=sigma, padding=padding), dev)
+
+
+def test_tile_configs_agree_and_unaligned_planes(P, dev):
+    x, y = synth.config1(frames=2, h=333, w=501)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    cfg = P.SSIMConfig()
+    maps, scores = [], []
+    try:
+        for t in range(P.num_tile_configs()):
+            P.set_tile_override(t)
+            s, m = P.ssim(xt, yt, cfg, return_map=True)
+            maps.append(m)
+            scores.append(s)
+    finally:
+        P.set_tile_override(-1)
+    for m in maps[1:]:
+        assert torch.equal(m, maps[0])
+    for s in scores[1:]:
+        assert torch.allclose(s, scores[0], rtol=0, atol=2e-7)
+    # the same frames at an odd byte offset (no vector loads) give the same map
+    bx = torch.zeros((2, 333, 503), dtype=torch.uint8, device=dev)
+    by = torch.zeros_like(bx)
+    bx[:, :, 1:502] = xt
+    by[:, :, 1:502] = yt
+    s2, m2 = P.ssim(bx[:, :, 1:502], by[:, :, 1:502], cfg, return_map=True)
+    assert torch.equal(m2, maps[0])
+    for f in range(2):
+        ref = O.ssim_map(x[f], y[f], oparams(cfg))["map"]
+        assert np.abs(maps[0][f].cpu().numpy() - ref).max() <= MAP_TOL
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32", "bf16"])
+def test_band_kernel_other_dtypes(P, dev, dtype):
+    if dtype == "u16":
+        x, y = synth.config2(frames=1, h=200, w=300)
+        x, y, L = x[0], y[0], 1023.0
+        xo, yo = x, y
+        xt, yt = to_dev(x, dev), to_dev(y, dev)
+    else:
+        r, d = synth.config4(batch=1, h=200, w=300)
+        x, y, L = r[0, 0], d[0, 0], 1.0
+        xt, yt = to_dev(x, dev), to_dev(y, dev)
+        xo, yo = x, y
+        if dtype == "bf16":
+            xt, yt = xt.bfloat16(), yt.bfloat16()
+            xo, yo = bf16_round(x), bf16_round(y)
+    cfg = P.SSIMConfig(L=L)
+    s, m = P.ssim(xt, yt, cfg, return_map=True)
+    ref = O.ssim_map(xo, yo, oparams(cfg))["map"]
+    assert np.abs(m[0].cpu().numpy() - ref).max() <= MAP_TOL
+    assert abs(float(s[0]) - O.mean_pool(ref)) <= SCORE_TOL
