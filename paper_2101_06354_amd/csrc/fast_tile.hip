@@ -1,12 +1,14 @@
 // Stride-1 tiled kernels with a compile-time window size K.
 //
 // A block owns a 64-column tile of the map and marches down it in chunks of
-// 32 output rows.  Per chunk the footprint rows are staged in LDS, the row
+// 16 output rows.  Per chunk the footprint rows are staged in LDS, the row
 // pass writes four row-statistics maps (row mean and row variance of u and
-// v) into an LDS band of 32 + K - 1 rows, and the column pass consumes it.
+// v) into an LDS band of 16 + K - 1 rows, and the column pass consumes it.
 // The K - 1 band rows shared with the next chunk are moved to the top of the
-// band instead of being recomputed, so the row pass costs (32 n + K - 1) /
-// (32 n) per output row for an n-chunk tile instead of (32 + K - 1) / 32.
+// band instead of being recomputed, so the row pass costs (16 n + K - 1) /
+// (16 n) per output row for an n-chunk tile instead of (16 + K - 1) / 16.
+// The next chunk's pixels are fetched into registers before the column pass
+// so that their load latency is hidden behind it.
 //
 // Register blocking: a row-pass item computes 4 adjacent outputs of one row
 // and a column-pass item 4 adjacent outputs of one column.  The 4 outputs of
@@ -33,7 +35,7 @@ namespace ssimx {
 namespace {
 
 constexpr int kTW = 64;   // map columns per tile
-constexpr int kCH = 32;   // output rows per chunk
+constexpr int kCH = 16;   // output rows per chunk
 constexpr int kNT = 256;  // threads per block
 
 template <int K>
@@ -97,6 +99,115 @@ __device__ __forceinline__ void stage_rows(const FastArgs& a, const T* X, const 
     load4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, yv);
     *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
     *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
+  }
+}
+
+// Raw footprint quad held in registers between the global load and the LDS
+// store (4 elements in the plane's own packing), so that the load latency of
+// the next chunk overlaps the column pass.  Border elements are gathered one
+// by one (zero outside the padded plane) and packed the same way.
+template <typename T>
+struct Quad {
+  static constexpr int NW = sizeof(T);  // 32-bit words for 4 elements
+  uint32_t w[NW];
+};
+
+template <typename T>
+__device__ __forceinline__ uint32_t elem_bits(T v) {
+  if constexpr (sizeof(T) == 4) return __float_as_uint(*(const float*)&v);
+  else if constexpr (sizeof(T) == 2) return (uint32_t)(*(const uint16_t*)&v);
+  else return (uint32_t)(*(const uint8_t*)&v);
+}
+
+template <typename T>
+__device__ __forceinline__ void fetch4(const T* P, int64_t pitch, const Geom& g, int vec_ok, int py, int px,
+                                       Quad<T>& q) {
+  if (vec_ok && g.pad == SSIMX_PAD_VALID && py < g.H && px + 3 < g.W) {
+    const T* s = P + (int64_t)py * pitch + px;
+    if constexpr (sizeof(T) == 1) {
+      q.w[0] = *(const uint32_t*)s;
+    } else if constexpr (sizeof(T) == 2) {
+      const uint2 v = *(const uint2*)s;
+      q.w[0] = v.x;
+      q.w[1] = v.y;
+    } else {
+      const uint4 v = *(const uint4*)s;
+      q.w[0] = v.x;
+      q.w[1] = v.y;
+      q.w[2] = v.z;
+      q.w[3] = v.w;
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < Quad<T>::NW; ++i) q.w[i] = 0u;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int sy, sx;
+    const uint32_t e =
+        padded_source(py, px + i, g.H, g.W, g.pad, g.before, g.Hp, g.Wp, sy, sx) ? elem_bits<T>(P[(int64_t)sy * pitch + sx])
+                                                                                 : 0u;
+    if constexpr (sizeof(T) == 1) q.w[0] |= e << (8 * i);
+    else if constexpr (sizeof(T) == 2) q.w[i >> 1] |= e << (16 * (i & 1));
+    else q.w[i] = e;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void unpack4(const Quad<T>& q, float* o) {
+  if constexpr (sizeof(T) == 1) {
+    o[0] = (float)(q.w[0] & 0xffu);
+    o[1] = (float)((q.w[0] >> 8) & 0xffu);
+    o[2] = (float)((q.w[0] >> 16) & 0xffu);
+    o[3] = (float)(q.w[0] >> 24);
+  } else if constexpr (sizeof(T) == 2) {
+    const T* e = (const T*)&q.w[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = to_f32<T>(e[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = __uint_as_float(q.w[i]);
+  }
+}
+
+// Chunk staging split in two halves: fetch_chunk issues the global loads of
+// kCH footprint rows into registers, store_chunk converts them to u, v and
+// writes LDS.
+template <int K>
+struct ChunkItems {
+  static constexpr int N = kCH * Shape<K>::NQ;
+  static constexpr int PER_THREAD = (N + kNT - 1) / kNT;
+};
+
+template <int K, typename T>
+__device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const T* Y, int py0, int px0, Quad<T>* qx,
+                                            Quad<T>* qy) {
+  using S = Shape<K>;
+#pragma unroll
+  for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
+    const int it = threadIdx.x + i * kNT;
+    if (it < ChunkItems<K>::N) {
+      const int r = it / S::NQ, q = it - r * S::NQ;
+      fetch4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qx[i]);
+      fetch4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qy[i]);
+    }
+  }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy, float* U, float* V) {
+  using S = Shape<K>;
+#pragma unroll
+  for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
+    const int it = threadIdx.x + i * kNT;
+    if (it < ChunkItems<K>::N) {
+      const int r = it / S::NQ, q = it - r * S::NQ;
+      float xv[4], yv[4];
+      unpack4<T>(qx[i], xv);
+      unpack4<T>(qy[i], yv);
+      *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
+      *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
+    }
   }
 }
 
@@ -164,7 +275,7 @@ __device__ __forceinline__ void band_shift(float* HM) {
 }  // namespace
 
 template <int K, typename T, int EPI>
-__global__ __launch_bounds__(kNT, 2) void fast_stats_kernel(FastArgs a) {
+__global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel(FastArgs a) {
   using S = Shape<K>;
   __shared__ __align__(16) float U[kCH * S::IWP];
   __shared__ __align__(16) float V[kCH * S::IWP];
@@ -192,12 +303,16 @@ __global__ __launch_bounds__(kNT, 2) void fast_stats_kernel(FastArgs a) {
   const float gframe = (EPI == 1 && !a.grad_map) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
   float acc = 0.f;
   const int oy_end = min(a.g.Ho, oy0 + a.g.TH);
+  Quad<T> qx[ChunkItems<K>::PER_THREAD], qy[ChunkItems<K>::PER_THREAD];
+  fetch_chunk<K, T>(a, X, Y, oy0 + S::HALO, ox0, qx, qy);
   for (int cy = oy0; cy < oy_end; cy += kCH) {
     __syncthreads();  // U, V free; band rows [0, HALO) ready
-    stage_rows<K, T>(a, X, Y, cy + S::HALO, ox0, kCH, U, V);
+    store_chunk<K, T>(qx, qy, U, V);
     __syncthreads();
     row_pass<K>(taps, U, V, kCH, HM, S::HALO);
     __syncthreads();
+    // the next chunk's pixels are loaded while this chunk's column pass runs
+    if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
     // column pass: item = (4 output rows, 1 column)
     for (int it = threadIdx.x; it < (kCH / 4) * kTW; it += kNT) {
       const int gr = it / kTW, c = it - gr * kTW;

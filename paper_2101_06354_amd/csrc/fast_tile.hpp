@@ -7,7 +7,7 @@ namespace ssimx {
 
 struct FastArgs {
   PlaneArg x, y;
-  Geom g;            // TW fixed at 64; TH = output rows per tile (multiple of 32)
+  Geom g;            // TW fixed at 64; TH = output rows per tile (multiple of 16)
   float C1, C2;
   int mode;          // 0: Q = l*cs, 1: cs
   int vec_ok;        // 4-element vector loads allowed for interior footprint rows
@@ -36,6 +36,6 @@ struct FastArgs {
 bool fast_supported(int k, int stride);
 int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStream_t st);
 int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st);
-int fast_chunks(int tile_idx);   // 32-row chunks per tile of the fast kernels
+int fast_chunks(int tile_idx);   // 16-row chunks per tile of the fast kernels
 
 }  // namespace ssimx

@@ -74,8 +74,8 @@ ssimx_status check_path(const ssimx_params* p, int dtype) {
 // ---------------------------------------------------------------- geometry
 static const TileCfg kTiles[] = {{32, 32}, {64, 16}, {64, 32}, {32, 16}, {128, 8}, {16, 32}};
 
-// 32-row chunks per tile of the stride-1 fast kernels, for the same index
-static const int kFastChunks[] = {4, 2, 8, 1, 16, 34};
+// 16-row chunks per tile of the stride-1 fast kernels, for the same index
+static const int kFastChunks[] = {8, 4, 16, 2, 32, 68};
 
 int num_tile_cfgs() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
 int fast_chunks(int idx) { return kFastChunks[(idx >= 0 && idx < num_tile_cfgs()) ? idx : 0]; }
@@ -115,9 +115,9 @@ static bool aligned_vec(const void* p, int64_t pitch, int64_t bstride, int esize
 int dtype_size(int dtype) { return dtype == SSIMX_U8 ? 1 : dtype == SSIMX_F32 ? 4 : 2; }
 
 Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx) {
-  Geom g = geom_with(p, W, H, 64, 32 * fast_chunks(tile_idx));
+  Geom g = geom_with(p, W, H, 64, 16 * fast_chunks(tile_idx));
   g.TW = 64;
-  g.TH = 32 * fast_chunks(tile_idx);
+  g.TH = 16 * fast_chunks(tile_idx);
   g.tiles_x = (g.Wo + 63) / 64;
   g.tiles_y = (g.Ho + g.TH - 1) / g.TH;
   return g;
