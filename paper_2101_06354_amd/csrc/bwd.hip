@@ -6,13 +6,15 @@
 //   dT(p)/du(q) = w(q - s p) [alpha_u(p) + 2 beta_u(p) (u(q) - mean_u(p))]
 // and likewise for v; dy = du - dv.  The backward therefore
 //   1. recomputes the moments of every map position (same centred passes as
-//      the forward; nothing is stored by the forward) and writes four
-//      coefficient maps, centred on a fixed shift t:
+//      the forward; nothing is stored by the forward) and forms, centred on
+//      a fixed shift t,
 //        A_u = g (alpha_u - 2 beta_u (mean_u - t_u)),  B_u = 2 g beta_u
-//      (g = upstream dL/dT(p)); then
+//      (g = upstream dL/dT(p)) and likewise for v; since the transposed
+//      window W^T is linear, only three planes are written:
+//        A = A_u - A_v, B_u, B_v;
 //   2. applies the transposed window to them (a gather over the positions
 //      whose window covers q) and combines
-//        dL/du(q) = (W^T A_u)(q) + (u(q) - t_u) (W^T B_u)(q).
+//        dL/dy(q) = (W^T A)(q) + (u(q) - t_u) (W^T B_u)(q) - (v(q) - t_v) (W^T B_v)(q).
 // Border handling is adjoined by folding the padded gradient back onto its
 // source pixels; the MS-SSIM pyramid by the transpose of 2x2 averaging.
 #include <math.h>
@@ -39,7 +41,8 @@ struct CoefArgs {
   int gscale_stride;
   float gmul;
   float tu, tv;
-  float* coef;  // [4][batch][Ho][Wo]
+  float* coef;  // planes A = A_u - A_v, B_u, B_v, each [batch][Ho][cpitch]
+  int cpitch;
   int batch;
   float taps[KMAX_GAUSS];
 };
@@ -52,8 +55,6 @@ __global__ __launch_bounds__(BLOCK) void bwd_coef_kernel(CoefArgs a) {
   const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
   const int ox0 = txi * a.g.TW, oy0 = tyi * a.g.TH;
   sep_tile_rows<T>(a.g, a.taps, a.x, a.y, frame, ox0, oy0, lds);
-  const int64_t plane = (int64_t)a.g.Ho * a.g.Wo;
-  const int64_t qstride = plane * a.batch;
   const float gframe = a.grad_map ? 0.f : a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul;
   for (int idx = threadIdx.x; idx < a.g.TH * a.g.TW; idx += BLOCK) {
     const int i = idx / a.g.TW, j = idx - i * a.g.TW;
@@ -77,18 +78,19 @@ __global__ __launch_bounds__(BLOCK) void bwd_coef_kernel(CoefArgs a) {
       bu = dcs_du;
       bv = dcs_dv;
     }
-    const int64_t o = (int64_t)frame * plane + (int64_t)oi * a.g.Wo + oj;
-    a.coef[o] = g * (au - 2.f * bu * (st.mean_u - a.tu));
-    a.coef[qstride + o] = 2.f * g * bu;
-    a.coef[2 * qstride + o] = g * (av - 2.f * bv * (st.mean_v - a.tv));
-    a.coef[3 * qstride + o] = 2.f * g * bv;
+    const int64_t o = ((int64_t)frame * a.g.Ho + oi) * a.cpitch + oj;
+    const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
+    a.coef[o] = g * ((au - 2.f * bu * (st.mean_u - a.tu)) - (av - 2.f * bv * (st.mean_v - a.tv)));
+    a.coef[qs + o] = 2.f * g * bu;
+    a.coef[2 * qs + o] = 2.f * g * bv;
   }
 }
 
 struct ScatArgs {
   PlaneArg x, y;
   Geom g;
-  const float* coef;
+  const float* coef;  // planes A, B_u, B_v, row pitch cpitch
+  int cpitch;
   int batch;
   float tu, tv;
   int QW, QH, qtiles_x, MR, MC;
@@ -117,34 +119,33 @@ __global__ __launch_bounds__(BLOCK) void bwd_scatter_kernel(ScatArgs a) {
   const int pc_hi = min(g.Wo - 1, (qx0 + a.QW - 1) / s);
   const int nr = max(0, pr_hi - pr_lo + 1), nc = max(0, pc_hi - pc_lo + 1);
   const int MR = a.MR, MC = a.MC, QW = a.QW;
-  float* C = lds;                  // [4][MR][MC]
-  float* Hm = C + 4 * MR * MC;     // [4][MR][QW]
-  const int64_t plane = (int64_t)g.Ho * g.Wo;
-  const int64_t qstride = plane * a.batch;
-  for (int idx = threadIdx.x; idx < 4 * nr * nc; idx += BLOCK) {
-    const int q = idx / (nr * nc), rem = idx - q * nr * nc;
-    const int r = rem / nc, c = rem - r * nc;
-    C[(q * MR + r) * MC + c] = a.coef[q * qstride + (int64_t)frame * plane + (int64_t)(pr_lo + r) * g.Wo + pc_lo + c];
+  float* C = lds;                  // [3][MR][MC]
+  float* Hm = C + 3 * MR * MC;     // [3][MR][QW]
+  const int64_t qs = (int64_t)a.batch * g.Ho * a.cpitch;
+  for (int idx = threadIdx.x; idx < nr * nc; idx += BLOCK) {
+    const int r = idx / nc, c = idx - r * nc;
+    const int64_t o = ((int64_t)frame * g.Ho + pr_lo + r) * a.cpitch + pc_lo + c;
+    C[r * MC + c] = a.coef[o];
+    C[(MR + r) * MC + c] = a.coef[qs + o];
+    C[(2 * MR + r) * MC + c] = a.coef[2 * qs + o];
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < nr * QW; idx += BLOCK) {
     const int r = idx / QW, qx = idx - r * QW;
     const int px = qx0 + qx;
     const int ca = max(pc_lo, ceil_div_i(px - k + 1, s)), cb = min(pc_hi, px / s);
-    float h0 = 0.f, h1 = 0.f, h2 = 0.f, h3 = 0.f;
+    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
     for (int pc = ca; pc <= cb; ++pc) {
       const float w = a.taps[px - s * pc];
       const int o = r * MC + (pc - pc_lo);
       h0 = fmaf(w, C[o], h0);
       h1 = fmaf(w, C[MR * MC + o], h1);
       h2 = fmaf(w, C[2 * MR * MC + o], h2);
-      h3 = fmaf(w, C[3 * MR * MC + o], h3);
     }
     const int o = r * QW + qx;
     Hm[o] = h0;
     Hm[MR * QW + o] = h1;
     Hm[2 * MR * QW + o] = h2;
-    Hm[3 * MR * QW + o] = h3;
   }
   __syncthreads();
   const T* X = (const T*)a.x.data + (int64_t)frame * a.x.bstride;
@@ -154,14 +155,13 @@ __global__ __launch_bounds__(BLOCK) void bwd_scatter_kernel(ScatArgs a) {
     const int py = qy0 + qy, px = qx0 + qx;
     if (py >= g.Hp || px >= g.Wp) continue;
     const int ra = max(pr_lo, ceil_div_i(py - k + 1, s)), rb = min(pr_hi, py / s);
-    float ga = 0.f, gb = 0.f, gc = 0.f, gd = 0.f;
+    float ga = 0.f, gb = 0.f, gc = 0.f;
     for (int pr = ra; pr <= rb; ++pr) {
       const float w = a.taps[py - s * pr];
       const int o = (pr - pr_lo) * QW + qx;
       ga = fmaf(w, Hm[o], ga);
       gb = fmaf(w, Hm[MR * QW + o], gb);
       gc = fmaf(w, Hm[2 * MR * QW + o], gc);
-      gd = fmaf(w, Hm[3 * MR * QW + o], gd);
     }
     int sy, sx;
     float xv = 0.f, yv = 0.f;
@@ -169,9 +169,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_scatter_kernel(ScatArgs a) {
       xv = to_f32<T>(X[(int64_t)sy * a.x.pitch + sx]);
       yv = to_f32<T>(Y[(int64_t)sy * a.y.pitch + sx]);
     }
-    const float du = fmaf((xv + yv) - a.tu, gb, ga);
-    const float dv = fmaf((xv - yv) - a.tv, gd, gc);
-    float gy = du - dv;
+    float gy = fmaf((xv + yv) - a.tu, gb, ga) - ((xv - yv) - a.tv) * gc;
     if (a.coarse) {
       const int cy = py >> 1, cx = px >> 1;
       if (cy < a.Hc && cx < a.Wc) gy += 0.25f * a.coarse[((int64_t)frame * a.Hc + cy) * a.Wc + cx];
@@ -253,7 +251,7 @@ static Geom scat_geom_fit(const Geom& g, int& QW, int& QH, int& MR, int& MC, int
   while (true) {
     MR = (QH + g.k - 2) / g.s + 1;
     MC = (QW + g.k - 2) / g.s + 1;
-    const size_t bytes = sizeof(float) * (4 * (size_t)MR * MC + 4 * (size_t)MR * QW);
+    const size_t bytes = sizeof(float) * (3 * (size_t)MR * MC + 3 * (size_t)MR * QW);
     if (bytes <= kLdsLimit || (QW == 1 && QH == 1)) break;
     if (QH >= QW && QH > 1)
       QH /= 2;
@@ -282,6 +280,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
   Geom g = make_geom_path(&pf, SSIMX_F32, lv.W, lv.H, 0);
   const bool valid = p->padding == SSIMX_PAD_VALID;
   const bool fast = use_fast(&pf, SSIMX_F32);
+  const int cpitch = (g.Wo + 3) & ~3;
   const float tu = shift_guess(p), tv = 0.f;
   int err = 0;
   FastArgs fa{};
@@ -297,6 +296,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     fa.tu = tu;
     fa.tv = tv;
     fa.coef = coef;
+    fa.cpitch = cpitch;
     fa.batch = batch;
     err = launch_fast_stats(lv.dtype, 1, fa, batch, st);
     if (err) return hip_status(err);
@@ -317,6 +317,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     ca.tu = tu;
     ca.tv = tv;
     ca.coef = coef;
+    ca.cpitch = cpitch;
     ca.batch = batch;
     gaussian_taps_f32(p->window, p->k, p->sigma, ca.taps);
     const size_t lds1 = sizeof(float) * sep_tile_lds_floats(g.IH, g.IW, g.TW);
@@ -349,6 +350,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
   sa.y = lv.y;
   sa.g = g;
   sa.coef = coef;
+  sa.cpitch = cpitch;
   sa.batch = batch;
   sa.tu = tu;
   sa.tv = tv;
@@ -368,7 +370,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     sa.out_bstride = (int64_t)g.Wp * g.Hp;
   }
   gaussian_taps_f32(p->window, p->k, p->sigma, sa.taps);
-  const size_t lds2 = sizeof(float) * (4 * (size_t)sa.MR * sa.MC + 4 * (size_t)sa.MR * sa.QW);
+  const size_t lds2 = sizeof(float) * (3 * (size_t)sa.MR * sa.MC + 3 * (size_t)sa.MR * sa.QW);
   dim3 grid2(qtx * qty, batch);
   switch (lv.dtype) {
     case SSIMX_U8: hipLaunchKernelGGL(bwd_scatter_kernel<uint8_t>, grid2, dim3(BLOCK), lds2, st, sa); break;
@@ -413,7 +415,7 @@ static SsimBwdLayout ssim_bwd_layout(const ssimx_params* p, int W, int H, int ba
   const int Hp = p->padding == SSIMX_PAD_VALID ? H : H + p->k - 1;
   Ws ws;
   SsimBwdLayout L;
-  L.coef = ws.take(sizeof(float) * 4 * (size_t)batch * Wo * Ho);
+  L.coef = ws.take(sizeof(float) * 3 * (size_t)batch * ((Wo + 3) & ~3) * Ho);
   L.gpad = p->padding == SSIMX_PAD_VALID ? 0 : ws.take(sizeof(float) * (size_t)batch * Wp * Hp);
   L.total = ws.used;
   return L;
@@ -433,7 +435,7 @@ static MsBwdLayout ms_bwd_layout(const ssimx_params* p, int dtype, int W, int H,
   L.up = ws.take(sizeof(float) * batch * M);
   int Wo, Ho;
   map_dims(p, W, H, Wo, Ho);
-  L.coef = ws.take(sizeof(float) * 4 * (size_t)batch * Wo * Ho);
+  L.coef = ws.take(sizeof(float) * 3 * (size_t)batch * ((Wo + 3) & ~3) * Ho);
   const int Wp = p->padding == SSIMX_PAD_VALID ? W : W + p->k - 1;
   const int Hp = p->padding == SSIMX_PAD_VALID ? H : H + p->k - 1;
   L.gpad = p->padding == SSIMX_PAD_VALID ? 0 : ws.take(sizeof(float) * (size_t)batch * Wp * Hp);

@@ -35,6 +35,8 @@ namespace ssimx {
 namespace {
 
 constexpr int kTW = 64;   // map columns per tile
+constexpr int kTWP = 68;  // LDS row stride of the statistics band (4 floats of padding keep rows and
+                          // map planes off a common bank)
 constexpr int kCH = 16;   // output rows per chunk
 constexpr int kNT = 256;  // threads per block
 
@@ -45,6 +47,7 @@ struct Shape {
   static constexpr int IWP = kTW - 4 + 4 * NREAD;      // LDS row length of the footprint
   static constexpr int NQ = IWP / 4;                   // float4 quads per footprint row
   static constexpr int BAND = kCH + HALO;              // rows of the row-statistics band
+  static constexpr int PL = BAND * kTWP;               // floats per statistics map
   static constexpr int SHIFT = K / 2 + 1;              // centring offset of an item
   static_assert(IWP >= kTW + K - 1, "footprint row too short");
   static_assert(kCH >= HALO, "band copy needs CH >= K - 1");
@@ -217,7 +220,7 @@ __device__ __forceinline__ void row_pass(const float* taps, const float* U, cons
                                          int band0) {
   using S = Shape<K>;
   constexpr int NG = kTW / 4;
-  constexpr int PL = S::BAND * kTW;  // one statistics map in the band
+  constexpr int PL = S::PL;
   for (int it = threadIdx.x; it < nrows * NG; it += kNT) {
     const int r = it / NG, gq = it - r * NG;
     float u[4 * S::NREAD], v[4 * S::NREAD];
@@ -252,7 +255,7 @@ __device__ __forceinline__ void row_pass(const float* taps, const float* U, cons
       vu[j] = fmaf(-au, au, qu);
       vv[j] = fmaf(-av, av, qv);
     }
-    const int o = (band0 + r) * kTW + 4 * gq;
+    const int o = (band0 + r) * kTWP + 4 * gq;
     *(float4*)&HM[o] = make_float4(hu[0], hu[1], hu[2], hu[3]);
     *(float4*)&HM[PL + o] = make_float4(hv[0], hv[1], hv[2], hv[3]);
     *(float4*)&HM[2 * PL + o] = make_float4(vu[0], vu[1], vu[2], vu[3]);
@@ -264,11 +267,11 @@ __device__ __forceinline__ void row_pass(const float* taps, const float* U, cons
 template <int K>
 __device__ __forceinline__ void band_shift(float* HM) {
   using S = Shape<K>;
-  constexpr int PL = S::BAND * kTW;
   constexpr int NV = S::HALO * kTW / 4;  // float4 per map
   for (int it = threadIdx.x; it < 4 * NV; it += kNT) {
     const int m = it / NV, e = it - m * NV;
-    *(float4*)&HM[m * PL + 4 * e] = *(const float4*)&HM[m * PL + kCH * kTW + 4 * e];
+    const int row = e / (kTW / 4), q = e % (kTW / 4);
+    *(float4*)&HM[m * S::PL + row * kTWP + 4 * q] = *(const float4*)&HM[m * S::PL + (kCH + row) * kTWP + 4 * q];
   }
 }
 
@@ -279,9 +282,9 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
   using S = Shape<K>;
   __shared__ __align__(16) float U[kCH * S::IWP];
   __shared__ __align__(16) float V[kCH * S::IWP];
-  __shared__ __align__(16) float HM[4 * S::BAND * kTW];
+  __shared__ __align__(16) float HM[4 * S::PL];
   __shared__ float red[kNT / 64];
-  constexpr int PL = S::BAND * kTW;
+  constexpr int PL = S::PL;
 
   const int frame = blockIdx.y;
   const int tile = blockIdx.x;
@@ -298,8 +301,6 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
   __syncthreads();
   row_pass<K>(taps, U, V, S::HALO, HM, 0);
 
-  const int64_t plane = (int64_t)a.g.Ho * a.g.Wo;
-  const int64_t qstride = plane * a.batch;
   const float gframe = (EPI == 1 && !a.grad_map) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
   float acc = 0.f;
   const int oy_end = min(a.g.Ho, oy0 + a.g.TH);
@@ -317,15 +318,15 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
     for (int it = threadIdx.x; it < (kCH / 4) * kTW; it += kNT) {
       const int gr = it / kTW, c = it - gr * kTW;
       const int oj = ox0 + c;
-      const float* hu_ = HM + 4 * gr * kTW + c;
-      const float Tu = hu_[S::SHIFT * kTW], Tv = hu_[PL + S::SHIFT * kTW];
+      const float* hu_ = HM + 4 * gr * kTWP + c;
+      const float Tu = hu_[S::SHIFT * kTWP], Tv = hu_[PL + S::SHIFT * kTWP];
       float Mu[4] = {0.f, 0.f, 0.f, 0.f}, Mv[4] = {0.f, 0.f, 0.f, 0.f};
       float Su[4] = {0.f, 0.f, 0.f, 0.f}, Sv[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int m = 0; m < K + 3; ++m) {
-        const float du = hu_[m * kTW] - Tu, dv = hu_[PL + m * kTW] - Tv;
-        const float su = fmaf(du, du, hu_[2 * PL + m * kTW]);
-        const float sv = fmaf(dv, dv, hu_[3 * PL + m * kTW]);
+        const float du = hu_[m * kTWP] - Tu, dv = hu_[PL + m * kTWP] - Tv;
+        const float su = fmaf(du, du, hu_[2 * PL + m * kTWP]);
+        const float sv = fmaf(dv, dv, hu_[3 * PL + m * kTWP]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int t = m - j;
@@ -352,12 +353,13 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
         } else {
           const float g = a.grad_map ? a.grad_map[(int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch + oj]
                                      : gframe;
-          const float ib2 = 1.f / t.B2;
+          // reciprocal estimates (about 1 ulp) suffice for the adjoint
+          const float ib2 = __builtin_amdgcn_rcpf(t.B2);
           const float dcs_du = 0.5f * var_v * ib2 * ib2;
           const float dcs_dv = -0.5f * (t.A2 + t.B2) * ib2 * ib2;
           float au = 0.f, av = 0.f, bu, bv;
           if (a.mode == 0) {
-            const float ib1 = 1.f / t.B1;
+            const float ib1 = __builtin_amdgcn_rcpf(t.B1);
             const float l = t.A1 * ib1, cs = t.A2 * ib2;
             au = cs * mean_u * (mean_v * mean_v) * ib1 * ib1;
             av = -cs * mean_v * (t.A1 + t.B1) * ib1 * ib1;
@@ -367,11 +369,12 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
             bu = dcs_du;
             bv = dcs_dv;
           }
-          const int64_t o = (int64_t)frame * plane + (int64_t)oi * a.g.Wo + oj;
-          a.coef[o] = g * (au - 2.f * bu * (mean_u - a.tu));
-          a.coef[qstride + o] = 2.f * g * bu;
-          a.coef[2 * qstride + o] = g * (av - 2.f * bv * (mean_v - a.tv));
-          a.coef[3 * qstride + o] = 2.f * g * bv;
+          // W^T is linear: the two A maps are combined before the transpose
+          const int64_t o = ((int64_t)frame * a.g.Ho + oi) * a.cpitch + oj;
+          const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
+          a.coef[o] = g * ((au - 2.f * bu * (mean_u - a.tu)) - (av - 2.f * bv * (mean_v - a.tv)));
+          a.coef[qs + o] = 2.f * g * bu;
+          a.coef[2 * qs + o] = 2.f * g * bv;
         }
       }
     }
@@ -385,93 +388,138 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
 }
 
 // ---------------------------------------------------------------- adjoint
-// Transposed window over the four coefficient maps (valid borders, stride 1):
+// Transposed window over the coefficient planes (valid borders, stride 1):
 // G_q(y) = sum_{p in map, y - p in [0, K)} w(y - p) C_q(p), a plain K x K
-// correlation of the zero-extended maps with the (symmetric) window.
+// correlation of the zero-extended planes with the (symmetric) window.  Three
+// planes arrive (A = A_u - A_v, B_u, B_v), each with a row pitch that is a
+// multiple of 4; the footprint origin is aligned to 4 map columns so that an
+// interior footprint quad is one aligned 16-byte load per plane.  The next
+// chunk's quads are fetched into registers before the column pass.
 namespace {
+
+constexpr int kNM = 3;  // coefficient planes
 
 template <int K>
 struct AShape {
   static constexpr int HALO = K - 1;
-  static constexpr int NREAD = (K + 3 + 3) / 4;
+  static constexpr int LP = (4 - HALO % 4) % 4;          // left pad aligning the footprint origin
+  static constexpr int NREAD = (LP + K + 3 + 3) / 4;     // float4 LDS reads per row-pass item
   static constexpr int IWP = kTW - 4 + 4 * NREAD;
   static constexpr int NQ = IWP / 4;
-  static constexpr int CH = 16;                     // pixel rows per chunk
+  static constexpr int CH = 16;                           // pixel rows per chunk
   static constexpr int BAND = CH + HALO;
+  static constexpr int PL = BAND * kTWP;
+  static constexpr int ITEMS = CH * NQ;
+  static constexpr int PER_THREAD = (ITEMS + kNT - 1) / kNT;
   static_assert(CH >= HALO, "band copy needs CH >= K - 1");
+  static_assert(IWP >= LP + kTW + K - 1, "footprint row too short");
 };
 
+struct CQuad {
+  float4 v[kNM];  // four consecutive map positions of each plane
+};
+
+// Map rows r0 .. r0+nrows-1, footprint columns from c0 (a multiple of 4),
+// into registers.
 template <int K>
-__device__ __forceinline__ void stage_coef(const FastArgs& a, int frame, int r0, int c0, int nrows, float* C) {
+__device__ __forceinline__ void fetch_coef(const FastArgs& a, int frame, int r0, int c0, int nrows, CQuad* q) {
   using S = AShape<K>;
-  constexpr int PLC = S::CH * S::IWP;
-  const int64_t plane = (int64_t)a.g.Ho * a.g.Wo;
-  const int64_t qstride = plane * a.batch;
-  for (int it = threadIdx.x; it < nrows * S::NQ; it += kNT) {
-    const int r = it / S::NQ, q = it - r * S::NQ;
-    const int pr = r0 + r, pc = c0 + 4 * q;
-    const bool rowin = pr >= 0 && pr < a.g.Ho;
+  const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
+  const float* base = a.coef + (int64_t)frame * a.g.Ho * a.cpitch;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      float e[4];
-      const float* src = a.coef + m * qstride + (int64_t)frame * plane + (int64_t)pr * a.g.Wo;
+  for (int i = 0; i < S::PER_THREAD; ++i) {
+    const int it = threadIdx.x + i * kNT;
+    if (it < nrows * S::NQ) {
+      const int r = it / S::NQ, qq = it - r * S::NQ;
+      const int pr = r0 + r, pc = c0 + 4 * qq;
+      if (pr >= 0 && pr < a.g.Ho && pc >= 0 && pc + 3 < a.g.Wo) {
+        const float* src = base + (int64_t)pr * a.cpitch + pc;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) e[i] = (rowin && pc + i >= 0 && pc + i < a.g.Wo) ? src[pc + i] : 0.f;
-      *(float4*)&C[m * PLC + r * S::IWP + 4 * q] = make_float4(e[0], e[1], e[2], e[3]);
+        for (int m = 0; m < kNM; ++m) q[i].v[m] = *(const float4*)(src + m * qs);
+      } else {
+#pragma unroll
+        for (int m = 0; m < kNM; ++m) {
+          float e[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const bool in = pr >= 0 && pr < a.g.Ho && pc + k >= 0 && pc + k < a.g.Wo;
+            e[k] = in ? base[m * qs + (int64_t)pr * a.cpitch + pc + k] : 0.f;
+          }
+          q[i].v[m] = make_float4(e[0], e[1], e[2], e[3]);
+        }
+      }
     }
   }
 }
 
+// Registers -> the LDS planes C[m][r][col].
+template <int K>
+__device__ __forceinline__ void store_coef(const CQuad* q, int nrows, float* C) {
+  using S = AShape<K>;
+  constexpr int PLC = S::CH * S::IWP;
+#pragma unroll
+  for (int i = 0; i < S::PER_THREAD; ++i) {
+    const int it = threadIdx.x + i * kNT;
+    if (it < nrows * S::NQ) {
+      const int r = it / S::NQ, qq = it - r * S::NQ;
+      float* d = C + r * S::IWP + 4 * qq;
+#pragma unroll
+      for (int m = 0; m < kNM; ++m) *(float4*)&d[m * PLC] = q[i].v[m];
+    }
+  }
+}
+
+// Row pass of the transposed window: an item is one plane of one row and 4
+// adjacent outputs.  Consecutive lanes take consecutive 4-column groups of
+// the same plane and row, so every 8-lane phase of a 16-byte LDS read
+// touches 32 distinct banks.
 template <int K>
 __device__ __forceinline__ void coef_row_pass(const float* taps, const float* C, int nrows, float* HM, int band0) {
   using S = AShape<K>;
   constexpr int PLC = S::CH * S::IWP;
-  constexpr int PL = S::BAND * kTW;
   constexpr int NG = kTW / 4;
-  for (int it = threadIdx.x; it < nrows * NG; it += kNT) {
-    const int r = it / NG, gq = it - r * NG;
+  for (int it = threadIdx.x; it < nrows * kNM * NG; it += kNT) {
+    const int gq = it % NG, m = (it / NG) % kNM, r = it / (kNM * NG);
+    float z[4 * S::NREAD];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      float z[4 * S::NREAD];
+    for (int n = 0; n < S::NREAD; ++n)
+      *(float4*)&z[4 * n] = *(const float4*)&C[m * PLC + r * S::IWP + 4 * gq + 4 * n];
+    float h[4];
 #pragma unroll
-      for (int n = 0; n < S::NREAD; ++n)
-        *(float4*)&z[4 * n] = *(const float4*)&C[m * PLC + r * S::IWP + 4 * gq + 4 * n];
-      float h[4];
+    for (int j = 0; j < 4; ++j) {
+      float acc = 0.f;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float s = 0.f;
-#pragma unroll
-        for (int t = 0; t < K; ++t) s = fmaf(taps[t], z[j + t], s);
-        h[j] = s;
-      }
-      *(float4*)&HM[m * PL + (band0 + r) * kTW + 4 * gq] = make_float4(h[0], h[1], h[2], h[3]);
+      for (int t = 0; t < K; ++t) acc = fmaf(taps[t], z[S::LP + j + t], acc);
+      h[j] = acc;
     }
+    *(float4*)&HM[m * S::PL + (band0 + r) * kTWP + 4 * gq] = make_float4(h[0], h[1], h[2], h[3]);
   }
 }
 
 template <int K>
 __device__ __forceinline__ void coef_band_shift(float* HM) {
   using S = AShape<K>;
-  constexpr int PL = S::BAND * kTW;
   constexpr int NV = S::HALO * kTW / 4;
-  for (int it = threadIdx.x; it < 4 * NV; it += kNT) {
+  for (int it = threadIdx.x; it < kNM * NV; it += kNT) {
     const int m = it / NV, e = it - m * NV;
-    *(float4*)&HM[m * PL + 4 * e] = *(const float4*)&HM[m * PL + S::CH * kTW + 4 * e];
+    const int row = e / (kTW / 4), q = e % (kTW / 4);
+    *(float4*)&HM[m * S::PL + row * kTWP + 4 * q] = *(const float4*)&HM[m * S::PL + (S::CH + row) * kTWP + 4 * q];
   }
 }
 
 }  // namespace
 
 template <int K, typename T>
-__global__ __launch_bounds__(kNT, 2) void fast_adjoint_kernel(FastArgs a) {
+__global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   using S = AShape<K>;
-  __shared__ __align__(16) float C[4 * S::CH * S::IWP];
-  __shared__ __align__(16) float HM[4 * S::BAND * kTW];
-  constexpr int PL = S::BAND * kTW;
+  __shared__ __align__(16) float C[kNM * S::CH * S::IWP];
+  __shared__ __align__(16) float HM[kNM * S::PL];
+  constexpr int PL = S::PL;
   const int frame = blockIdx.y;
   const int tile = blockIdx.x;
   const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
   const int qx0 = txi * kTW, qy0 = tyi * a.QH;
+  const int c0 = qx0 - S::HALO - S::LP;
   float taps[K];
 #pragma unroll
   for (int t = 0; t < K; ++t) taps[t] = a.taps[t];
@@ -479,35 +527,39 @@ __global__ __launch_bounds__(kNT, 2) void fast_adjoint_kernel(FastArgs a) {
   const T* Y = (const T*)a.y.data + (int64_t)frame * a.y.bstride;
 
   // pixel row y reads map rows y-K+1 .. y; prologue = the first K-1 of them
-  stage_coef<K>(a, frame, qy0 - S::HALO, qx0 - S::HALO, S::HALO, C);
+  CQuad q[S::PER_THREAD];
+  fetch_coef<K>(a, frame, qy0 - S::HALO, c0, S::HALO, q);
+  store_coef<K>(q, S::HALO, C);
   __syncthreads();
   coef_row_pass<K>(taps, C, S::HALO, HM, 0);
   const int qy_end = min(a.g.H, qy0 + a.QH);
+  fetch_coef<K>(a, frame, qy0, c0, S::CH, q);
   for (int cy = qy0; cy < qy_end; cy += S::CH) {
     __syncthreads();
-    stage_coef<K>(a, frame, cy, qx0 - S::HALO, S::CH, C);
+    store_coef<K>(q, S::CH, C);
     __syncthreads();
     coef_row_pass<K>(taps, C, S::CH, HM, S::HALO);
     __syncthreads();
+    if (cy + S::CH < qy_end) fetch_coef<K>(a, frame, cy + S::CH, c0, S::CH, q);
     for (int it = threadIdx.x; it < (S::CH / 4) * kTW; it += kNT) {
       const int gr = it / kTW, c = it - gr * kTW;
       const int px = qx0 + c;
-      float G[4][4];
+      float G[kNM][4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < kNM; ++m)
 #pragma unroll
         for (int j = 0; j < 4; ++j) G[m][j] = 0.f;
 #pragma unroll
       for (int r = 0; r < K + 3; ++r) {
-        float h[4];
+        float h[kNM];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) h[m] = HM[m * PL + (4 * gr + r) * kTW + c];
+        for (int m = 0; m < kNM; ++m) h[m] = HM[m * PL + (4 * gr + r) * kTWP + c];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int t = r - j;
           if (t >= 0 && t < K) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) G[m][j] = fmaf(taps[t], h[m], G[m][j]);
+            for (int m = 0; m < kNM; ++m) G[m][j] = fmaf(taps[t], h[m], G[m][j]);
           }
         }
       }
@@ -518,9 +570,8 @@ __global__ __launch_bounds__(kNT, 2) void fast_adjoint_kernel(FastArgs a) {
         if (py >= qy_end) continue;
         const float xv = to_f32<T>(X[(int64_t)py * a.x.pitch + px]);
         const float yv = to_f32<T>(Y[(int64_t)py * a.y.pitch + px]);
-        const float du = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]);
-        const float dv = fmaf((xv - yv) - a.tv, G[3][j], G[2][j]);
-        float gy = du - dv;
+        // dL/dy = W^T A + (u - t_u) W^T B_u - (v - t_v) W^T B_v
+        float gy = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]) - ((xv - yv) - a.tv) * G[2][j];
         if (a.coarse) {
           const int cyy = py >> 1, cxx = px >> 1;
           if (cyy < a.Hc && cxx < a.Wc) gy += 0.25f * a.coarse[((int64_t)frame * a.Hc + cyy) * a.Wc + cxx];

@@ -22,7 +22,8 @@ struct FastArgs {
   int gscale_stride;
   float gmul;
   float tu, tv;
-  float* coef;       // [4][batch][Ho][Wo]
+  float* coef;       // planes A = A_u - A_v, B_u, B_v, each [batch][Ho][cpitch]
+  int cpitch;        // map positions per coefficient row (multiple of 4)
   int batch;
   // adjoint (transposed window) pass
   int QH, qtiles_x, qtiles_y;
