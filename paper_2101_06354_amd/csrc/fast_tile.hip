@@ -26,364 +26,20 @@
 //                                 maps and the per-pixel combine (valid
 //                                 borders), optionally adding the 2x2
 //                                 transpose of a coarser-scale gradient.
-#include "fast_tile.hpp"
-#include "ssim_epilogue.hpp"
-#include "ssimx_internal.hpp"
+#include "fast_tile_body.hpp"
 
 namespace ssimx {
 
-namespace {
-
-constexpr int kTW = 64;   // map columns per tile
-constexpr int kTWP = 68;  // LDS row stride of the statistics band (4 floats of padding keep rows and
-                          // map planes off a common bank)
-constexpr int kCH = 16;   // output rows per chunk
-constexpr int kNT = 256;  // threads per block
-
-template <int K>
-struct Shape {
-  static constexpr int HALO = K - 1;
-  static constexpr int NREAD = (K + 3 + 3) / 4;        // float4 reads per row-pass item
-  static constexpr int IWP = kTW - 4 + 4 * NREAD;      // LDS row length of the footprint
-  static constexpr int NQ = IWP / 4;                   // float4 quads per footprint row
-  static constexpr int BAND = kCH + HALO;              // rows of the row-statistics band
-  static constexpr int PL = BAND * kTWP;               // floats per statistics map
-  static constexpr int SHIFT = K / 2 + 1;              // centring offset of an item
-  static_assert(IWP >= kTW + K - 1, "footprint row too short");
-  static_assert(kCH >= HALO, "band copy needs CH >= K - 1");
-  static_assert(SHIFT - 3 >= 0 && SHIFT < K, "shared centring value must lie in all 4 windows");
-};
-
-// Four consecutive elements of the padded plane (zeros outside), as floats.
-template <typename T>
-__device__ __forceinline__ void load4(const T* P, int64_t pitch, const Geom& g, int vec_ok, int py, int px,
-                                      float* o) {
-  if (vec_ok && g.pad == SSIMX_PAD_VALID && py < g.H && px + 3 < g.W) {
-    const T* s = P + (int64_t)py * pitch + px;
-    if constexpr (sizeof(T) == 1) {
-      const uint32_t w = *(const uint32_t*)s;
-      o[0] = (float)(w & 0xffu);
-      o[1] = (float)((w >> 8) & 0xffu);
-      o[2] = (float)((w >> 16) & 0xffu);
-      o[3] = (float)(w >> 24);
-    } else if constexpr (sizeof(T) == 2) {
-      const uint2 w = *(const uint2*)s;
-      const T* e = (const T*)&w;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) o[i] = to_f32<T>(e[i]);
-    } else {
-      const float4 w = *(const float4*)s;
-      o[0] = w.x;
-      o[1] = w.y;
-      o[2] = w.z;
-      o[3] = w.w;
-    }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int sy, sx;
-    o[i] = padded_source(py, px + i, g.H, g.W, g.pad, g.before, g.Hp, g.Wp, sy, sx)
-               ? to_f32<T>(P[(int64_t)sy * pitch + sx])
-               : 0.f;
-  }
-}
-
-// Stage `nrows` footprint rows starting at padded row py0 into U, V (u = x+y,
-// v = x-y).
-template <int K, typename T>
-__device__ __forceinline__ void stage_rows(const FastArgs& a, const T* X, const T* Y, int py0, int px0, int nrows,
-                                           float* U, float* V) {
-  using S = Shape<K>;
-  for (int it = threadIdx.x; it < nrows * S::NQ; it += kNT) {
-    const int r = it / S::NQ, q = it - r * S::NQ;
-    float xv[4], yv[4];
-    load4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, xv);
-    load4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, yv);
-    *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
-    *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
-  }
-}
-
-// Raw footprint quad held in registers between the global load and the LDS
-// store (4 elements in the plane's own packing), so that the load latency of
-// the next chunk overlaps the column pass.  Border elements are gathered one
-// by one (zero outside the padded plane) and packed the same way.
-template <typename T>
-struct Quad {
-  static constexpr int NW = sizeof(T);  // 32-bit words for 4 elements
-  uint32_t w[NW];
-};
-
-template <typename T>
-__device__ __forceinline__ uint32_t elem_bits(T v) {
-  if constexpr (sizeof(T) == 4) return __float_as_uint(*(const float*)&v);
-  else if constexpr (sizeof(T) == 2) return (uint32_t)(*(const uint16_t*)&v);
-  else return (uint32_t)(*(const uint8_t*)&v);
-}
-
-template <typename T>
-__device__ __forceinline__ void fetch4(const T* P, int64_t pitch, const Geom& g, int vec_ok, int py, int px,
-                                       Quad<T>& q) {
-  if (vec_ok && g.pad == SSIMX_PAD_VALID && py < g.H && px + 3 < g.W) {
-    const T* s = P + (int64_t)py * pitch + px;
-    if constexpr (sizeof(T) == 1) {
-      q.w[0] = *(const uint32_t*)s;
-    } else if constexpr (sizeof(T) == 2) {
-      const uint2 v = *(const uint2*)s;
-      q.w[0] = v.x;
-      q.w[1] = v.y;
-    } else {
-      const uint4 v = *(const uint4*)s;
-      q.w[0] = v.x;
-      q.w[1] = v.y;
-      q.w[2] = v.z;
-      q.w[3] = v.w;
-    }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < Quad<T>::NW; ++i) q.w[i] = 0u;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int sy, sx;
-    const uint32_t e =
-        padded_source(py, px + i, g.H, g.W, g.pad, g.before, g.Hp, g.Wp, sy, sx) ? elem_bits<T>(P[(int64_t)sy * pitch + sx])
-                                                                                 : 0u;
-    if constexpr (sizeof(T) == 1) q.w[0] |= e << (8 * i);
-    else if constexpr (sizeof(T) == 2) q.w[i >> 1] |= e << (16 * (i & 1));
-    else q.w[i] = e;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void unpack4(const Quad<T>& q, float* o) {
-  if constexpr (sizeof(T) == 1) {
-    o[0] = (float)(q.w[0] & 0xffu);
-    o[1] = (float)((q.w[0] >> 8) & 0xffu);
-    o[2] = (float)((q.w[0] >> 16) & 0xffu);
-    o[3] = (float)(q.w[0] >> 24);
-  } else if constexpr (sizeof(T) == 2) {
-    const T* e = (const T*)&q.w[0];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = to_f32<T>(e[i]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = __uint_as_float(q.w[i]);
-  }
-}
-
-// Chunk staging split in two halves: fetch_chunk issues the global loads of
-// kCH footprint rows into registers, store_chunk converts them to u, v and
-// writes LDS.
-template <int K>
-struct ChunkItems {
-  static constexpr int N = kCH * Shape<K>::NQ;
-  static constexpr int PER_THREAD = (N + kNT - 1) / kNT;
-};
-
-template <int K, typename T>
-__device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const T* Y, int py0, int px0, Quad<T>* qx,
-                                            Quad<T>* qy) {
-  using S = Shape<K>;
-#pragma unroll
-  for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
-    const int it = threadIdx.x + i * kNT;
-    if (it < ChunkItems<K>::N) {
-      const int r = it / S::NQ, q = it - r * S::NQ;
-      fetch4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qx[i]);
-      fetch4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qy[i]);
-    }
-  }
-}
-
-template <int K, typename T>
-__device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy, float* U, float* V) {
-  using S = Shape<K>;
-#pragma unroll
-  for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
-    const int it = threadIdx.x + i * kNT;
-    if (it < ChunkItems<K>::N) {
-      const int r = it / S::NQ, q = it - r * S::NQ;
-      float xv[4], yv[4];
-      unpack4<T>(qx[i], xv);
-      unpack4<T>(qy[i], yv);
-      *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
-      *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
-    }
-  }
-}
-
-// Row pass over `nrows` staged rows into band rows [band0, band0 + nrows).
-template <int K>
-__device__ __forceinline__ void row_pass(const float* taps, const float* U, const float* V, int nrows, float* HM,
-                                         int band0) {
-  using S = Shape<K>;
-  constexpr int NG = kTW / 4;
-  constexpr int PL = S::PL;
-  for (int it = threadIdx.x; it < nrows * NG; it += kNT) {
-    const int r = it / NG, gq = it - r * NG;
-    float u[4 * S::NREAD], v[4 * S::NREAD];
-#pragma unroll
-    for (int n = 0; n < S::NREAD; ++n) {
-      *(float4*)&u[4 * n] = *(const float4*)&U[r * S::IWP + 4 * gq + 4 * n];
-      *(float4*)&v[4 * n] = *(const float4*)&V[r * S::IWP + 4 * gq + 4 * n];
-    }
-    const float tu = u[S::SHIFT], tv = v[S::SHIFT];
-    float du[K + 3], dv[K + 3], pu[K + 3], pv[K + 3];
-#pragma unroll
-    for (int n = 0; n < K + 3; ++n) {
-      du[n] = u[n] - tu;
-      dv[n] = v[n] - tv;
-      pu[n] = du[n] * du[n];
-      pv[n] = dv[n] * dv[n];
-    }
-    float hu[4], hv[4], vu[4], vv[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float au = 0.f, av = 0.f, qu = 0.f, qv = 0.f;
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        const float w = taps[t];
-        au = fmaf(w, du[j + t], au);
-        av = fmaf(w, dv[j + t], av);
-        qu = fmaf(w, pu[j + t], qu);
-        qv = fmaf(w, pv[j + t], qv);
-      }
-      hu[j] = tu + au;
-      hv[j] = tv + av;
-      vu[j] = fmaf(-au, au, qu);
-      vv[j] = fmaf(-av, av, qv);
-    }
-    const int o = (band0 + r) * kTWP + 4 * gq;
-    *(float4*)&HM[o] = make_float4(hu[0], hu[1], hu[2], hu[3]);
-    *(float4*)&HM[PL + o] = make_float4(hv[0], hv[1], hv[2], hv[3]);
-    *(float4*)&HM[2 * PL + o] = make_float4(vu[0], vu[1], vu[2], vu[3]);
-    *(float4*)&HM[3 * PL + o] = make_float4(vv[0], vv[1], vv[2], vv[3]);
-  }
-}
-
-// Move band rows [CH, CH + HALO) to [0, HALO).
-template <int K>
-__device__ __forceinline__ void band_shift(float* HM) {
-  using S = Shape<K>;
-  constexpr int NV = S::HALO * kTW / 4;  // float4 per map
-  for (int it = threadIdx.x; it < 4 * NV; it += kNT) {
-    const int m = it / NV, e = it - m * NV;
-    const int row = e / (kTW / 4), q = e % (kTW / 4);
-    *(float4*)&HM[m * S::PL + row * kTWP + 4 * q] = *(const float4*)&HM[m * S::PL + (kCH + row) * kTWP + 4 * q];
-  }
-}
-
-}  // namespace
+using namespace fast;
 
 template <int K, typename T, int EPI>
 __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel(FastArgs a) {
-  using S = Shape<K>;
-  __shared__ __align__(16) float U[kCH * S::IWP];
-  __shared__ __align__(16) float V[kCH * S::IWP];
-  __shared__ __align__(16) float HM[4 * S::PL];
+  __shared__ __align__(16) float smem[fast_smem_floats<K>()];
   __shared__ float red[kNT / 64];
-  constexpr int PL = S::PL;
-
-  const int frame = blockIdx.y;
-  const int tile = blockIdx.x;
-  const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
-  const int ox0 = txi * kTW, oy0 = tyi * a.g.TH;
-  const T* X = (const T*)a.x.data + (int64_t)frame * a.x.bstride;
-  const T* Y = (const T*)a.y.data + (int64_t)frame * a.y.bstride;
-  float taps[K];
-#pragma unroll
-  for (int t = 0; t < K; ++t) taps[t] = a.taps[t];
-
-  // prologue: the first K-1 footprint rows
-  stage_rows<K, T>(a, X, Y, oy0, ox0, S::HALO, U, V);
-  __syncthreads();
-  row_pass<K>(taps, U, V, S::HALO, HM, 0);
-
-  const float gframe = (EPI == 1 && !a.grad_map) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
-  float acc = 0.f;
-  const int oy_end = min(a.g.Ho, oy0 + a.g.TH);
-  Quad<T> qx[ChunkItems<K>::PER_THREAD], qy[ChunkItems<K>::PER_THREAD];
-  fetch_chunk<K, T>(a, X, Y, oy0 + S::HALO, ox0, qx, qy);
-  for (int cy = oy0; cy < oy_end; cy += kCH) {
-    __syncthreads();  // U, V free; band rows [0, HALO) ready
-    store_chunk<K, T>(qx, qy, U, V);
-    __syncthreads();
-    row_pass<K>(taps, U, V, kCH, HM, S::HALO);
-    __syncthreads();
-    // the next chunk's pixels are loaded while this chunk's column pass runs
-    if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
-    // column pass: item = (4 output rows, 1 column)
-    for (int it = threadIdx.x; it < (kCH / 4) * kTW; it += kNT) {
-      const int gr = it / kTW, c = it - gr * kTW;
-      const int oj = ox0 + c;
-      const float* hu_ = HM + 4 * gr * kTWP + c;
-      const float Tu = hu_[S::SHIFT * kTWP], Tv = hu_[PL + S::SHIFT * kTWP];
-      float Mu[4] = {0.f, 0.f, 0.f, 0.f}, Mv[4] = {0.f, 0.f, 0.f, 0.f};
-      float Su[4] = {0.f, 0.f, 0.f, 0.f}, Sv[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int m = 0; m < K + 3; ++m) {
-        const float du = hu_[m * kTWP] - Tu, dv = hu_[PL + m * kTWP] - Tv;
-        const float su = fmaf(du, du, hu_[2 * PL + m * kTWP]);
-        const float sv = fmaf(dv, dv, hu_[3 * PL + m * kTWP]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int t = m - j;
-          if (t >= 0 && t < K) {
-            const float w = taps[t];
-            Mu[j] = fmaf(w, du, Mu[j]);
-            Mv[j] = fmaf(w, dv, Mv[j]);
-            Su[j] = fmaf(w, su, Su[j]);
-            Sv[j] = fmaf(w, sv, Sv[j]);
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int oi = cy + 4 * gr + j;
-        if (oi >= oy_end || oj >= a.g.Wo) continue;
-        const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
-        const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
-        const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
-        if constexpr (EPI == 0) {
-          const float val = ssim_value(t, a.mode);
-          if (a.map) a.map[(int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + oj] = val;
-          acc += val;
-        } else {
-          const float g = a.grad_map ? a.grad_map[(int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch + oj]
-                                     : gframe;
-          // reciprocal estimates (about 1 ulp) suffice for the adjoint
-          const float ib2 = __builtin_amdgcn_rcpf(t.B2);
-          const float dcs_du = 0.5f * var_v * ib2 * ib2;
-          const float dcs_dv = -0.5f * (t.A2 + t.B2) * ib2 * ib2;
-          float au = 0.f, av = 0.f, bu, bv;
-          if (a.mode == 0) {
-            const float ib1 = __builtin_amdgcn_rcpf(t.B1);
-            const float l = t.A1 * ib1, cs = t.A2 * ib2;
-            au = cs * mean_u * (mean_v * mean_v) * ib1 * ib1;
-            av = -cs * mean_v * (t.A1 + t.B1) * ib1 * ib1;
-            bu = l * dcs_du;
-            bv = l * dcs_dv;
-          } else {
-            bu = dcs_du;
-            bv = dcs_dv;
-          }
-          // W^T is linear: the two A maps are combined before the transpose
-          const int64_t o = ((int64_t)frame * a.g.Ho + oi) * a.cpitch + oj;
-          const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
-          a.coef[o] = g * ((au - 2.f * bu * (mean_u - a.tu)) - (av - 2.f * bv * (mean_v - a.tv)));
-          a.coef[qs + o] = 2.f * g * bu;
-          a.coef[2 * qs + o] = 2.f * g * bv;
-        }
-      }
-    }
-    __syncthreads();
-    band_shift<K>(HM);
-  }
+  const float acc = fast_stats_tile<K, T, EPI>(a, blockIdx.y, blockIdx.x, smem);
   if constexpr (EPI == 0) {
     const float tot = block_sum<kNT>(acc, red);
-    if (threadIdx.x == 0) a.partial[(int64_t)frame * gridDim.x + tile] = tot;
+    if (threadIdx.x == 0) a.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
   }
 }
 
@@ -518,7 +174,7 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   const int frame = blockIdx.y;
   const int tile = blockIdx.x;
   const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
-  const int qx0 = txi * kTW, qy0 = tyi * a.QH;
+  const int qx0 = __builtin_amdgcn_readfirstlane(txi * kTW), qy0 = __builtin_amdgcn_readfirstlane(tyi * a.QH);
   const int c0 = qx0 - S::HALO - S::LP;
   float taps[K];
 #pragma unroll
@@ -532,7 +188,7 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   store_coef<K>(q, S::HALO, C);
   __syncthreads();
   coef_row_pass<K>(taps, C, S::HALO, HM, 0);
-  const int qy_end = min(a.g.H, qy0 + a.QH);
+  const int qy_end = __builtin_amdgcn_readfirstlane(min(a.g.H, qy0 + a.QH));
   fetch_coef<K>(a, frame, qy0, c0, S::CH, q);
   for (int cy = qy0; cy < qy_end; cy += S::CH) {
     __syncthreads();

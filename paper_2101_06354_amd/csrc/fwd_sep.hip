@@ -30,27 +30,10 @@ size_t sep_lds_bytes(const Geom& g) {
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void sep_fwd_kernel(SepArgs a) {
   extern __shared__ float lds[];
-  const int frame = blockIdx.y;
-  const int tile = blockIdx.x;
-  const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
-  const int ox0 = txi * a.g.TW, oy0 = tyi * a.g.TH;
   float* red = lds + sep_tile_lds_floats(a.g.IH, a.g.IW, a.g.TW);
-
-  sep_tile_rows<T>(a.g, a.taps, a.x, a.y, frame, ox0, oy0, lds);
-
-  float acc = 0.f;
-  for (int idx = threadIdx.x; idx < a.g.TH * a.g.TW; idx += BLOCK) {
-    const int i = idx / a.g.TW, j = idx - i * a.g.TW;
-    const int oi = oy0 + i, oj = ox0 + j;
-    if (oi >= a.g.Ho || oj >= a.g.Wo) continue;
-    const TileStats st = sep_tile_column(a.g, a.taps, lds, i, j);
-    const SsimTerms t = ssim_terms_uv(st.mean_u, st.mean_v, st.var_u, st.var_v, a.C1, a.C2);
-    const float val = ssim_value(t, a.mode);
-    if (a.map) a.map[(int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + oj] = val;
-    acc += val;
-  }
+  const float acc = sep_fwd_tile<T>(a, blockIdx.y, blockIdx.x, lds);
   const float tot = block_sum<BLOCK>(acc, red);
-  if (threadIdx.x == 0) a.partial[(int64_t)frame * gridDim.x + tile] = tot;
+  if (threadIdx.x == 0) a.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
 }
 
 int launch_sep_fwd(int dtype, const SepArgs& a, int batch, size_t lds, hipStream_t st) {

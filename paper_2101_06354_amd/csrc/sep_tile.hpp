@@ -14,6 +14,7 @@
 // relative to local deviations, not to the magnitude of u.
 #pragma once
 
+#include "ssim_epilogue.hpp"
 #include "ssimx_internal.hpp"
 
 namespace ssimx {
@@ -105,6 +106,28 @@ __device__ __forceinline__ TileStats sep_tile_column(const Geom& g, const float*
   st.var_u = su - mu * mu;
   st.var_v = sv - mv * mv;
   return st;
+}
+
+// Forward tile of the generic separable kernel: map store and this thread's
+// share of the tile's pooled sum.  `lds` holds sep_tile_lds_floats() floats.
+template <typename T>
+__device__ __forceinline__ float sep_fwd_tile(const SepArgs& a, int frame, int tile, float* lds) {
+  const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
+  const int ox0 = txi * a.g.TW, oy0 = tyi * a.g.TH;
+  sep_tile_rows<T>(a.g, a.taps, a.x, a.y, frame, ox0, oy0, lds);
+  float acc = 0.f;
+  for (int idx = threadIdx.x; idx < a.g.TH * a.g.TW; idx += BLOCK) {
+    const int i = idx / a.g.TW, j = idx - i * a.g.TW;
+    const int oi = oy0 + i, oj = ox0 + j;
+    if (oi >= a.g.Ho || oj >= a.g.Wo) continue;
+    const TileStats st = sep_tile_column(a.g, a.taps, lds, i, j);
+    const SsimTerms t = ssim_terms_uv(st.mean_u, st.mean_v, st.var_u, st.var_v, a.C1, a.C2);
+    const float val = ssim_value(t, a.mode);
+    if (a.map) a.map[(int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + oj] = val;
+    acc += val;
+  }
+  __syncthreads();  // the caller may reuse lds for the next tile
+  return acc;
 }
 
 }  // namespace ssimx

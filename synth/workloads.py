@@ -111,19 +111,32 @@ def config2(frames: int = 32, h: int = 2160, w: int = 3840, stream: int = 0):
     return ref, dis
 
 
-def config3(pairs: int = 256, ladder=LADDER, stream: int = 0):
-    """Returns a list of dicts {ref, dis, window, k, stride}."""
+def _config3_pair(args):
+    seed, w, h, q, gauss, stride = args
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ref = _round_clip(smooth_field(rng, h, w, 16, 235), 0, 255, np.uint8)
+    dis = dct_quantise(ref, q)
+    return {"ref": ref, "dis": dis, "window": "gaussian" if gauss else "box",
+            "k": 11 if gauss else 8, "stride": stride}
+
+
+def config3(pairs: int = 256, ladder=LADDER, stream: int = 0, workers: int = 0):
+    """Returns a list of dicts {ref, dis, window, k, stride}.  `workers` > 1
+    generates the pairs in a process pool (same result)."""
     rng = rng_for(3, stream)
-    out = []
-    for _ in range(pairs):
+    jobs = []
+    seeds = np.random.SeedSequence([ROOT_SEED, 3, stream, 1]).spawn(pairs)
+    for i in range(pairs):
         w, h = ladder[int(rng.integers(0, len(ladder)))]
-        ref = _round_clip(smooth_field(rng, h, w, 16, 235), 0, 255, np.uint8)
-        dis = dct_quantise(ref, int(rng.integers(8, 65)))
+        q = int(rng.integers(8, 65))
         gauss = bool(rng.integers(0, 2))
         stride = int((1, 4)[int(rng.integers(0, 2))])
-        out.append({"ref": ref, "dis": dis, "window": "gaussian" if gauss else "box",
-                    "k": 11 if gauss else 8, "stride": stride})
-    return out
+        jobs.append((seeds[i], w, h, q, gauss, stride))
+    if workers and workers > 1:
+        import concurrent.futures as cf
+        with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(_config3_pair, jobs, chunksize=4))
+    return [_config3_pair(j) for j in jobs]
 
 
 def config4(batch: int = 16, h: int = 512, w: int = 512, stream: int = 0):

@@ -137,3 +137,19 @@ def test_workspace_size_and_tile_api(L):
     assert L.lib.ssimx_set_tile_override(10**6) == L.EINVAL
     assert L.lib.ssimx_strerror(L.EWORKSPACE) == b"workspace missing or too small"
     assert L.lib.ssimx_version() >= 100
+
+
+def test_plan_create_validates_before_allocating(L):
+    pair = L.Pair()
+    pair.ref = L.Image(12345, L.U8, 64, 64, 64, 4096)
+    pair.dis = L.Image(12345, L.U8, 64, 64, 64, 4096)
+    pair.p = _params(L, k=10)  # even Gaussian window
+    arr = (L.Pair * 1)(pair)
+    h = ctypes.c_void_p()
+    assert L.lib.ssimx_plan_create(arr, 1, None, ctypes.byref(h)) == L.EINVAL
+    pair.p = _params(L)
+    pair.dis = L.Image(12345, L.U16, 64, 64, 64, 4096)
+    arr = (L.Pair * 1)(pair)
+    assert L.lib.ssimx_plan_create(arr, 1, None, ctypes.byref(h)) == L.EINVAL
+    assert L.lib.ssimx_plan_create(arr, 0, None, ctypes.byref(h)) == L.EINVAL
+    assert L.lib.ssimx_plan_destroy(None) == L.EINVAL
