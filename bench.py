@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the secondary workloads (box / integral image / stride 4 / MS-SSIM 4K / ragged / loss)")
     ap.add_argument("--fwd-only", action="store_true", help="time the forward alone (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES (counter calibration) and exit")
@@ -125,6 +126,7 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    log("generating 64 x 1080p u8 pairs")
     x, y = synth.config1(frames=a.frames)
     B, H, W = x.shape
     xt = torch.from_numpy(x).to(dev)
@@ -168,6 +170,7 @@ def main():
                                            gscore.data_ptr(), grad.data_ptr(), W, H * W, ws_b.data_ptr(),
                                            ws_b.numel(), stream.cuda_stream), "ssim_pooled_backward")
 
+    log("warm-up and timed steps")
     for _ in range(a.warmup):
         fwd()
         if with_bwd:
@@ -227,9 +230,121 @@ def main():
         "hbm_roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
     }
+    if not a.no_variants:
+        res["variants"] = variants(P, x, y, xt, yt, dev, stream)
     if not a.no_cpu_baseline:
+        log("CPU baseline (FP64 oracle)")
         res["cpu_baseline"] = cpu_baseline(x, y, 1, with_bwd)
     print(json.dumps(res))
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _time(fn, reps=10, warmup=2, stream=None):
+    """Mean device time (ms) of fn() over reps calls, HIP events on `stream`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def variants(P, x, y, xt, yt, dev, stream):
+    """Secondary workloads, each timed on device-resident inputs."""
+    import numpy as np
+    import torch
+
+    import synth
+    out = {}
+    B, H, W = x.shape
+    px1 = B * H * W
+
+    def rec(name, ms, px, note):
+        out[name] = {"ms": ms, "mpixel_s": px / (ms * 1e-3) / 1e6, "note": note}
+
+    # 64 x 1080p u8: other windows / algorithms / strides (map + score)
+    for name, cfg, note in [
+        ("c1_gauss11_pooled_only", P.SSIMConfig(), "Gaussian 11x11, score only (no map store)"),
+        ("c1_box8_tile_sums", P.SSIMConfig(window="box", k=8), "8x8 box, exact tile-local integer sums, map+score"),
+        ("c1_box8_integral_image", P.SSIMConfig(window="box", k=8, algo="integral"),
+         "8x8 box via the five uint32 integral images in HBM (the paper's method), map+score"),
+        ("c1_gauss11_stride4", P.SSIMConfig(stride=4), "Gaussian 11x11, stride 4, map+score"),
+        ("c1_box8_stride4", P.SSIMConfig(window="box", k=8, stride=4), "8x8 box, stride 4, map+score"),
+    ]:
+        if name.endswith("pooled_only"):
+            ms = _time(lambda c=cfg: P.ssim(xt, yt, c), stream=stream)
+        else:
+            ms = _time(lambda c=cfg: P.ssim(xt, yt, c, return_map=True), stream=stream)
+        rec(name, ms, px1, note)
+        log(f"{name}: {ms:.3f} ms")
+    # one batched launch vs one launch per frame (same frames, Gaussian map+score)
+    cfg = P.SSIMConfig()
+    ms_b = _time(lambda: P.ssim(xt, yt, cfg, return_map=True), stream=stream)
+    ms_f = _time(lambda: [P.ssim(xt[f], yt[f], cfg, return_map=True) for f in range(B)], reps=3, stream=stream)
+    rec("c1_batched_launch", ms_b, px1, "64 frames in one launch")
+    rec("c1_per_frame_launches", ms_f, px1, "64 single-frame launches")
+
+    # MS-SSIM, 32 x 3840x2160 10-bit, 5 scales
+    log("generating 32 x 4K u16 pairs")
+    r2, d2 = synth.config2()
+    x2 = torch.from_numpy(r2).to(dev)
+    y2 = torch.from_numpy(d2).to(dev)
+    del r2, d2
+    c2 = P.SSIMConfig(L=1023.0)
+    ms = _time(lambda: P.ms_ssim(x2, y2, c2), reps=5, stream=stream)
+    rec("c2_msssim_4k_u16_fwd", ms, x2.numel(), "32x2160x3840 u16, 5 scales, score per frame")
+    ms = _time(lambda: P.ms_ssim_backward(x2[:8], y2[:8], torch.ones(8, device=dev), c2), reps=3,
+               stream=stream)
+    rec("c2_msssim_4k_u16_bwd_8frames", ms, x2[:8].numel(), "adjoint of MS-SSIM on 8 of the frames")
+    del x2, y2
+
+    # ragged batch: 256 pairs, one graph launch vs per-pair launches
+    log("generating 256 ragged pairs")
+    pairs = synth.config3(workers=8)
+    items = [{"ref": torch.from_numpy(p["ref"]).to(dev), "dis": torch.from_numpy(p["dis"]).to(dev),
+              "cfg": P.SSIMConfig(window=p["window"], k=p["k"], stride=p["stride"])} for p in pairs]
+    tuned = set()
+    for it in items:  # tile shapes from the autotuner, before the plan is built
+        h, w = it["ref"].shape
+        key = (it["cfg"].window, it["cfg"].k, it["cfg"].stride, h, w)
+        if key not in tuned:
+            P.autotune(it["cfg"], torch.uint8, h, w, 1)
+            tuned.add(key)
+    log(f"autotuned {len(tuned)} shapes; building the plan")
+    plan = P.BatchPlan(items)
+    pxr = sum(int(it["ref"].numel()) for it in items)
+    sc = torch.empty(len(items), dtype=torch.float32, device=dev)
+    ms_g = _time(lambda: plan.run(sc), stream=stream)
+    ms_u = _time(lambda: plan.run_unbatched(sc), stream=stream)
+    ni, nb = plan.info()
+    rec("c3_ragged_graph", ms_g, pxr, f"256 ladder pairs, one hipGraph launch ({ni} tiles, {nb} blocks)")
+    rec("c3_ragged_per_pair", ms_u, pxr, "same pairs, per-pair kernel launches")
+    plan.close()
+    del items
+
+    log("differentiable loss workload")
+    # differentiable loss: 16 x 3 x 512 x 512 RGB, 1 - MS-SSIM (3 scales) forward + backward
+    r4, d4 = synth.config4()
+    rt = torch.from_numpy(r4).to(dev)
+    dt = torch.from_numpy(d4).to(dev).requires_grad_(True)
+    c4 = P.SSIMConfig(L=1.0)
+
+    def step():
+        dt.grad = None
+        loss = P.autograd.ms_ssim_loss_rgb(rt, dt, c4, n_scales=3, renorm=True)
+        loss.backward()
+    ms = _time(step, stream=stream)
+    rec("c4_msssim_loss_fwd_bwd", ms, 16 * 512 * 512, "16x3x512x512 f32 RGB, BT.601 luma, 3 scales, fwd+bwd")
+    return out
 
 
 if __name__ == "__main__":
