@@ -50,8 +50,8 @@ struct CoefArgs {
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void bwd_coef_kernel(CoefArgs a) {
   extern __shared__ float lds[];
-  const int frame = blockIdx.y;
-  const int tile = blockIdx.x;
+  int tile, frame;
+  xcd_tile(tile, frame);
   const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
   const int ox0 = txi * a.g.TW, oy0 = tyi * a.g.TH;
   sep_tile_rows<T>(a.g, a.taps, a.x, a.y, frame, ox0, oy0, lds);
@@ -107,8 +107,8 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void bwd_scatter_kernel(ScatArgs a) {
   extern __shared__ float lds[];
   const Geom& g = a.g;
-  const int frame = blockIdx.y;
-  const int tile = blockIdx.x;
+  int tile, frame;
+  xcd_tile(tile, frame);
   const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
   const int qx0 = txi * a.QW, qy0 = tyi * a.QH;
   const int k = g.k, s = g.s;

@@ -36,10 +36,12 @@ template <int K, typename T, int EPI>
 __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel(FastArgs a) {
   __shared__ __align__(16) float smem[fast_smem_floats<K>()];
   __shared__ float red[kNT / 64];
-  const float acc = fast_stats_tile<K, T, EPI>(a, blockIdx.y, blockIdx.x, smem);
+  int tile, frame;
+  xcd_tile(tile, frame);
+  const float acc = fast_stats_tile<K, T, EPI>(a, frame, tile, smem);
   if constexpr (EPI == 0) {
     const float tot = block_sum<kNT>(acc, red);
-    if (threadIdx.x == 0) a.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (threadIdx.x == 0) a.partial[(int64_t)frame * gridDim.x + tile] = tot;
   }
 }
 
@@ -171,8 +173,8 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   __shared__ __align__(16) float C[kNM * S::CH * S::IWP];
   __shared__ __align__(16) float HM[kNM * S::PL];
   constexpr int PL = S::PL;
-  const int frame = blockIdx.y;
-  const int tile = blockIdx.x;
+  int tile, frame;
+  xcd_tile(tile, frame);
   const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
   const int qx0 = __builtin_amdgcn_readfirstlane(txi * kTW), qy0 = __builtin_amdgcn_readfirstlane(tyi * a.QH);
   const int c0 = qx0 - S::HALO - S::LP;

@@ -21,9 +21,11 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void box_fwd_kernel(BoxArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* red = (float*)(lds_raw + box_tile_lds_bytes(a.g, sizeof(typename BoxAcc<T>::type)));
-  const float acc = box_fwd_tile<T>(a, blockIdx.y, blockIdx.x, lds_raw);
+  int tile, frame;
+  xcd_tile(tile, frame);
+  const float acc = box_fwd_tile<T>(a, frame, tile, lds_raw);
   const float tot = block_sum<BLOCK>(acc, red);
-  if (threadIdx.x == 0 && a.partial) a.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+  if (threadIdx.x == 0 && a.partial) a.partial[(int64_t)frame * gridDim.x + tile] = tot;
 }
 
 static size_t box_lds_bytes(const Geom& g, int dtype) {

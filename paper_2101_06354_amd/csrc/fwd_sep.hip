@@ -31,9 +31,11 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void sep_fwd_kernel(SepArgs a) {
   extern __shared__ float lds[];
   float* red = lds + sep_tile_lds_floats(a.g.IH, a.g.IW, a.g.TW);
-  const float acc = sep_fwd_tile<T>(a, blockIdx.y, blockIdx.x, lds);
+  int tile, frame;
+  xcd_tile(tile, frame);
+  const float acc = sep_fwd_tile<T>(a, frame, tile, lds);
   const float tot = block_sum<BLOCK>(acc, red);
-  if (threadIdx.x == 0) a.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+  if (threadIdx.x == 0) a.partial[(int64_t)frame * gridDim.x + tile] = tot;
 }
 
 int launch_sep_fwd(int dtype, const SepArgs& a, int batch, size_t lds, hipStream_t st) {

@@ -8,9 +8,13 @@
 //   2 sigma_xy           = (var_u - var_v) / 2
 //   sigma_x^2+sigma_y^2  = (var_u + var_v) / 2
 // so the numerator and denominator of l (and of cs) differ by exactly
-// mu_v^2 (and var_v).  When x == y, mu_v = var_v = 0 and both are formed by the
-// same operations, so Q == 1.0f exactly; swapping x and y only flips the sign
-// of v, so Q is bitwise symmetric.
+// mu_v^2 (and var_v).  Writing D1 = B1 - A1 and D2 = B2 - A2,
+//   Q = A1 A2 / (B1 B2) = 1 - (D1 A2 + D2 B1) / (B1 B2),   cs = 1 - D2 / B2,
+// so the division only scales a correction term: a reciprocal estimate
+// (about 1 ulp) then costs at most a few ulp of 1 - Q, and when x == y the
+// correction is exactly 0 (D1 = D2 = 0), so Q == 1.0f exactly.  Swapping x and
+// y only flips the sign of v, which D1, D2, A and B do not see, so Q is
+// bitwise symmetric.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +23,7 @@ namespace ssimx {
 
 struct SsimTerms {
   float A1, B1, A2, B2;
+  float D1, D2;  // B1 - A1 and B2 - A2, formed without cancellation
 };
 
 __device__ __forceinline__ SsimTerms ssim_terms_uv(float mean_u, float mean_v, float var_u, float var_v, float C1,
@@ -30,13 +35,16 @@ __device__ __forceinline__ SsimTerms ssim_terms_uv(float mean_u, float mean_v, f
   t.B1 = (P + R) + C1;
   t.A2 = 0.5f * (var_u - var_v) + C2;
   t.B2 = 0.5f * (var_u + var_v) + C2;
+  t.D1 = 2.f * R;
+  t.D2 = var_v;
   return t;
 }
 
 // mode 0: Q = l*cs ; mode 1: cs
 __device__ __forceinline__ float ssim_value(const SsimTerms& t, int mode) {
-  if (mode == 1) return t.A2 / t.B2;
-  return (t.A1 * t.A2) / (t.B1 * t.B2);
+  if (mode == 1) return fmaf(-t.D2, __builtin_amdgcn_rcpf(t.B2), 1.f);
+  const float n = fmaf(t.D1, t.A2, t.D2 * t.B1);
+  return fmaf(-n, __builtin_amdgcn_rcpf(t.B1 * t.B2), 1.f);
 }
 
 // Same terms from exact integer window sums of a k x k rectangular window
@@ -52,6 +60,9 @@ __device__ __forceinline__ SsimTerms ssim_terms_box(int64_t sx, int64_t sy, int6
   t.B1 = (float)(sx * sx + sy * sy) / k4 + C1;
   t.A2 = (float)(2 * nxy) / k4 + C2;
   t.B2 = (float)(nxx + nyy) / k4 + C2;
+  const int64_t dxy = sx - sy;
+  t.D1 = (float)(dxy * dxy) / k4;                // (mu_x - mu_y)^2
+  t.D2 = (float)(nxx + nyy - 2 * nxy) / k4;      // variance of x - y
   return t;
 }
 

@@ -94,6 +94,22 @@ __device__ __forceinline__ float block_sum(float v, float* lds_scratch) {
 }
 
 // ---------------------------------------------------------------- arguments
+// Workgroups of a launch are handed to the 8 XCDs round-robin in dispatch
+// order, and each XCD has its own L2.  The i-th workgroup that lands on XCD x
+// takes logical index x * per + i instead (XCDs 0 .. rem-1 take per + 1), so
+// each XCD walks a contiguous range of tiles and neighbouring tiles, which
+// read the same halo cache lines, meet in the same L2.  Returns (tile, frame)
+// for a (tiles, frames) grid; the mapping is a bijection on [0, n).
+__device__ __forceinline__ void xcd_tile(int& tile, int& frame) {
+  const int nx = gridDim.x;
+  const int n = nx * gridDim.y;
+  const int b = blockIdx.x + nx * blockIdx.y;
+  const int per = n >> 3, rem = n & 7, x = b & 7, i = b >> 3;
+  const int l = x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+  frame = l / nx;
+  tile = l - frame * nx;
+}
+
 struct PlaneArg {
   const void* data;
   int64_t pitch, bstride;
