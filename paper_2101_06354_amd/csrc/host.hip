@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "box_band.hpp"
 #include "fast_tile.hpp"
 #include "host_common.hpp"
 #include "ssimx_internal.hpp"
@@ -123,6 +124,26 @@ Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx) {
   return g;
 }
 
+// Input rows per tile of the 8-bit box band kernel, for the same index.
+static const int kBandRows[] = {128, 256, 64, 512, 32, 1024};
+
+Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx) {
+  Geom g = geom_with(p, W, H, 256, 1);
+  const int rows = kBandRows[(tile_idx >= 0 && tile_idx < num_tile_cfgs()) ? tile_idx : 0];
+  g.TW = 256;
+  g.TH = std::max(1, rows / p->stride);
+  g.tiles_x = (g.Wo + 255) / 256;
+  g.tiles_y = (g.Ho + g.TH - 1) / g.TH;
+  return g;
+}
+
+// 8-bit rectangular windows with valid borders go to the band kernel when its
+// compile-time window/stride set covers them and the planes allow dword loads.
+bool band_eligible(const ssimx_params* p, int dtype) {
+  return choose_path(p, dtype) == Path::kBox && dtype == SSIMX_U8 && p->padding == SSIMX_PAD_VALID &&
+         box_band_supported(p->k, p->stride);
+}
+
 // The fast kernels share one centring value among 4 adjacent windows; it sits
 // at window offsets k/2-2 .. k/2+1.  Their weights bound the rounding error
 // (sum g (z - t)^2 <= V (1 + 1/g_t)), so windows whose taps there are small
@@ -188,6 +209,10 @@ int max_partials(const ssimx_params* p, int dtype, int W, int H) {
     if (use_fast(p, dtype)) {
       const Geom f = fast_geom(p, W, H, i);
       m = std::max(m, f.tiles_x * f.tiles_y);
+    }
+    if (band_eligible(p, dtype)) {
+      const Geom b = band_geom(p, W, H, i);
+      m = std::max(m, b.tiles_x * b.tiles_y);
     }
   }
   return m;
@@ -308,6 +333,23 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
     a.partial = partial;
     gaussian_taps_f32(p->window, p->k, p->sigma, a.taps);
     err = launch_sep_fwd(dtype, a, batch, sep_lds_bytes(g), st);
+    tiles = g.tiles_x * g.tiles_y;
+  } else if (path == Path::kBox && mode != 2 && band_eligible(p, dtype) &&
+             aligned_vec(x.data, x.pitch, x.bstride, 1) && aligned_vec(y.data, y.pitch, y.bstride, 1)) {
+    BandArgs a{};
+    g = band_geom(p, W, H, tile_idx);
+    a.x = x;
+    a.y = y;
+    a.g = g;
+    a.C1 = C1;
+    a.C2 = C2;
+    a.inv_k4 = (float)(1.0 / ((double)p->k * p->k * p->k * p->k));
+    a.mode = mode;
+    a.map = map;
+    a.map_pitch = map_pitch;
+    a.map_bstride = map_bstride;
+    a.partial = partial;
+    err = launch_box_band(a, batch, st);
     tiles = g.tiles_x * g.tiles_y;
   } else if (path == Path::kBox) {
     BoxArgs a{};

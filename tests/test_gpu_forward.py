@@ -264,3 +264,83 @@ def test_band_kernel_other_dtypes(P, dev, dtype):
     ref = O.ssim_map(xo, yo, oparams(cfg))["map"]
     assert np.abs(m[0].cpu().numpy() - ref).max() <= MAP_TOL
     assert abs(float(s[0]) - O.mean_pool(ref)) <= SCORE_TOL
+
+
+# 8-bit rectangular windows with valid borders run on the band kernel for these
+# window/stride pairs (the others on the generic tile kernel).
+BAND_CASES = [(k, 1) for k in range(2, 17)] + [(k, 2) for k in (2, 4, 6, 8, 16)] + [(k, 4) for k in (4, 8, 12, 16)]
+
+
+def _band_frames(k, stride, h, w):
+    rng = np.random.default_rng(1000 + 17 * k + stride)
+    x = np.empty((2, h, w), np.uint8)
+    y = np.empty((2, h, w), np.uint8)
+    for f in range(2):
+        x[f] = synth.smooth_field(rng, h, w, 16, 235).round().astype(np.uint8)
+        y[f] = np.clip(x[f] + rng.normal(0, 14, (h, w)).round(), 0, 255).astype(np.uint8)
+    # saturated patches: the largest window sums (x = 255, y = 0) and a 0/255 checkerboard
+    x[0, :40, :70] = 255
+    y[0, :40, :70] = 0
+    yy, xx = np.mgrid[0:50, 0:90]
+    x[1, -50:, -90:] = ((yy + xx) % 2) * 255
+    y[1, -50:, -90:] = ((yy // 2 + xx // 3) % 2) * 255
+    return x, y
+
+
+@pytest.mark.parametrize("k,stride", BAND_CASES)
+def test_box_band_kernel_windows_and_strides(P, dev, k, stride):
+    # several 256-column tiles and row tiles, ragged tails, two frames
+    h, w = (300, 600) if stride == 1 else (290, 1100)
+    x, y = _band_frames(k, stride, h, w)
+    cfg = P.SSIMConfig(window="box", k=k, stride=stride)
+    s, m = P.ssim(to_dev(x, dev), to_dev(y, dev), cfg, return_map=True)
+    s, m = s.cpu().numpy().astype(np.float64), m.cpu().numpy().astype(np.float64)
+    for f in range(2):
+        ref = O.ssim_map(x[f], y[f], oparams(cfg))["map"]
+        assert m[f].shape == ref.shape
+        err = np.abs(m[f] - ref).max()
+        assert err <= MAP_TOL, f"frame {f} map error {err}"
+        assert abs(s[f] - O.mean_pool(ref)) <= SCORE_TOL
+
+
+@pytest.mark.parametrize("k,stride", [(2, 1), (5, 1), (8, 1), (16, 1), (6, 2), (8, 4), (16, 4)])
+def test_box_band_identity_and_symmetry(P, dev, k, stride):
+    x, y = _band_frames(k, stride, 270, 700)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    cfg = P.SSIMConfig(window="box", k=k, stride=stride)
+    _, mxx = P.ssim(xt, xt, cfg, return_map=True)
+    assert bool(torch.all(mxx == 1.0))
+    _, mxy = P.ssim(xt, yt, cfg, return_map=True)
+    _, myx = P.ssim(yt, xt, cfg, return_map=True)
+    assert torch.equal(mxy, myx)
+    assert bool(torch.all(mxy.abs() <= 1.0))
+
+
+@pytest.mark.parametrize("stride", [1, 4])
+def test_box_band_tile_configs_agree(P, dev, stride):
+    x, y = synth.config1(frames=2, h=333, w=1100)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    cfg = P.SSIMConfig(window="box", k=8, stride=stride)
+    maps, scores = [], []
+    try:
+        for t in range(P.num_tile_configs()):
+            P.set_tile_override(t)
+            s, m = P.ssim(xt, yt, cfg, return_map=True)
+            maps.append(m)
+            scores.append(s)
+    finally:
+        P.set_tile_override(-1)
+    for m in maps[1:]:
+        assert torch.equal(m, maps[0])
+    for s in scores[1:]:
+        assert torch.allclose(s, scores[0], rtol=0, atol=2e-7)
+    # odd byte offset: the generic tile kernel takes the call; both match the oracle
+    bx = torch.zeros((2, 333, 1102), dtype=torch.uint8, device=dev)
+    by = torch.zeros_like(bx)
+    bx[:, :, 1:1101] = xt
+    by[:, :, 1:1101] = yt
+    _, m2 = P.ssim(bx[:, :, 1:1101], by[:, :, 1:1101], cfg, return_map=True)
+    for f in range(2):
+        ref = O.ssim_map(x[f], y[f], oparams(cfg))["map"]
+        assert np.abs(maps[0][f].cpu().numpy() - ref).max() <= MAP_TOL
+        assert np.abs(m2[f].cpu().numpy() - ref).max() <= MAP_TOL
