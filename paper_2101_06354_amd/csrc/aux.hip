@@ -1,4 +1,5 @@
 // Pooling finalisation, 2x2 pyramid and the MS-SSIM product.
+#include "launch.hpp"
 #include "host_common.hpp"
 #include "ssimx_internal.hpp"
 

@@ -20,6 +20,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "launch.hpp"
 #include "box_tile.hpp"
 #include "fast_tile_body.hpp"
 #include "host_common.hpp"

@@ -1,4 +1,5 @@
 // Rectangular-window band kernels on 8-bit planes (see box_band.hpp).
+#include "launch.hpp"
 #include "box_band.hpp"
 
 namespace ssimx {

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 
+#include "launch.hpp"
 #include "fast_tile.hpp"
 #include "host_common.hpp"
 #include "sep_tile.hpp"

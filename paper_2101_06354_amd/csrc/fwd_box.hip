@@ -11,6 +11,7 @@
 // The statistics then follow eqs. mean_from_sum .. corr_from_sum with the
 // variance numerators k^2 S2 - S1^2 formed exactly in int64 and rounded to
 // float once.
+#include "launch.hpp"
 #include "box_tile.hpp"
 #include "ssim_epilogue.hpp"
 #include "ssimx_internal.hpp"
@@ -123,7 +124,9 @@ __global__ __launch_bounds__(BLOCK) void sat_cols_kernel(uint32_t* sat, int W, i
   }
 }
 
-int launch_sat(int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, uint32_t* sat, hipStream_t st) {
+// Row scan then column scan (any width); the group-scan build in sat.hip
+// takes frames up to 8192 columns.
+int launch_sat_rowcol(int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, uint32_t* sat, hipStream_t st) {
   dim3 g1(H + 1, batch);
   if (dtype == SSIMX_U8)
     hipLaunchKernelGGL(sat_rows_kernel<uint8_t>, g1, dim3(BLOCK), 0, st, x, y, W, H, sat, batch);
@@ -176,8 +179,9 @@ __global__ __launch_bounds__(BLOCK) void sat_ssim_kernel(const uint32_t* sat, Ge
   if (threadIdx.x == 0 && partial) partial[(int64_t)frame * gridDim.x + blockIdx.x] = tot;
 }
 
-int launch_sat_ssim(const uint32_t* sat, const Geom& g, int batch, float C1, float C2, int mode, float* map,
-                    int64_t map_pitch, int64_t map_bstride, float* partial, int32_t* sums, hipStream_t st) {
+int launch_sat_ssim_generic(const uint32_t* sat, const Geom& g, int batch, float C1, float C2, int mode, float* map,
+                            int64_t map_pitch, int64_t map_bstride, float* partial, int32_t* sums,
+                            hipStream_t st) {
   const int n = g.Ho * g.Wo;
   dim3 grid((n + BLOCK - 1) / BLOCK, batch);
   hipLaunchKernelGGL(sat_ssim_kernel, grid, dim3(BLOCK), 0, st, sat, g, batch, C1, C2, mode, map, map_pitch,

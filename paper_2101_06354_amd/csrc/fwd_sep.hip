@@ -17,6 +17,7 @@
 // Every rounding error is then relative to local deviations, not to |u|, so
 // flat regions far from any global shift stay exact.  For integer planes the
 // row-pass differences and squares are exact integers in float32.
+#include "launch.hpp"
 #include "sep_tile.hpp"
 #include "ssim_epilogue.hpp"
 #include "ssimx_internal.hpp"

@@ -7,8 +7,10 @@
 #include <algorithm>
 #include <vector>
 
+#include "launch.hpp"
 #include "box_band.hpp"
 #include "fast_tile.hpp"
+#include "strided_tile.hpp"
 #include "host_common.hpp"
 #include "ssimx_internal.hpp"
 
@@ -137,6 +139,27 @@ Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx) {
   return g;
 }
 
+// Map rows per tile of the strided Gaussian kernels, for the same index
+// (rounded to whole chunks).
+static const int kStridedRows[] = {32, 64, 16, 128, 8, 256};
+
+Geom strided_geom(const ssimx_params* p, int W, int H, int tile_idx) {
+  Geom g = geom_with(p, W, H, strided::kTWo, 1);
+  const int cho = strided::kRows / p->stride;
+  const int rows = kStridedRows[(tile_idx >= 0 && tile_idx < num_tile_cfgs()) ? tile_idx : 0];
+  g.TW = strided::kTWo;
+  g.TH = std::max(1, rows / cho) * cho;
+  g.tiles_x = (g.Wo + strided::kTWo - 1) / strided::kTWo;
+  g.tiles_y = (g.Ho + g.TH - 1) / g.TH;
+  return g;
+}
+
+// Windows on the float path with stride 2..4 and K in {7, 9, 11, 13}: each
+// window centres on its own middle element, so any tap profile is accurate.
+bool use_strided(const ssimx_params* p, int dtype) {
+  return choose_path(p, dtype) == Path::kSep && strided_supported(p->k, p->stride) && p->k > p->stride;
+}
+
 // 8-bit rectangular windows with valid borders go to the band kernel when its
 // compile-time window/stride set covers them and the planes allow dword loads.
 bool band_eligible(const ssimx_params* p, int dtype) {
@@ -201,7 +224,12 @@ int max_partials(const ssimx_params* p, int dtype, int W, int H) {
   const Path path = choose_path(p, dtype);
   int Wo, Ho;
   map_dims(p, W, H, Wo, Ho);
-  if (path == Path::kSat) return (Wo * Ho + BLOCK - 1) / BLOCK;
+  if (path == Path::kSat) {
+    int m = (Wo * Ho + BLOCK - 1) / BLOCK;
+    const Geom g = make_geom_path(p, dtype, W, H, 0);
+    for (int i = 0; i < num_tile_cfgs(); ++i) m = std::max(m, sat_ssim_tiles(g, dtype, 0, i));
+    return m;
+  }
   int m = 1;
   for (int i = 0; i < num_tile_cfgs(); ++i) {
     const Geom g = make_geom_path(p, dtype, W, H, i);
@@ -212,6 +240,10 @@ int max_partials(const ssimx_params* p, int dtype, int W, int H) {
     }
     if (band_eligible(p, dtype)) {
       const Geom b = band_geom(p, W, H, i);
+      m = std::max(m, b.tiles_x * b.tiles_y);
+    }
+    if (use_strided(p, dtype)) {
+      const Geom b = strided_geom(p, W, H, i);
       m = std::max(m, b.tiles_x * b.tiles_y);
     }
   }
@@ -319,6 +351,18 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
     a.batch = batch;
     err = launch_fast_stats(dtype, 0, a, batch, st);
     tiles = g.tiles_x * g.tiles_y;
+  } else if (use_strided(p, dtype)) {
+    FastArgs a{};
+    g = strided_geom(p, W, H, tile_idx);
+    fill_fast_common(a, p, dtype, x, y, g);
+    a.mode = mode;
+    a.map = map;
+    a.map_pitch = map_pitch;
+    a.map_bstride = map_bstride;
+    a.partial = partial;
+    a.batch = batch;
+    err = launch_strided(dtype, a, batch, st);
+    tiles = g.tiles_x * g.tiles_y;
   } else if (path == Path::kSep) {
     SepArgs a{};
     a.x = x;
@@ -369,8 +413,9 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
   } else {
     err = launch_sat(dtype, x, y, W, H, batch, sat, st);
     if (err) return hip_status(err);
-    err = launch_sat_ssim(sat, g, batch, C1, C2, mode, map, map_pitch, map_bstride, partial, nullptr, st);
-    tiles = (g.Wo * g.Ho + BLOCK - 1) / BLOCK;
+    err = launch_sat_ssim(sat, g, dtype, batch, C1, C2, mode, map, map_pitch, map_bstride, partial, nullptr, tile_idx,
+                          st);
+    tiles = sat_ssim_tiles(g, dtype, mode, tile_idx);
   }
   if (err) return hip_status(err);
   if (out) {
@@ -514,7 +559,8 @@ ssimx_status ssimx_box_sums(int k, int stride, int algo, const ssimx_image* ref,
     if (!ws || ws_bytes < need) return SSIMX_EWORKSPACE;
     const Geom g = make_geom_path(&p, ref->dtype, ref->width, ref->height, 0);
     int err = launch_sat(ref->dtype, x, y, ref->width, ref->height, batch, (uint32_t*)ws, st);
-    if (!err) err = launch_sat_ssim((uint32_t*)ws, g, batch, 0.f, 0.f, 2, nullptr, 0, 0, nullptr, sums_out, st);
+    if (!err)
+      err = launch_sat_ssim((uint32_t*)ws, g, ref->dtype, batch, 0.f, 0.f, 2, nullptr, 0, 0, nullptr, sums_out, 0, st);
     return hip_status(err);
   }
   BoxArgs a{};

@@ -4,6 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "launch.hpp"
 #include "ssimx_internal.hpp"
 
 namespace ssimx {

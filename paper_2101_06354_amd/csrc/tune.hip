@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "launch.hpp"
 #include "host_common.hpp"
 #include "ssimx_internal.hpp"
 

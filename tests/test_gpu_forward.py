@@ -344,3 +344,87 @@ def test_box_band_tile_configs_agree(P, dev, stride):
         ref = O.ssim_map(x[f], y[f], oparams(cfg))["map"]
         assert np.abs(maps[0][f].cpu().numpy() - ref).max() <= MAP_TOL
         assert np.abs(m2[f].cpu().numpy() - ref).max() <= MAP_TOL
+
+
+@pytest.mark.parametrize("dtype,h,w", [("u8", 70, 5000), ("u16", 45, 4700), ("u8", 37, 8300), ("u8", 333, 97)])
+def test_integral_images_group_scan_shapes(P, dev, dtype, h, w):
+    # row groups, several 64-lane waves per row, 16 columns per thread, and
+    # the row/column-scan fallback beyond 8192 columns
+    rng = np.random.default_rng(h + w)
+    hi = 256 if dtype == "u8" else 1024
+    npt = np.uint8 if dtype == "u8" else np.uint16
+    x = rng.integers(0, hi, (2, h, w)).astype(npt)
+    y = rng.integers(0, hi, (2, h, w)).astype(npt)
+    got = P.integral_images(to_dev(x, dev), to_dev(y, dev)).cpu().numpy().view(np.uint32)
+    for f in range(2):
+        want = O.integral_images(x[f], y[f])
+        for q in range(5):
+            np.testing.assert_array_equal(got[q, f], want[q])
+
+
+@pytest.mark.parametrize("k,stride", [(5, 1), (8, 1), (16, 1), (8, 2), (8, 4), (7, 3)])
+def test_integral_image_ssim_windows(P, dev, k, stride):
+    h, w = (300, 600) if stride < 4 else (290, 1100)
+    x, y = _band_frames(k, 1, h, w)
+    cfg = P.SSIMConfig(window="box", k=k, stride=stride, algo="integral")
+    s, m = P.ssim(to_dev(x, dev), to_dev(y, dev), cfg, return_map=True)
+    s, m = s.cpu().numpy().astype(np.float64), m.cpu().numpy().astype(np.float64)
+    for f in range(2):
+        ref = O.ssim_map(x[f], y[f], oparams(cfg))["map"]
+        assert np.abs(m[f] - ref).max() <= MAP_TOL
+        assert abs(s[f] - O.mean_pool(ref)) <= SCORE_TOL
+    _, mxx = P.ssim(to_dev(x, dev), to_dev(x, dev), cfg, return_map=True)
+    assert bool(torch.all(mxx == 1.0))
+
+
+@pytest.mark.parametrize("k", [7, 9, 11, 13])
+@pytest.mark.parametrize("stride", [2, 3, 4])
+@pytest.mark.parametrize("padding", ["valid", "reflect", "zero"])
+def test_strided_gaussian_kernel(P, dev, k, stride, padding):
+    # several 64-column tiles and row tiles with ragged tails, two frames
+    h, w = 300, 200 * stride + 37
+    x, y = _band_frames(k, stride, h, w)
+    cfg = P.SSIMConfig(k=k, sigma=1.5 if k == 11 else 0.8 + 0.1 * k, stride=stride, padding=padding)
+    s, m = P.ssim(to_dev(x, dev), to_dev(y, dev), cfg, return_map=True)
+    s, m = s.cpu().numpy().astype(np.float64), m.cpu().numpy().astype(np.float64)
+    for f in range(2):
+        ref = O.ssim_map(x[f], y[f], oparams(cfg))["map"]
+        assert m[f].shape == ref.shape
+        err = np.abs(m[f] - ref).max()
+        assert err <= MAP_TOL, f"frame {f} map error {err}"
+        assert abs(s[f] - O.mean_pool(ref)) <= SCORE_TOL
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32", "bf16"])
+def test_strided_gaussian_dtypes_identity_and_tiles(P, dev, dtype):
+    if dtype == "u16":
+        x, y = synth.config2(frames=2, h=260, w=530)
+        xo, yo, L = x, y, 1023.0
+        xt, yt = to_dev(x, dev), to_dev(y, dev)
+    else:
+        r, d = synth.config4(batch=2, h=260, w=530)
+        x, y, L = r[:, 0], d[:, 0], 1.0
+        xt, yt = to_dev(x, dev), to_dev(y, dev)
+        xo, yo = x, y
+        if dtype == "bf16":
+            xt, yt = xt.bfloat16(), yt.bfloat16()
+            xo, yo = bf16_round(x), bf16_round(y)
+    cfg = P.SSIMConfig(L=L, stride=4)
+    maps = []
+    try:
+        for t in range(P.num_tile_configs()):
+            P.set_tile_override(t)
+            s, m = P.ssim(xt, yt, cfg, return_map=True)
+            maps.append(m)
+    finally:
+        P.set_tile_override(-1)
+    for m in maps[1:]:
+        assert torch.equal(m, maps[0])
+    for f in range(2):
+        ref = O.ssim_map(xo[f], yo[f], oparams(cfg))["map"]
+        assert np.abs(maps[0][f].cpu().numpy() - ref).max() <= MAP_TOL
+    _, mxx = P.ssim(xt, xt, cfg, return_map=True)
+    assert bool(torch.all(mxx == 1.0))
+    _, mxy = P.ssim(xt, yt, cfg, return_map=True)
+    _, myx = P.ssim(yt, xt, cfg, return_map=True)
+    assert torch.equal(mxy, myx)
