@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the secondary workloads (box / integral image / stride 4 / MS-SSIM 4K / ragged / loss)")
     ap.add_argument("--fwd-only", action="store_true", help="time the forward alone (profiling)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated name prefixes: run only these secondary workloads (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
@@ -236,7 +238,7 @@ def main():
                          "frac": achieved_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
     }
     if not a.no_variants:
-        res["variants"] = variants(P, x, y, xt, yt, dev, stream)
+        res["variants"] = variants(P, x, y, xt, yt, dev, stream, [o for o in a.only.split(",") if o])
     if not a.no_cpu_baseline:
         log("CPU baseline (FP64 oracle)")
         res["cpu_baseline"] = cpu_baseline(x, y, 1, with_bwd)
@@ -263,8 +265,9 @@ def _time(fn, reps=10, warmup=2, stream=None):
     return e0.elapsed_time(e1) / reps
 
 
-def variants(P, x, y, xt, yt, dev, stream):
-    """Secondary workloads, each timed on device-resident inputs."""
+def variants(P, x, y, xt, yt, dev, stream, only=()):
+    """Secondary workloads, each timed on device-resident inputs (all, or
+    those whose names start with one of `only`)."""
     import numpy as np
     import torch
 
@@ -276,6 +279,9 @@ def variants(P, x, y, xt, yt, dev, stream):
     def rec(name, ms, px, note):
         out[name] = {"ms": ms, "mpixel_s": px / (ms * 1e-3) / 1e6, "note": note}
 
+    def want(*names):
+        return not only or any(n.startswith(o) for n in names for o in only)
+
     # 64 x 1080p u8: other windows / algorithms / strides (map + score)
     for name, cfg, note in [
         ("c1_gauss11_pooled_only", P.SSIMConfig(), "Gaussian 11x11, score only (no map store)"),
@@ -285,6 +291,8 @@ def variants(P, x, y, xt, yt, dev, stream):
         ("c1_gauss11_stride4", P.SSIMConfig(stride=4), "Gaussian 11x11, stride 4, map+score"),
         ("c1_box8_stride4", P.SSIMConfig(window="box", k=8, stride=4), "8x8 box, stride 4, map+score"),
     ]:
+        if not want(name):
+            continue
         if name.endswith("pooled_only"):
             ms = _time(lambda c=cfg: P.ssim(xt, yt, c), stream=stream)
         else:
@@ -293,10 +301,24 @@ def variants(P, x, y, xt, yt, dev, stream):
         log(f"{name}: {ms:.3f} ms")
     # one batched launch vs one launch per frame (same frames, Gaussian map+score)
     cfg = P.SSIMConfig()
-    ms_b = _time(lambda: P.ssim(xt, yt, cfg, return_map=True), stream=stream)
-    ms_f = _time(lambda: [P.ssim(xt[f], yt[f], cfg, return_map=True) for f in range(B)], reps=3, stream=stream)
-    rec("c1_batched_launch", ms_b, px1, "64 frames in one launch")
-    rec("c1_per_frame_launches", ms_f, px1, "64 single-frame launches")
+    if want("c1_batched_launch", "c1_per_frame_launches"):
+        ms_b = _time(lambda: P.ssim(xt, yt, cfg, return_map=True), stream=stream)
+        ms_f = _time(lambda: [P.ssim(xt[f], yt[f], cfg, return_map=True) for f in range(B)], reps=3, stream=stream)
+        rec("c1_batched_launch", ms_b, px1, "64 frames in one launch")
+        rec("c1_per_frame_launches", ms_f, px1, "64 single-frame launches")
+    if want("c2_"):
+        _variants_c2(P, dev, stream, rec)
+    if want("c3_"):
+        _variants_c3(P, dev, stream, rec)
+    if want("c4_"):
+        _variants_c4(P, dev, stream, rec)
+    return out
+
+
+def _variants_c2(P, dev, stream, rec):
+    import torch
+
+    import synth
 
     # MS-SSIM, 32 x 3840x2160 10-bit, 5 scales
     log("generating 32 x 4K u16 pairs")
@@ -312,6 +334,11 @@ def variants(P, x, y, xt, yt, dev, stream):
     rec("c2_msssim_4k_u16_bwd_8frames", ms, x2[:8].numel(), "adjoint of MS-SSIM on 8 of the frames")
     del x2, y2
 
+
+def _variants_c3(P, dev, stream, rec):
+    import torch
+
+    import synth
     # ragged batch: 256 pairs, one graph launch vs per-pair launches
     log("generating 256 ragged pairs")
     pairs = synth.config3(workers=8)
@@ -336,6 +363,11 @@ def variants(P, x, y, xt, yt, dev, stream):
     plan.close()
     del items
 
+
+def _variants_c4(P, dev, stream, rec):
+    import torch
+
+    import synth
     log("differentiable loss workload")
     # differentiable loss: 16 x 3 x 512 x 512 RGB, 1 - MS-SSIM (3 scales) forward + backward
     r4, d4 = synth.config4()
@@ -349,7 +381,6 @@ def variants(P, x, y, xt, yt, dev, stream):
         loss.backward()
     ms = _time(step, stream=stream)
     rec("c4_msssim_loss_fwd_bwd", ms, 16 * 512 * 512, "16x3x512x512 f32 RGB, BT.601 luma, 3 scales, fwd+bwd")
-    return out
 
 
 if __name__ == "__main__":

@@ -3,10 +3,11 @@
 //
 // ssimx_plan_create builds, on the host,
 //   * one descriptor per pair holding the argument block of the tile body
-//     that serves it (stride-1 band kernel for 11x11 windows with usable
-//     taps, the generic separable kernel otherwise, the integer tile-sum
-//     kernel for rectangular windows on integer planes), with the tile shape
-//     of the autotune cache;
+//     that serves it, with the tile shape of the autotune cache: the stride-1
+//     band body for 11x11 windows with usable taps, the strided band body
+//     for 11x11 windows at stride 4, the byte-dot band body for 8x8
+//     rectangular windows on 8-bit planes at strides 1 and 4, and the
+//     generic separable / integer tile-sum bodies for everything else;
 //   * a flat work list of (pair, tile) items, costliest pairs first;
 // and captures persistent kernel -> per-pair finalise into a graph.  The
 // persistent blocks take the items round-robin, so the list is balanced
@@ -21,36 +22,42 @@
 #include <vector>
 
 #include "launch.hpp"
+#include "box_band.hpp"
 #include "box_tile.hpp"
 #include "fast_tile_body.hpp"
+#include "strided_tile.hpp"
 #include "host_common.hpp"
 #include "sep_tile.hpp"
 #include "ssimx_internal.hpp"
 
 namespace ssimx {
 
-enum PairKind { kKindFast = 0, kKindSep = 1, kKindBox = 2 };
+enum PairKind { kKindFast = 0, kKindSep = 1, kKindBox = 2, kKindStrided4 = 3, kKindBand8s1 = 4, kKindBand8s4 = 5 };
 
 struct PairDesc {
   int kind;
   int tiles;
   int part_off;
   int count;  // map positions of the pair
-  FastArgs fa;
+  FastArgs fa;   // stride-1 and strided band bodies
   SepArgs sa;
   BoxArgs ba;
+  BandArgs bb;
 };
 
 constexpr int kPlanSmemBytes = 48 * 1024;
 constexpr int kPlanSmemFloats = kPlanSmemBytes / 4;
 static_assert(fast::fast_smem_floats<11>() <= kPlanSmemFloats, "band tile does not fit the plan buffer");
+static_assert(strided::strided_smem_floats<11, 4>() <= kPlanSmemFloats, "strided tile does not fit the plan buffer");
+static_assert(bband::band_lds_dwords<8, 4>() <= kPlanSmemFloats, "box band tile does not fit the plan buffer");
+static_assert(bband::band_lds_dwords<8, 1>() <= kPlanSmemFloats, "box band tile does not fit the plan buffer");
 
 // Items are dealt round-robin to the persistent blocks from a list sorted
 // costliest first.  The loop bounds depend only on blockIdx / gridDim /
 // n_items, so every wave of a block takes the same trip count and meets the
 // same barriers, and every block exits after ceil(n_items / gridDim) items.
 template <typename T>
-__global__ __launch_bounds__(BLOCK, 4) void ragged_kernel(const PairDesc* __restrict__ descs,
+__global__ __launch_bounds__(BLOCK, 3) void ragged_kernel(const PairDesc* __restrict__ descs,
                                                           const int2* __restrict__ items, int n_items,
                                                           float* partial) {
   __shared__ __align__(16) float smem[kPlanSmemFloats];
@@ -59,14 +66,24 @@ __global__ __launch_bounds__(BLOCK, 4) void ragged_kernel(const PairDesc* __rest
     const int2 w = items[it];
     const PairDesc& d = descs[w.x];
     float acc;
-    if (d.kind == kKindFast)
+    if (d.kind == kKindFast) {
       acc = fast::fast_stats_tile<11, T, 0>(d.fa, 0, w.y, smem);
-    else if (d.kind == kKindSep)
+    } else if (d.kind == kKindStrided4) {
+      acc = strided::strided_tile<11, 4, T>(d.fa, 0, w.y, smem);
+    } else if (d.kind == kKindSep) {
       acc = sep_fwd_tile<T>(d.sa, 0, w.y, smem);
-    else if constexpr (std::is_integral<T>::value)
+    } else if constexpr (std::is_same<T, uint8_t>::value) {
+      if (d.kind == kKindBand8s1)
+        acc = bband::box_band_tile<8, 1>(d.bb, 0, w.y, (uint32_t*)smem);
+      else if (d.kind == kKindBand8s4)
+        acc = bband::box_band_tile<8, 4, false>(d.bb, 0, w.y, (uint32_t*)smem);
+      else
+        acc = box_fwd_tile<T>(d.ba, 0, w.y, (unsigned char*)smem);
+    } else if constexpr (std::is_integral<T>::value) {
       acc = box_fwd_tile<T>(d.ba, 0, w.y, (unsigned char*)smem);
-    else
+    } else {
       acc = 0.f;  // integer-box pairs only exist in integer plans
+    }
     const float tot = block_sum<BLOCK>(acc, red);
     if (threadIdx.x == 0) partial[d.part_off + w.y] = tot;
   }
@@ -156,6 +173,8 @@ static ssimx_status build_desc(const ssimx_pair& pr, PairDesc& d, double& cost) 
   const int tile_idx = pick_tile(&p, dtype, W, H, 1);
   memset(&d, 0, sizeof(d));
   d.count = Wo * Ho;
+  // tile cost: map positions per tile times the measured time per position
+  // of each body on 1080p frames (picoseconds)
   if (use_fast(&p, dtype) && p.k == 11) {
     d.kind = kKindFast;
     const Geom g = fast_geom(&p, W, H, tile_idx);
@@ -165,7 +184,33 @@ static ssimx_status build_desc(const ssimx_pair& pr, PairDesc& d, double& cost) 
     d.fa.map_pitch = pr.map_pitch;
     d.fa.batch = 1;
     d.tiles = g.tiles_x * g.tiles_y;
-    cost = 64.0 * g.TH * 1.0;
+    cost = 64.0 * g.TH * 4.7;
+  } else if (use_strided(&p, dtype) && p.k == 11 && p.stride == 4) {
+    d.kind = kKindStrided4;
+    const Geom g = strided_geom(&p, W, H, tile_idx);
+    fill_fast_common(d.fa, &p, dtype, x, y, g);
+    d.fa.mode = 0;
+    d.fa.map = pr.map_out;
+    d.fa.map_pitch = pr.map_pitch;
+    d.fa.batch = 1;
+    d.tiles = g.tiles_x * g.tiles_y;
+    cost = 64.0 * g.TH * 38.0;
+  } else if (band_eligible(&p, dtype) && p.k == 8 && (p.stride == 1 || p.stride == 4) &&
+             aligned_vec(x.data, x.pitch, x.bstride, 1) && aligned_vec(y.data, y.pitch, y.bstride, 1)) {
+    d.kind = p.stride == 1 ? kKindBand8s1 : kKindBand8s4;
+    const Geom g = band_geom(&p, W, H, tile_idx);
+    BandArgs& a = d.bb;
+    a.x = x;
+    a.y = y;
+    a.g = g;
+    a.C1 = (float)p.C1;
+    a.C2 = (float)p.C2;
+    a.inv_k4 = (float)(1.0 / 4096.0);
+    a.mode = 0;
+    a.map = pr.map_out;
+    a.map_pitch = pr.map_pitch;
+    d.tiles = g.tiles_x * g.tiles_y;
+    cost = 256.0 * g.TH * (p.stride == 1 ? 2.5 : 13.4);
   } else if (choose_path(&p, dtype) == Path::kSep) {
     d.kind = kKindSep;
     const Geom g = plan_generic_geom(&p, dtype, Path::kSep, W, H, tile_idx);
@@ -180,7 +225,7 @@ static ssimx_status build_desc(const ssimx_pair& pr, PairDesc& d, double& cost) 
     a.map_pitch = pr.map_pitch;
     gaussian_taps_f32(p.window, p.k, p.sigma, a.taps);
     d.tiles = g.tiles_x * g.tiles_y;
-    cost = (double)g.IH * g.TW * p.k * 0.7 + (double)g.TH * g.TW * p.k * 1.2;
+    cost = (double)g.TH * g.TW * (10.0 * p.stride * p.stride);
   } else {
     d.kind = kKindBox;
     const Geom g = plan_generic_geom(&p, dtype, Path::kBox, W, H, tile_idx);
@@ -195,7 +240,7 @@ static ssimx_status build_desc(const ssimx_pair& pr, PairDesc& d, double& cost) 
     a.map_pitch = pr.map_pitch;
     a.batch = 1;
     d.tiles = g.tiles_x * g.tiles_y;
-    cost = (double)g.IH * g.TW * p.k * 0.3 + (double)g.TH * g.TW * p.k * 0.3;
+    cost = (double)g.TH * g.TW * (13.0 * p.stride * p.stride);
   }
   return SSIMX_OK;
 }
@@ -302,6 +347,7 @@ ssimx_status ssimx_plan_create(const ssimx_pair* pairs, int n, void* stream, ssi
     d.fa.partial = pl->partial + d.part_off;
     d.sa.partial = pl->partial + d.part_off;
     d.ba.partial = pl->partial + d.part_off;
+    d.bb.partial = pl->partial + d.part_off;
   }
   if (!err) err = (int)hipMemcpy(pl->descs, pl->host_descs.data(), sizeof(PairDesc) * n, hipMemcpyHostToDevice);
   if (!err) err = (int)hipMemcpy(pl->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
@@ -338,6 +384,10 @@ ssimx_status ssimx_plan_run_unbatched(ssimx_plan* pl, float* scores_out, void* s
     int err;
     if (d.kind == kKindFast)
       err = launch_fast_stats(pl->dtype, 0, d.fa, 1, st);
+    else if (d.kind == kKindStrided4)
+      err = launch_strided(pl->dtype, d.fa, 1, st);
+    else if (d.kind == kKindBand8s1 || d.kind == kKindBand8s4)
+      err = launch_box_band(d.bb, 1, st);
     else if (d.kind == kKindSep)
       err = launch_sep_fwd(pl->dtype, d.sa, 1, sep_lds_bytes(d.sa.g), st);
     else

@@ -162,8 +162,10 @@ __device__ __forceinline__ SsimTerms band_terms(uint32_t sx, uint32_t sy, uint32
 }
 
 // One 256-column tile: returns this thread's share of the tile's pooled sum.
-// `lds` holds band_lds_dwords<K, S>() dwords.
-template <int K, int S>
+// `lds` holds band_lds_dwords<K, S>() dwords.  PF = false loads each chunk
+// right before it is consumed instead of one chunk ahead (fewer live
+// registers, for callers that also host other tile bodies).
+template <int K, int S, bool PF = true>
 __device__ __forceinline__ float box_band_tile(const BandArgs& a, int frame, int tile, uint32_t* lds) {
   using Sh = Shape<K, S>;
   constexpr int R = Sh::R;
@@ -188,20 +190,24 @@ __device__ __forceinline__ float box_band_tile(const BandArgs& a, int frame, int
   for (int q = 0; q < 5; ++q) hist[0][q] = 0u;  // sample 0: nothing summed yet
 
   uint32_t rx[Sh::PER], ry[Sh::PER];
-  band_fetch<K, S>(a, X, Y, ry0, px0, rx, ry);
+  if constexpr (PF) band_fetch<K, S>(a, X, Y, ry0, px0, rx, ry);
   float acc = 0.f;
   // m0 runs over 1, 1 + R, 1 + 2R, ...: sample m = m0 + u lives in ring slot
   // (1 + u) % R, and the sample K rows earlier in slot (2 + u) % R.
   for (int m0 = 1; m0 <= m_max; m0 += R) {
     __syncthreads();  // staging buffer free
+    if constexpr (!PF) band_fetch<K, S>(a, X, Y, ry0 + S * (m0 - 1), px0, rx, ry);
     band_store<K, S>(rx, ry, Xs, Ys);
     __syncthreads();
-    if (m0 + R <= m_max) band_fetch<K, S>(a, X, Y, ry0 + S * (m0 - 1 + R), px0, rx, ry);
+    if constexpr (PF)
+      if (m0 + R <= m_max) band_fetch<K, S>(a, X, Y, ry0 + S * (m0 - 1 + R), px0, rx, ry);
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int m = m0 + u;
       if (m <= m_max) {
-#pragma unroll
+        // the S rows of a sample only add into P: kept rolled to bound the
+        // number of live registers
+#pragma unroll 1
         for (int rr = 0; rr < S; ++rr) {
           const int lr = u * S + rr;
           band_row<K, S>(Xs + lr * Sh::RW + w0, Ys + lr * Sh::RW + w0, sh, P);

@@ -111,7 +111,7 @@ static Geom geom_with(const ssimx_params* p, int W, int H, int tw, int th) {
   return g;
 }
 
-static bool aligned_vec(const void* p, int64_t pitch, int64_t bstride, int esize) {
+bool aligned_vec(const void* p, int64_t pitch, int64_t bstride, int esize) {
   return ((uintptr_t)p % (4 * esize)) == 0 && pitch % 4 == 0 && bstride % 4 == 0;
 }
 
@@ -145,7 +145,8 @@ static const int kStridedRows[] = {32, 64, 16, 128, 8, 256};
 
 Geom strided_geom(const ssimx_params* p, int W, int H, int tile_idx) {
   Geom g = geom_with(p, W, H, strided::kTWo, 1);
-  const int cho = strided::kRows / p->stride;
+  const int cho = p->stride == 2 ? strided::Shape<7, 2>::CHo : p->stride == 3 ? strided::Shape<7, 3>::CHo
+                                                                              : strided::Shape<7, 4>::CHo;
   const int rows = kStridedRows[(tile_idx >= 0 && tile_idx < num_tile_cfgs()) ? tile_idx : 0];
   g.TW = strided::kTWo;
   g.TH = std::max(1, rows / cho) * cho;

@@ -33,6 +33,11 @@ size_t fwd_ws_bytes(const ssimx_params* p, int dtype, int W, int H, int batch);
 struct FastArgs;
 int dtype_size(int dtype);
 Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx);
+Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx);
+Geom strided_geom(const ssimx_params* p, int W, int H, int tile_idx);
+bool use_strided(const ssimx_params* p, int dtype);
+bool band_eligible(const ssimx_params* p, int dtype);
+bool aligned_vec(const void* p, int64_t pitch, int64_t bstride, int esize);
 bool use_fast(const ssimx_params* p, int dtype);
 void fill_fast_common(FastArgs& a, const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, const Geom& g);
 

@@ -78,6 +78,7 @@ __device__ __forceinline__ void sat_load(const T* P, int64_t pitch, int W, int r
 template <typename T, int CPT, int PHASE>
 __global__ __launch_bounds__(kSNT) void sat_group_kernel(SatArgs a) {
   __shared__ uint32_t wtot[2][kSNT / 64][5];
+  __shared__ __align__(16) uint32_t tbuf[PHASE == 1 ? kSNT / 64 : 1][PHASE == 1 ? 64 * CPT : 4];
   const int g = blockIdx.x, frame = blockIdx.y;
   const int r0 = g * a.G, r1 = min(a.H, r0 + a.G);  // image rows; table rows r0+1 .. r1
   const int c0 = threadIdx.x * CPT;
@@ -94,10 +95,21 @@ __global__ __launch_bounds__(kSNT) void sat_group_kernel(SatArgs a) {
     for (int i = 0; i < CPT; ++i)
       col[q][i] = (PHASE == 1 && c0 + i < a.W) ? tab[q * a.qstride + (int64_t)r0 * a.rowlen + c0 + i + 1] : 0u;
 
+  // the next row's pixels are loaded while the current row is scanned
+  uint32_t nx[CPT], ny[CPT];
+  sat_load<T, CPT>(X, a.x.pitch, a.W, r0, c0, a.vec_ok, nx);
+  sat_load<T, CPT>(Y, a.y.pitch, a.W, r0, c0, a.vec_ok, ny);
   for (int r = r0; r < r1; ++r) {
     uint32_t xv[CPT], yv[CPT];
-    sat_load<T, CPT>(X, a.x.pitch, a.W, r, c0, a.vec_ok, xv);
-    sat_load<T, CPT>(Y, a.y.pitch, a.W, r, c0, a.vec_ok, yv);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      xv[i] = nx[i];
+      yv[i] = ny[i];
+    }
+    if (r + 1 < r1) {
+      sat_load<T, CPT>(X, a.x.pitch, a.W, r + 1, c0, a.vec_ok, nx);
+      sat_load<T, CPT>(Y, a.y.pitch, a.W, r + 1, c0, a.vec_ok, ny);
+    }
     uint32_t p[5][CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -134,14 +146,28 @@ __global__ __launch_bounds__(kSNT) void sat_group_kernel(SatArgs a) {
 #pragma unroll
       for (int i = 0; i < CPT; ++i) col[q][i] += p[q][i] + ex[q];
     if (PHASE == 1 && r + 1 < r1) {
+      // Each lane holds CPT consecutive columns; the row goes out through a
+      // wave-private LDS slab so that every store instruction writes 64
+      // consecutive entries (one lane per column).
       const int64_t ro = (int64_t)(r + 1) * a.rowlen;
+      uint32_t* wb = tbuf[wid];
+      const int wc0 = (threadIdx.x & ~63) * CPT;  // first column of this wave
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        uint32_t* d = tab + q * a.qstride + ro;
-        if (threadIdx.x == 0) d[0] = 0u;
 #pragma unroll
-        for (int i = 0; i < CPT; ++i)
-          if (c0 + i < a.W) d[c0 + i + 1] = col[q][i];
+        for (int i = 0; i < CPT; i += 4)
+          *(uint4*)&wb[lane * CPT + i] = make_uint4(col[q][i], col[q][i + 1], col[q][i + 2], col[q][i + 3]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        uint32_t* d = tab + q * a.qstride + ro + 1;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+          const int c = wc0 + i * 64 + lane;
+          if (c < a.W) d[c] = wb[i * 64 + lane];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (threadIdx.x == 0) d[-1] = 0u;
       }
     }
   }
@@ -213,13 +239,30 @@ __global__ __launch_bounds__(256) void sat_band_ssim_kernel(SatSsimArgs a) {
   float acc = 0.f;
   // sample m = table row S (oy0 + m); m0 runs over multiples of R, so sample
   // m sits in ring slot u and the sample K rows above it in slot (u + 1) % R
+  // corner values of the next sample are loaded one sample ahead
+  uint32_t lo[5], hi[5];
+  {
+    const uint32_t* p = T0 + (int64_t)(S * oy0) * a.rowlen;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      lo[q] = p[q * a.qstride];
+      hi[q] = p[q * a.qstride + K];
+    }
+  }
   for (int m0 = 0; m0 <= m_max; m0 += R) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int m = min(m0 + u, m_max);
-      const uint32_t* p = T0 + (int64_t)(S * (oy0 + m)) * a.rowlen;
 #pragma unroll
-      for (int q = 0; q < 5; ++q) hist[u][q] = p[q * a.qstride + K] - p[q * a.qstride];
+      for (int q = 0; q < 5; ++q) hist[u][q] = hi[q] - lo[q];
+      {
+        const int mn = min(m0 + u + 1, m_max);
+        const uint32_t* p = T0 + (int64_t)(S * (oy0 + mn)) * a.rowlen;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          lo[q] = p[q * a.qstride];
+          hi[q] = p[q * a.qstride + K];
+        }
+      }
       if (m0 + u <= m_max && m0 + u >= R - 1) {
         const int pv = (u + 1) % R;
         const int oi = oy0 + m0 + u - (R - 1);

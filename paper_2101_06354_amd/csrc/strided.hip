@@ -7,7 +7,7 @@ namespace ssimx {
 using namespace strided;
 
 template <int K, int S, typename T>
-__global__ __launch_bounds__(kNT, 2) void strided_kernel(FastArgs a) {
+__global__ __launch_bounds__(kNT, 3) void strided_kernel(FastArgs a) {
   __shared__ __align__(16) float smem[strided_smem_floats<K, S>()];
   __shared__ float red[kNT / 64];
   int tile, frame;

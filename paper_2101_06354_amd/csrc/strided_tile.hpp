@@ -3,7 +3,7 @@
 // only the windows at (S i, S j) are evaluated.
 //
 // A block owns 64 map columns and marches down its tile in chunks of CHo map
-// rows (16 / S, so that S * CHo <= 16 new footprint rows arrive per chunk).
+// rows (16 / S, or 3 at stride 4: at most 16 new footprint rows per chunk).
 // Per chunk:
 //   * the new footprint rows are staged in LDS as u = x + y, v = x - y;
 //   * row pass: for every staged row and map column, the row mean and the
@@ -27,12 +27,17 @@ namespace strided {
 
 constexpr int kNT = 256;   // threads per block
 constexpr int kTWo = 64;   // map columns per tile
-constexpr int kRows = 16;  // footprint rows per chunk, rounded down to a multiple of S
+// Footprint rows per chunk (rounded down to a multiple of S); stride 4 takes
+// 12 so that the LDS of three blocks fits a compute unit.
+template <int S>
+constexpr int chunk_rows() {
+  return S == 4 ? 12 : 16;
+}
 
 template <int K, int S>
 struct Shape {
   static_assert(K > S, "windows of consecutive map rows must overlap");
-  static constexpr int CHo = kRows / S;                 // map rows per chunk
+  static constexpr int CHo = chunk_rows<S>() / S;       // map rows per chunk
   static constexpr int NEW = S * CHo;                   // new footprint rows per chunk
   static constexpr int KEEP = K - S;                    // band rows shared by consecutive chunks
   static constexpr int BAND = NEW + KEEP;               // = S (CHo - 1) + K
