@@ -110,6 +110,50 @@ __device__ __forceinline__ void fetch_coef(const FastArgs& a, int frame, int r0,
   }
 }
 
+// Pixel quads of the chunk's rows (the 64 output columns of the tile), one
+// quad per thread and plane, held in registers until the chunk is staged
+// (valid borders: pixels outside the plane read as zero and are not used).
+template <typename T>
+__device__ __forceinline__ void fetch_quad_valid(const T* P, int64_t pitch, int W, int H, int vec_ok, int py, int px,
+                                                 fast::Quad<T>& q) {
+#pragma unroll
+  for (int i = 0; i < fast::Quad<T>::NW; ++i) q.w[i] = 0u;
+  if (py >= H) return;
+  const T* s = P + (int64_t)py * pitch + px;
+  if (vec_ok && px + 3 < W) {
+    if constexpr (sizeof(T) == 1) {
+      q.w[0] = *(const uint32_t*)s;
+    } else if constexpr (sizeof(T) == 2) {
+      const uint2 v = *(const uint2*)s;
+      q.w[0] = v.x;
+      q.w[1] = v.y;
+    } else {
+      const uint4 v = *(const uint4*)s;
+      q.w[0] = v.x;
+      q.w[1] = v.y;
+      q.w[2] = v.z;
+      q.w[3] = v.w;
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (px + e >= W) break;
+    const uint32_t b = fast::elem_bits<T>(s[e]);
+    if constexpr (sizeof(T) == 1) q.w[0] |= b << (8 * e);
+    else if constexpr (sizeof(T) == 2) q.w[e >> 1] |= b << (16 * (e & 1));
+    else q.w[e] = b;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void fetch_xy(const FastArgs& a, const T* X, const T* Y, int py0, int px0,
+                                         fast::Quad<T>& qx, fast::Quad<T>& qy) {
+  const int r = threadIdx.x >> 4, q = threadIdx.x & 15;  // 16 rows x 16 quads
+  fetch_quad_valid<T>(X, a.x.pitch, a.g.W, a.g.H, a.vec_ok, py0 + r, px0 + 4 * q, qx);
+  fetch_quad_valid<T>(Y, a.y.pitch, a.g.W, a.g.H, a.vec_ok, py0 + r, px0 + 4 * q, qy);
+}
+
 // Registers -> the LDS planes C[m][r][col].
 template <int K>
 __device__ __forceinline__ void store_coef(const CQuad* q, int nrows, float* C) {
@@ -170,8 +214,10 @@ __device__ __forceinline__ void coef_band_shift(float* HM) {
 template <int K, typename T>
 __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   using S = AShape<K>;
+  static_assert(S::CH == 16 && kTW == 64 && kNT == 256, "one pixel quad per thread and plane per chunk");
   __shared__ __align__(16) float C[kNM * S::CH * S::IWP];
   __shared__ __align__(16) float HM[kNM * S::PL];
+  __shared__ __align__(16) uint32_t XY[2][S::CH * kTW * sizeof(T) / 4];  // the chunk's x, y in their own packing
   constexpr int PL = S::PL;
   int tile, frame;
   xcd_tile(tile, frame);
@@ -192,13 +238,23 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   coef_row_pass<K>(taps, C, S::HALO, HM, 0);
   const int qy_end = __builtin_amdgcn_readfirstlane(min(a.g.H, qy0 + a.QH));
   fetch_coef<K>(a, frame, qy0, c0, S::CH, q);
+  fast::Quad<T> px4, py4;
+  fetch_xy<T>(a, X, Y, qy0, qx0, px4, py4);
   for (int cy = qy0; cy < qy_end; cy += S::CH) {
     __syncthreads();
     store_coef<K>(q, S::CH, C);
+#pragma unroll
+    for (int w = 0; w < fast::Quad<T>::NW; ++w) {
+      XY[0][threadIdx.x * fast::Quad<T>::NW + w] = px4.w[w];
+      XY[1][threadIdx.x * fast::Quad<T>::NW + w] = py4.w[w];
+    }
     __syncthreads();
     coef_row_pass<K>(taps, C, S::CH, HM, S::HALO);
     __syncthreads();
-    if (cy + S::CH < qy_end) fetch_coef<K>(a, frame, cy + S::CH, c0, S::CH, q);
+    if (cy + S::CH < qy_end) {
+      fetch_coef<K>(a, frame, cy + S::CH, c0, S::CH, q);
+      fetch_xy<T>(a, X, Y, cy + S::CH, qx0, px4, py4);
+    }
     for (int it = threadIdx.x; it < (S::CH / 4) * kTW; it += kNT) {
       const int gr = it / kTW, c = it - gr * kTW;
       const int px = qx0 + c;
@@ -222,12 +278,15 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
         }
       }
       if (px >= a.g.W) continue;
+      const T* xs = (const T*)XY[0];
+      const T* ys = (const T*)XY[1];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int py = cy + 4 * gr + j;
         if (py >= qy_end) continue;
-        const float xv = to_f32<T>(X[(int64_t)py * a.x.pitch + px]);
-        const float yv = to_f32<T>(Y[(int64_t)py * a.y.pitch + px]);
+        // staged row 4 gr + j, column c (quads are stored row-major, 16 per row)
+        const float xv = to_f32<T>(xs[(4 * gr + j) * kTW + c]);
+        const float yv = to_f32<T>(ys[(4 * gr + j) * kTW + c]);
         // dL/dy = W^T A + (u - t_u) W^T B_u - (v - t_v) W^T B_v
         float gy = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]) - ((xv - yv) - a.tv) * G[2][j];
         if (a.coarse) {
