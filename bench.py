@@ -24,6 +24,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FP32 flop/clk (packed FMA)
+# Without packed FP32 (not used by this build) one wave64 VALU instruction
+# occupies a 16-lane SIMD for 4 cycles: 256 CU x 4 SIMD x 16 lanes x 2 flop
+# x 2.4 GHz for FMA.
+FP32_VALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+SIMDS, CLOCK_HZ, CYCLES_PER_WAVE_INST = 1024, 2.4e9, 4
 # Textbook separable 5-moment Gaussian SSIM, per output map pixel: 5 maps x 11
 # taps x 2 passes x 2 flop + 3 products + ~17 flop of luminance/cs/Q terms.
 ALG_FLOP_PER_OUT_PX = 5 * 11 * 2 * 2 + 3 + 17
@@ -73,18 +78,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+def measured_counters(kernel: str) -> dict:
+    """Per-launch figures from the committed rocprofv3 PMC summary (HBM bytes
+    from FETCH_SIZE / WRITE_SIZE, VALU wave instructions), if they were taken
+    on the current kernel sources; else {}."""
+    path = os.path.join(ROOT, "profiles", "pmc_counters.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
-        return None
+        return {}
     e = d.get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
-        return None
-    return e.get("bytes_per_launch")
+        return {}
+    return e
 
 
 def cpu_baseline(x, y, frames_sample: int, with_bwd: bool, min_seconds: float = 10.0):
@@ -209,7 +215,12 @@ def main():
     alg_flop = out_px * ALG_FLOP_PER_OUT_PX
     achieved_tflops = alg_flop / (fwd_avg * 1e-3) / 1e12
     achieved_gbs = alg_bytes / (fwd_avg * 1e-3) / 1e9
-    traffic = measured_traffic("fast_stats_kernel<11,u8,0>")
+    pmc = measured_counters("fast_stats_kernel<11,u8,0>")
+    traffic = pmc.get("bytes_per_launch")
+    valu = pmc.get("valu_insts_per_launch")
+    # fraction of the VALU issue rate the forward uses (4 cycles per wave64
+    # instruction on each of the 1024 SIMDs), from the measured duration
+    issue_frac = (valu * CYCLES_PER_WAVE_INST / (SIMDS * CLOCK_HZ * fwd_avg * 1e-3)) if valu else None
     res = {
         "metric": "SSIM Mpixel/s fwd & fwd+bwd (1080p luma, Gaussian 11x11); % HBM roofline",
         "value": value,
@@ -233,7 +244,11 @@ def main():
         "roofline": {"bound": "alu", "kernel": "fast_stats_kernel<11,u8,0> (+finalize)", "achieved": achieved_tflops,
                      "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP32_VALU_PEAK_TFLOPS,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "peak_nonpacked": FP32_VALU_NONPACKED_TFLOPS,
+                     "frac_nonpacked": achieved_tflops / FP32_VALU_NONPACKED_TFLOPS,
+                     "valu_issue_frac": issue_frac,
+                     "alg_flop_per_launch": alg_flop},
         "hbm_roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
     }

@@ -19,13 +19,9 @@
 // bounded by the local deviations: the shared value lies inside each window
 // with weight g_t, and sum g (z - t)^2 <= V (1 + 1/g_t).
 //
-// Kernels:
-//   fast_stats_kernel<K, T, EPI>  EPI = 0: SSIM / cs map + pooled partials
-//                                 EPI = 1: the four adjoint coefficient maps
-//   fast_adjoint_kernel<K, T>     transposed window over the coefficient
-//                                 maps and the per-pixel combine (valid
-//                                 borders), optionally adding the 2x2
-//                                 transpose of a coarser-scale gradient.
+// Kernel: fast_stats_kernel<K, T, EPI>, EPI = 0: SSIM / cs map + pooled
+// partials; EPI = 1: the three adjoint coefficient planes (the transposed
+// window over them is in fast_adjoint.hip).
 #include "fast_tile_body.hpp"
 
 namespace ssimx {
@@ -42,262 +38,6 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
   if constexpr (EPI == 0) {
     const float tot = block_sum<kNT>(acc, red);
     if (threadIdx.x == 0) a.partial[(int64_t)frame * gridDim.x + tile] = tot;
-  }
-}
-
-// ---------------------------------------------------------------- adjoint
-// Transposed window over the coefficient planes (valid borders, stride 1):
-// G_q(y) = sum_{p in map, y - p in [0, K)} w(y - p) C_q(p), a plain K x K
-// correlation of the zero-extended planes with the (symmetric) window.  Three
-// planes arrive (A = A_u - A_v, B_u, B_v), each with a row pitch that is a
-// multiple of 4; the footprint origin is aligned to 4 map columns so that an
-// interior footprint quad is one aligned 16-byte load per plane.  The next
-// chunk's quads are fetched into registers before the column pass.
-namespace {
-
-constexpr int kNM = 3;  // coefficient planes
-
-template <int K>
-struct AShape {
-  static constexpr int HALO = K - 1;
-  static constexpr int LP = (4 - HALO % 4) % 4;          // left pad aligning the footprint origin
-  static constexpr int NREAD = (LP + K + 3 + 3) / 4;     // float4 LDS reads per row-pass item
-  static constexpr int IWP = kTW - 4 + 4 * NREAD;
-  static constexpr int NQ = IWP / 4;
-  static constexpr int CH = 16;                           // pixel rows per chunk
-  static constexpr int BAND = CH + HALO;
-  static constexpr int PL = BAND * kTWP;
-  static constexpr int ITEMS = CH * NQ;
-  static constexpr int PER_THREAD = (ITEMS + kNT - 1) / kNT;
-  static_assert(CH >= HALO, "band copy needs CH >= K - 1");
-  static_assert(IWP >= LP + kTW + K - 1, "footprint row too short");
-};
-
-struct CQuad {
-  float4 v[kNM];  // four consecutive map positions of each plane
-};
-
-// Map rows r0 .. r0+nrows-1, footprint columns from c0 (a multiple of 4),
-// into registers.
-template <int K>
-__device__ __forceinline__ void fetch_coef(const FastArgs& a, int frame, int r0, int c0, int nrows, CQuad* q) {
-  using S = AShape<K>;
-  const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
-  const float* base = a.coef + (int64_t)frame * a.g.Ho * a.cpitch;
-#pragma unroll
-  for (int i = 0; i < S::PER_THREAD; ++i) {
-    const int it = threadIdx.x + i * kNT;
-    if (it < nrows * S::NQ) {
-      const int r = it / S::NQ, qq = it - r * S::NQ;
-      const int pr = r0 + r, pc = c0 + 4 * qq;
-      if (pr >= 0 && pr < a.g.Ho && pc >= 0 && pc + 3 < a.g.Wo) {
-        const float* src = base + (int64_t)pr * a.cpitch + pc;
-#pragma unroll
-        for (int m = 0; m < kNM; ++m) q[i].v[m] = *(const float4*)(src + m * qs);
-      } else {
-#pragma unroll
-        for (int m = 0; m < kNM; ++m) {
-          float e[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const bool in = pr >= 0 && pr < a.g.Ho && pc + k >= 0 && pc + k < a.g.Wo;
-            e[k] = in ? base[m * qs + (int64_t)pr * a.cpitch + pc + k] : 0.f;
-          }
-          q[i].v[m] = make_float4(e[0], e[1], e[2], e[3]);
-        }
-      }
-    }
-  }
-}
-
-// Pixel quads of the chunk's rows (the 64 output columns of the tile), one
-// quad per thread and plane, held in registers until the chunk is staged
-// (valid borders: pixels outside the plane read as zero and are not used).
-template <typename T>
-__device__ __forceinline__ void fetch_quad_valid(const T* P, int64_t pitch, int W, int H, int vec_ok, int py, int px,
-                                                 fast::Quad<T>& q) {
-#pragma unroll
-  for (int i = 0; i < fast::Quad<T>::NW; ++i) q.w[i] = 0u;
-  if (py >= H) return;
-  const T* s = P + (int64_t)py * pitch + px;
-  if (vec_ok && px + 3 < W) {
-    if constexpr (sizeof(T) == 1) {
-      q.w[0] = *(const uint32_t*)s;
-    } else if constexpr (sizeof(T) == 2) {
-      const uint2 v = *(const uint2*)s;
-      q.w[0] = v.x;
-      q.w[1] = v.y;
-    } else {
-      const uint4 v = *(const uint4*)s;
-      q.w[0] = v.x;
-      q.w[1] = v.y;
-      q.w[2] = v.z;
-      q.w[3] = v.w;
-    }
-    return;
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    if (px + e >= W) break;
-    const uint32_t b = fast::elem_bits<T>(s[e]);
-    if constexpr (sizeof(T) == 1) q.w[0] |= b << (8 * e);
-    else if constexpr (sizeof(T) == 2) q.w[e >> 1] |= b << (16 * (e & 1));
-    else q.w[e] = b;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void fetch_xy(const FastArgs& a, const T* X, const T* Y, int py0, int px0,
-                                         fast::Quad<T>& qx, fast::Quad<T>& qy) {
-  const int r = threadIdx.x >> 4, q = threadIdx.x & 15;  // 16 rows x 16 quads
-  fetch_quad_valid<T>(X, a.x.pitch, a.g.W, a.g.H, a.vec_ok, py0 + r, px0 + 4 * q, qx);
-  fetch_quad_valid<T>(Y, a.y.pitch, a.g.W, a.g.H, a.vec_ok, py0 + r, px0 + 4 * q, qy);
-}
-
-// Registers -> the LDS planes C[m][r][col].
-template <int K>
-__device__ __forceinline__ void store_coef(const CQuad* q, int nrows, float* C) {
-  using S = AShape<K>;
-  constexpr int PLC = S::CH * S::IWP;
-#pragma unroll
-  for (int i = 0; i < S::PER_THREAD; ++i) {
-    const int it = threadIdx.x + i * kNT;
-    if (it < nrows * S::NQ) {
-      const int r = it / S::NQ, qq = it - r * S::NQ;
-      float* d = C + r * S::IWP + 4 * qq;
-#pragma unroll
-      for (int m = 0; m < kNM; ++m) *(float4*)&d[m * PLC] = q[i].v[m];
-    }
-  }
-}
-
-// Row pass of the transposed window: an item is one plane of one row and 4
-// adjacent outputs.  Consecutive lanes take consecutive 4-column groups of
-// the same plane and row, so every 8-lane phase of a 16-byte LDS read
-// touches 32 distinct banks.
-template <int K>
-__device__ __forceinline__ void coef_row_pass(const float* taps, const float* C, int nrows, float* HM, int band0) {
-  using S = AShape<K>;
-  constexpr int PLC = S::CH * S::IWP;
-  constexpr int NG = kTW / 4;
-  for (int it = threadIdx.x; it < nrows * kNM * NG; it += kNT) {
-    const int gq = it % NG, m = (it / NG) % kNM, r = it / (kNM * NG);
-    float z[4 * S::NREAD];
-#pragma unroll
-    for (int n = 0; n < S::NREAD; ++n)
-      *(float4*)&z[4 * n] = *(const float4*)&C[m * PLC + r * S::IWP + 4 * gq + 4 * n];
-    float h[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float acc = 0.f;
-#pragma unroll
-      for (int t = 0; t < K; ++t) acc = fmaf(taps[t], z[S::LP + j + t], acc);
-      h[j] = acc;
-    }
-    *(float4*)&HM[m * S::PL + (band0 + r) * kTWP + 4 * gq] = make_float4(h[0], h[1], h[2], h[3]);
-  }
-}
-
-template <int K>
-__device__ __forceinline__ void coef_band_shift(float* HM) {
-  using S = AShape<K>;
-  constexpr int NV = S::HALO * kTW / 4;
-  for (int it = threadIdx.x; it < kNM * NV; it += kNT) {
-    const int m = it / NV, e = it - m * NV;
-    const int row = e / (kTW / 4), q = e % (kTW / 4);
-    *(float4*)&HM[m * S::PL + row * kTWP + 4 * q] = *(const float4*)&HM[m * S::PL + (S::CH + row) * kTWP + 4 * q];
-  }
-}
-
-}  // namespace
-
-template <int K, typename T>
-__global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
-  using S = AShape<K>;
-  static_assert(S::CH == 16 && kTW == 64 && kNT == 256, "one pixel quad per thread and plane per chunk");
-  __shared__ __align__(16) float C[kNM * S::CH * S::IWP];
-  __shared__ __align__(16) float HM[kNM * S::PL];
-  __shared__ __align__(16) uint32_t XY[2][S::CH * kTW * sizeof(T) / 4];  // the chunk's x, y in their own packing
-  constexpr int PL = S::PL;
-  int tile, frame;
-  xcd_tile(tile, frame);
-  const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
-  const int qx0 = __builtin_amdgcn_readfirstlane(txi * kTW), qy0 = __builtin_amdgcn_readfirstlane(tyi * a.QH);
-  const int c0 = qx0 - S::HALO - S::LP;
-  float taps[K];
-#pragma unroll
-  for (int t = 0; t < K; ++t) taps[t] = a.taps[t];
-  const T* X = (const T*)a.x.data + (int64_t)frame * a.x.bstride;
-  const T* Y = (const T*)a.y.data + (int64_t)frame * a.y.bstride;
-
-  // pixel row y reads map rows y-K+1 .. y; prologue = the first K-1 of them
-  CQuad q[S::PER_THREAD];
-  fetch_coef<K>(a, frame, qy0 - S::HALO, c0, S::HALO, q);
-  store_coef<K>(q, S::HALO, C);
-  __syncthreads();
-  coef_row_pass<K>(taps, C, S::HALO, HM, 0);
-  const int qy_end = __builtin_amdgcn_readfirstlane(min(a.g.H, qy0 + a.QH));
-  fetch_coef<K>(a, frame, qy0, c0, S::CH, q);
-  fast::Quad<T> px4, py4;
-  fetch_xy<T>(a, X, Y, qy0, qx0, px4, py4);
-  for (int cy = qy0; cy < qy_end; cy += S::CH) {
-    __syncthreads();
-    store_coef<K>(q, S::CH, C);
-#pragma unroll
-    for (int w = 0; w < fast::Quad<T>::NW; ++w) {
-      XY[0][threadIdx.x * fast::Quad<T>::NW + w] = px4.w[w];
-      XY[1][threadIdx.x * fast::Quad<T>::NW + w] = py4.w[w];
-    }
-    __syncthreads();
-    coef_row_pass<K>(taps, C, S::CH, HM, S::HALO);
-    __syncthreads();
-    if (cy + S::CH < qy_end) {
-      fetch_coef<K>(a, frame, cy + S::CH, c0, S::CH, q);
-      fetch_xy<T>(a, X, Y, cy + S::CH, qx0, px4, py4);
-    }
-    for (int it = threadIdx.x; it < (S::CH / 4) * kTW; it += kNT) {
-      const int gr = it / kTW, c = it - gr * kTW;
-      const int px = qx0 + c;
-      float G[kNM][4];
-#pragma unroll
-      for (int m = 0; m < kNM; ++m)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) G[m][j] = 0.f;
-#pragma unroll
-      for (int r = 0; r < K + 3; ++r) {
-        float h[kNM];
-#pragma unroll
-        for (int m = 0; m < kNM; ++m) h[m] = HM[m * PL + (4 * gr + r) * kTWP + c];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int t = r - j;
-          if (t >= 0 && t < K) {
-#pragma unroll
-            for (int m = 0; m < kNM; ++m) G[m][j] = fmaf(taps[t], h[m], G[m][j]);
-          }
-        }
-      }
-      if (px >= a.g.W) continue;
-      const T* xs = (const T*)XY[0];
-      const T* ys = (const T*)XY[1];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int py = cy + 4 * gr + j;
-        if (py >= qy_end) continue;
-        // staged row 4 gr + j, column c (quads are stored row-major, 16 per row)
-        const float xv = to_f32<T>(xs[(4 * gr + j) * kTW + c]);
-        const float yv = to_f32<T>(ys[(4 * gr + j) * kTW + c]);
-        // dL/dy = W^T A + (u - t_u) W^T B_u - (v - t_v) W^T B_v
-        float gy = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]) - ((xv - yv) - a.tv) * G[2][j];
-        if (a.coarse) {
-          const int cyy = py >> 1, cxx = px >> 1;
-          if (cyy < a.Hc && cxx < a.Wc) gy += 0.25f * a.coarse[((int64_t)frame * a.Hc + cyy) * a.Wc + cxx];
-        }
-        a.out[(int64_t)frame * a.out_bstride + (int64_t)py * a.out_pitch + px] = gy;
-      }
-    }
-    __syncthreads();
-    coef_band_shift<K>(HM);
   }
 }
 
@@ -331,29 +71,6 @@ int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStrea
     default: return (int)hipErrorInvalidValue;
   }
 #undef SSIMX_K
-}
-
-template <int K>
-static int launch_adj_k(int dtype, const FastArgs& a, dim3 grid, hipStream_t st) {
-  switch (dtype) {
-    case SSIMX_U8: hipLaunchKernelGGL((fast_adjoint_kernel<K, uint8_t>), grid, dim3(kNT), 0, st, a); break;
-    case SSIMX_U16: hipLaunchKernelGGL((fast_adjoint_kernel<K, uint16_t>), grid, dim3(kNT), 0, st, a); break;
-    case SSIMX_F32: hipLaunchKernelGGL((fast_adjoint_kernel<K, float>), grid, dim3(kNT), 0, st, a); break;
-    case SSIMX_BF16: hipLaunchKernelGGL((fast_adjoint_kernel<K, bf16_t>), grid, dim3(kNT), 0, st, a); break;
-    default: return (int)hipErrorInvalidValue;
-  }
-  return (int)hipGetLastError();
-}
-
-int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st) {
-  dim3 grid(a.qtiles_x * a.qtiles_y, batch);
-  switch (a.g.k) {
-    case 7: return launch_adj_k<7>(dtype, a, grid, st);
-    case 9: return launch_adj_k<9>(dtype, a, grid, st);
-    case 11: return launch_adj_k<11>(dtype, a, grid, st);
-    case 13: return launch_adj_k<13>(dtype, a, grid, st);
-    default: return (int)hipErrorInvalidValue;
-  }
 }
 
 }  // namespace ssimx
