@@ -44,7 +44,8 @@ __all__ = [
     "box_sums_integral", "box_stats", "downsample2x2", "pyramid",
     "msssim", "ssim_map_backward", "ssim_pooled_backward",
     "msssim_backward", "rgb_to_y_bt601", "y_grad_to_rgb_bt601",
-    "MS_WEIGHTS",
+    "MS_WEIGHTS", "pool_mean", "pool_cov", "pool_md", "pool_minkowski",
+    "pool_distortion_weighted", "pool_five_number", "pool_percentile",
 ]
 
 # Exponents of the original five-scale MS-SSIM, as used by the configurations
@@ -522,3 +523,75 @@ def rgb_to_y_bt601(rgb: np.ndarray) -> np.ndarray:
 def y_grad_to_rgb_bt601(gy: np.ndarray) -> np.ndarray:
     gy = np.asarray(gy, dtype=np.float64)
     return np.stack([BT601[0] * gy, BT601[1] * gy, BT601[2] * gy])
+
+
+# --------------------------------------------------------------------------
+# Spatial pooling of a quality map (Spatial and Temporal Aggregation section).
+# q is the map of one frame; n = number of map positions.  Readings:
+#   * standard deviations are population ones (divide by n), as the mean-
+#     deviation equation with p = 2 makes them;
+#   * the mean-deviation Minkowski distance uses |Q - mu|^p;
+#   * distortion-weighted pooling with all weights zero (every Q = 1) gives 1;
+#   * quartiles and the median are linear interpolation between the two
+#     nearest order statistics at rank (n - 1) q;
+#   * percentile pooling divides the m = ceil(p_s n / 100) smallest values by
+#     r_s (ties at the cut do not change the result).
+# --------------------------------------------------------------------------
+def pool_mean(q: np.ndarray) -> float:
+    """Arithmetic mean of the map (the baseline pooling)."""
+    return mean_pool(q)
+
+
+def pool_cov(q: np.ndarray) -> float:
+    """Coefficient of variation sigma_Q / mu_Q (the CoV equation of the
+    Spatial and Temporal Aggregation section, after the MOVIE index)."""
+    v = np.asarray(q, dtype=np.float64).ravel()
+    mu = math.fsum(v) / v.size
+    var = math.fsum((v - mu) ** 2) / v.size
+    return math.sqrt(var) / mu
+
+
+def pool_md(q: np.ndarray, p: float, o: float) -> float:
+    """Mean-deviation pooling: (((1/n) sum |Q - mu|^p)^(1/p))^o."""
+    v = np.asarray(q, dtype=np.float64).ravel()
+    mu = math.fsum(v) / v.size
+    d = math.fsum(np.abs(v - mu) ** p) / v.size
+    return (d ** (1.0 / p)) ** o
+
+
+def pool_minkowski(q: np.ndarray, p: float) -> float:
+    """Minkowski pooling of the dissimilarity: (1/n) sum (1 - Q)^p."""
+    v = np.asarray(q, dtype=np.float64).ravel()
+    return math.fsum((1.0 - v) ** p) / v.size
+
+
+def pool_distortion_weighted(q: np.ndarray, p: float) -> float:
+    """Distortion-weighted pooling: sum (1-Q)^p Q / sum (1-Q)^p."""
+    v = np.asarray(q, dtype=np.float64).ravel()
+    w = (1.0 - v) ** p
+    den = math.fsum(w)
+    if den == 0.0:
+        return 1.0
+    return math.fsum(w * v) / den
+
+
+def _percentile_linear(sorted_v: np.ndarray, frac: float) -> float:
+    h = (sorted_v.size - 1) * frac
+    lo = int(math.floor(h))
+    hi = min(lo + 1, sorted_v.size - 1)
+    return float(sorted_v[lo] + (h - lo) * (sorted_v[hi] - sorted_v[lo]))
+
+
+def pool_five_number(q: np.ndarray) -> float:
+    """Five-number summary: (min + Q1 + median + Q3 + max) / 5."""
+    s = np.sort(np.asarray(q, dtype=np.float64).ravel())
+    parts = [s[0], _percentile_linear(s, 0.25), _percentile_linear(s, 0.5), _percentile_linear(s, 0.75), s[-1]]
+    return math.fsum(parts) / 5.0
+
+
+def pool_percentile(q: np.ndarray, p_s: float, r_s: float) -> float:
+    """Percentile pooling: the lowest p_s percent of the map divided by r_s,
+    then the mean."""
+    s = np.sort(np.asarray(q, dtype=np.float64).ravel())
+    m = int(math.ceil(p_s * s.size / 100.0))
+    return (math.fsum(s[:m] / r_s) + math.fsum(s[m:])) / s.size

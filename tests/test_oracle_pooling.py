@@ -1,0 +1,82 @@
+"""Pins of the oracle's spatial pooling functions (Spatial and Temporal
+Aggregation section) against closed forms, numpy's own statistics and brute
+force on small maps."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def _map(seed, shape=(37, 53), lo=-0.2, hi=1.0):
+    return np.random.default_rng(seed).uniform(lo, hi, shape)
+
+
+def test_mean_is_the_baseline_pool():
+    q = _map(0)
+    assert O.pool_mean(q) == O.mean_pool(q)
+
+
+@pytest.mark.parametrize("c", [0.3, 0.97, 1.0])
+def test_constant_map_closed_forms(c):
+    q = np.full((9, 7), c)
+    assert O.pool_cov(q) == 0.0
+    assert O.pool_md(q, 2, 1) == 0.0
+    assert O.pool_minkowski(q, 4) == pytest.approx((1 - c) ** 4, abs=1e-15)
+    assert O.pool_distortion_weighted(q, 2) == pytest.approx(c, abs=1e-15)
+    assert O.pool_five_number(q) == pytest.approx(c, abs=1e-15)
+    n, m = q.size, math.ceil(6 * q.size / 100)
+    assert O.pool_percentile(q, 6, 4000) == pytest.approx((m * c / 4000 + (n - m) * c) / n, abs=1e-15)
+
+
+def test_cov_of_a_two_valued_map():
+    a, b = 0.9, 0.5
+    q = np.array([a, b] * 50)
+    # sigma = |a - b| / 2, mu = (a + b) / 2
+    assert O.pool_cov(q) == pytest.approx(abs(a - b) / (a + b), rel=1e-14)
+
+
+def test_cov_and_mean_deviation_against_numpy():
+    q = _map(1)
+    assert O.pool_cov(q) == pytest.approx(np.std(q) / np.mean(q), rel=1e-12)
+    assert O.pool_md(q, 2, 1) == pytest.approx(np.std(q), rel=1e-12)
+    assert O.pool_md(q, 2, 3) == pytest.approx(np.std(q) ** 3, rel=1e-12)
+    d4 = np.mean(np.abs(q - q.mean()) ** 4) ** 0.25
+    assert O.pool_md(q, 4, 1) == pytest.approx(d4, rel=1e-12)
+
+
+def test_minkowski_order_one_is_one_minus_the_mean():
+    q = _map(2)
+    assert O.pool_minkowski(q, 1) == pytest.approx(1 - q.mean(), abs=1e-14)
+
+
+def test_distortion_weighted_limits():
+    q = _map(3, lo=0.0, hi=0.99)
+    # p = 0: every weight is one -> the mean
+    assert O.pool_distortion_weighted(q, 0) == pytest.approx(q.mean(), abs=1e-14)
+    # weights (1 - Q)^p for p = 1 written out
+    w = 1 - q
+    assert O.pool_distortion_weighted(q, 1) == pytest.approx((w * q).sum() / w.sum(), rel=1e-13)
+    # the weighted mean lies below the mean (low scores weigh more)
+    assert O.pool_distortion_weighted(q, 2) < q.mean()
+
+
+def test_five_number_summary_against_numpy_percentiles():
+    for seed, shape in ((4, (37, 53)), (5, (1, 1)), (6, (2, 3)), (7, (4, 4))):
+        q = _map(seed, shape)
+        want = (q.min() + np.percentile(q, 25) + np.median(q) + np.percentile(q, 75) + q.max()) / 5
+        assert O.pool_five_number(q) == pytest.approx(want, rel=1e-14, abs=1e-15)
+
+
+def test_percentile_pooling_brute_force():
+    q = _map(8, (5, 6))
+    n = q.size
+    for p_s, r_s in itertools.product((0.0, 6.0, 25.0, 50.0, 100.0), (1.0, 4.0, 4000.0)):
+        m = math.ceil(p_s * n / 100)
+        order = sorted(q.ravel().tolist())
+        want = (sum(v / r_s for v in order[:m]) + sum(order[m:])) / n
+        assert O.pool_percentile(q, p_s, r_s) == pytest.approx(want, rel=1e-13, abs=1e-15)
+    # r_s = 1 leaves the map unchanged
+    assert O.pool_percentile(q, 30, 1.0) == pytest.approx(q.mean(), abs=1e-15)
