@@ -180,6 +180,50 @@ ssimx_status ssimx_box_sums(int k, int stride, int algo, const ssimx_image* ref,
 ssimx_status ssimx_integral_images(const ssimx_image* ref, const ssimx_image* dis, int batch,
                                    uint32_t* sat_out, void* stream);
 
+/* ---------------- spatial pooling of quality maps -------------------------
+ * The pooling methods of the Spatial and Temporal Aggregation section,
+ * applied per frame to a float32 map (e.g. the output of ssim_map).  With
+ * n = w*h map positions and mu the map mean:
+ *   MEAN             (1/n) sum Q
+ *   COV              sigma_Q / mu, population sigma (the CoV equation)
+ *   MEAN_DEV         (((1/n) sum |Q - mu|^p)^(1/p))^o      (p > 0)
+ *   MINKOWSKI        (1/n) sum (1 - Q)^p                   (p > 0)
+ *   DIST_WEIGHTED    sum (1-Q)^p Q / sum (1-Q)^p; 1 when every Q == 1 (p >= 0)
+ *   FIVE_NUMBER      (min + Q1 + median + Q3 + max) / 5, quantiles by linear
+ *                    interpolation between the order statistics at rank
+ *                    floor((n-1) q) and the next one
+ *   PERCENTILE       the m = ceil(p n / 100) smallest values divided by r,
+ *                    then the mean                          (0 <= p <= 100, r > 0)
+ * Sums are accumulated in float64 in a fixed order (deterministic); order
+ * statistics are exact (radix select on the float bit patterns). */
+typedef enum {
+  SSIMX_POOL_MEAN = 0,
+  SSIMX_POOL_COV = 1,
+  SSIMX_POOL_MEAN_DEV = 2,
+  SSIMX_POOL_MINKOWSKI = 3,
+  SSIMX_POOL_DIST_WEIGHTED = 4,
+  SSIMX_POOL_FIVE_NUMBER = 5,
+  SSIMX_POOL_PERCENTILE = 6
+} ssimx_pool_kind;
+
+typedef struct {
+  ssimx_pool_kind kind;
+  double p;  /* order / exponent / percentile, per kind */
+  double o;  /* outer exponent of MEAN_DEV */
+  double r;  /* divisor of PERCENTILE */
+} ssimx_pool;
+
+/* Workspace bytes of ssimx_pool_map (host only). */
+ssimx_status ssimx_pool_workspace_size(const ssimx_pool* pool, int w, int h, int batch, size_t* bytes);
+
+/* map: float32 device, element (b, i, j) at b*batch_stride + i*pitch + j;
+ * out: float32 device [batch].  Host validation: EINVAL for a bad kind or
+ * parameter, null pointers, pitch < w; ETOOSMALL for an empty map; ENOTSUP for
+ * maps of 2^31 positions or more; EWORKSPACE for a missing or short workspace.
+ * Asynchronous on `stream`. */
+ssimx_status ssimx_pool_map(const ssimx_pool* pool, const float* map, int w, int h, long long pitch,
+                            long long batch_stride, int batch, float* out, void* ws, size_t ws_bytes, void* stream);
+
 /* Colour front end of the differentiable-loss workload: BT.601 luma
  * Y = 0.299 R + 0.587 G + 0.114 B of planar RGB (the paper's Channel-wise SSIM
  * subsection prints the BT.709 matrix; BT.601 weights are used here).

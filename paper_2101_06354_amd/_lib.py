@@ -39,6 +39,13 @@ class Pair(ctypes.Structure):
     _fields_ = [("ref", Image), ("dis", Image), ("p", Params), ("map_out", c_void_p), ("map_pitch", c_int64)]
 
 
+class Pool(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("p", c_double), ("o", c_double), ("r", c_double)]
+
+
+POOL_MEAN, POOL_COV, POOL_MEAN_DEV, POOL_MINKOWSKI, POOL_DIST_WEIGHTED, POOL_FIVE_NUMBER, POOL_PERCENTILE = range(7)
+
+
 class SSIMXError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -87,6 +94,9 @@ _SIGS = {
     "ssimx_tune_cache_save": (c_int, [c_char_p]),
     "ssimx_set_tile_override": (c_int, [c_int]),
     "ssimx_num_tile_configs": (c_int, []),
+    "ssimx_pool_workspace_size": (c_int, [POINTER(Pool), c_int, c_int, c_int, POINTER(c_size_t)]),
+    "ssimx_pool_map": (c_int, [POINTER(Pool), c_void_p, c_int, c_int, c_int64, c_int64, c_int, c_void_p, c_void_p,
+                               c_size_t, c_void_p]),
     "ssimx_strerror": (c_char_p, [c_int]),
     "ssimx_last_hip_error": (c_int, []),
     "ssimx_version": (c_int, []),

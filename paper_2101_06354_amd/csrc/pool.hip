@@ -1,0 +1,411 @@
+// Spatial pooling of quality maps (Spatial and Temporal Aggregation section):
+// mean, coefficient of variation, mean deviation, Minkowski and
+// distortion-weighted pooling as sums over the map, and the five-number
+// summary and percentile pooling from exact order statistics.
+//
+// Sums: each block takes map rows round-robin and accumulates up to two
+// float64 sums per frame; a finishing kernel adds the block sums of a frame in
+// a fixed order (deterministic) and forms the pooled value.
+//
+// Order statistics: radix select on the order-preserving uint32 image of the
+// float map values, 8 bits per pass from the top.  Per pass every block
+// histograms the keys that match each target's prefix in LDS and adds its
+// histogram to the frame's global histogram; a step kernel then picks, per
+// target, the bin that holds the wanted rank, extends the prefix and clears
+// the histogram for the next pass.  After four passes the prefix is the exact
+// key of the order statistic.
+#include "launch.hpp"
+#include "ssimx_internal.hpp"
+#include "host_common.hpp"
+
+#include <math.h>
+
+namespace ssimx {
+
+namespace {
+
+constexpr int kPoolNT = 256;
+constexpr int kMaxTargets = 8;
+
+struct MapArg {
+  const float* map;
+  int w, h;
+  int64_t pitch, bstride;
+};
+
+__device__ __forceinline__ uint32_t ordered_key(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_value(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// d^p for d >= 0: repeated products for small integer p, else powf.
+__device__ __forceinline__ double pow_term(double d, double p, int ip) {
+  if (ip >= 0) {
+    double r = 1.0;
+    for (int i = 0; i < ip; ++i) r *= d;
+    return r;
+  }
+  return (double)powf((float)d, (float)p);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// kind: 0 sum Q | 1 sum Q, Q^2 | 2 sum |Q - mu|^p | 3 sum (1-Q)^p | 4 sum (1-Q)^p Q, (1-Q)^p
+// | 5 sum of Q below the per-frame threshold, and their count
+__global__ __launch_bounds__(kPoolNT) void pool_sums_kernel(MapArg a, int kind, double p, int ip, const double* mu,
+                                                            const uint32_t* thr_key, double* partial) {
+  __shared__ double red[2][kPoolNT / 64];
+  const int frame = blockIdx.y;
+  const float* m = a.map + (int64_t)frame * a.bstride;
+  const double muf = mu ? mu[frame] : 0.0;
+  const uint32_t tk = thr_key ? thr_key[(int64_t)frame * 2 * kMaxTargets] : 0u;  // target 0's key
+  double s0 = 0.0, s1 = 0.0;
+  for (int r = blockIdx.x; r < a.h; r += gridDim.x) {
+    const float* row = m + (int64_t)r * a.pitch;
+    for (int c = threadIdx.x; c < a.w; c += kPoolNT) {
+      const float qf = row[c];
+      const double q = (double)qf;
+      switch (kind) {
+        case 0: s0 += q; break;
+        case 1: s0 += q; s1 += q * q; break;
+        case 2: s0 += pow_term(fabs(q - muf), p, ip); break;
+        case 3: s0 += pow_term(1.0 - q, p, ip); break;
+        case 4: {
+          const double wgt = pow_term(1.0 - q, p, ip);
+          s0 += wgt * q;
+          s1 += wgt;
+          break;
+        }
+        default:  // below the m-th smallest value of the frame
+          if (ordered_key(qf) < tk) {
+            s0 += q;
+            s1 += 1.0;
+          }
+          break;
+      }
+    }
+  }
+  s0 = wave_sum_d(s0);
+  s1 = wave_sum_d(s1);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wid] = s0;
+    red[1][wid] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = 0.0, t1 = 0.0;
+    for (int w = 0; w < kPoolNT / 64; ++w) {
+      t0 += red[0][w];
+      t1 += red[1][w];
+    }
+    double* o = partial + ((int64_t)frame * gridDim.x + blockIdx.x) * 2;
+    o[0] = t0;
+    o[1] = t1;
+  }
+}
+
+// Fixed-order sum of a frame's block sums.
+__device__ __forceinline__ void frame_sums(const double* partial, int nblk, int frame, double& s0, double& s1) {
+  s0 = s1 = 0.0;
+  const double* p = partial + (int64_t)frame * nblk * 2;
+  for (int b = 0; b < nblk; ++b) {
+    s0 += p[2 * b];
+    s1 += p[2 * b + 1];
+  }
+}
+
+struct FinishArgs {
+  int kind;      // ssimx_pool_kind
+  int stage;     // 0: final value; 1: store mu (first pass of the mean deviation)
+  double p, o, r;
+  double n;
+  int m;         // percentile pooling: number of values divided by r
+  int nt;        // order-statistic targets
+  double frac[kMaxTargets];  // interpolation weights for the five-number summary
+};
+
+__global__ void pool_finish_kernel(const double* partial, const double* total, int nblk, int batch, FinishArgs f,
+                                   const uint32_t* keys, double* mu_out, float* out, int64_t out_stride) {
+  const int frame = blockIdx.x * blockDim.x + threadIdx.x;
+  if (frame >= batch) return;
+  double s0 = 0.0, s1 = 0.0;
+  if (partial) frame_sums(partial, nblk, frame, s0, s1);
+  double v = 0.0;
+  switch (f.kind) {
+    case SSIMX_POOL_MEAN: v = s0 / f.n; break;
+    case SSIMX_POOL_COV: {
+      const double mean = s0 / f.n;
+      const double var = fmax(s1 / f.n - mean * mean, 0.0);
+      v = sqrt(var) / mean;
+      break;
+    }
+    case SSIMX_POOL_MEAN_DEV:
+      if (f.stage == 1) {
+        mu_out[frame] = s0 / f.n;
+        return;
+      }
+      v = pow(pow(s0 / f.n, 1.0 / f.p), f.o);
+      break;
+    case SSIMX_POOL_MINKOWSKI: v = s0 / f.n; break;
+    case SSIMX_POOL_DIST_WEIGHTED: v = s1 == 0.0 ? 1.0 : s0 / s1; break;
+    case SSIMX_POOL_FIVE_NUMBER: {
+      const uint32_t* k = keys + (int64_t)frame * 2 * kMaxTargets;  // (prefix, rank) pairs
+      double q[kMaxTargets];
+      for (int t = 0; t < f.nt; ++t) q[t] = (double)key_value(k[2 * t]);
+      // targets: min, max, then (lo, hi) pairs of Q1, median, Q3
+      double acc = q[0] + q[1];
+      for (int j = 0; j < 3; ++j) acc += q[2 + 2 * j] + f.frac[j] * (q[3 + 2 * j] - q[2 + 2 * j]);
+      v = acc / 5.0;
+      break;
+    }
+    case SSIMX_POOL_PERCENTILE: {
+      double tot = 0.0, tmp = 0.0;
+      frame_sums(total, nblk, frame, tot, tmp);
+      if (f.m == 0) {
+        v = tot / f.n;
+      } else {
+        const double thr = (double)key_value(keys[(int64_t)frame * 2 * kMaxTargets]);
+        // s0 = sum of the values strictly below the m-th smallest, s1 = their count
+        const double low = s0 + ((double)f.m - s1) * thr;
+        v = (low / f.r + (tot - low)) / f.n;
+      }
+      break;
+    }
+    default: v = 0.0; break;
+  }
+  out[(int64_t)frame * out_stride] = (float)v;
+}
+
+// ---------------------------------------------------------------- radix select
+struct SelArgs {
+  MapArg a;
+  int nt;
+  uint32_t* state;  // [batch][kMaxTargets][2] = (prefix, remaining rank)
+  uint32_t* hist;   // [batch][kMaxTargets][256]
+};
+
+struct Ranks {
+  uint32_t r[kMaxTargets];
+};
+
+__global__ void sel_init_kernel(SelArgs s, int batch, Ranks ranks) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < batch * kMaxTargets * 256) s.hist[i] = 0u;
+  if (i < batch * kMaxTargets) {
+    s.state[2 * i] = 0u;
+    s.state[2 * i + 1] = ranks.r[i % kMaxTargets];
+  }
+}
+
+__global__ __launch_bounds__(kPoolNT) void sel_hist_kernel(SelArgs s, int shift) {
+  __shared__ uint32_t h[kMaxTargets][256];
+  __shared__ uint32_t pre[kMaxTargets];
+  const int frame = blockIdx.y;
+  for (int i = threadIdx.x; i < kMaxTargets * 256; i += kPoolNT) (&h[0][0])[i] = 0u;
+  if (threadIdx.x < kMaxTargets) pre[threadIdx.x] = s.state[((int64_t)frame * kMaxTargets + threadIdx.x) * 2];
+  __syncthreads();
+  const uint32_t himask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
+  const float* m = s.a.map + (int64_t)frame * s.a.bstride;
+  for (int r = blockIdx.x; r < s.a.h; r += gridDim.x) {
+    const float* row = m + (int64_t)r * s.a.pitch;
+    for (int c = threadIdx.x; c < s.a.w; c += kPoolNT) {
+      const uint32_t k = ordered_key(row[c]);
+      const uint32_t bin = (k >> shift) & 255u;
+      for (int t = 0; t < s.nt; ++t)
+        if (((k ^ pre[t]) & himask) == 0u) atomicAdd(&h[t][bin], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* g = s.hist + (int64_t)frame * kMaxTargets * 256;
+  for (int i = threadIdx.x; i < s.nt * 256; i += kPoolNT) {
+    const uint32_t v = (&h[0][0])[i];
+    if (v) atomicAdd(&g[i], v);
+  }
+}
+
+// One thread per (frame, target): find the bin holding the remaining rank,
+// extend the prefix, clear the histogram row for the next pass.
+__global__ void sel_step_kernel(SelArgs s, int batch, int shift) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch * kMaxTargets || (i % kMaxTargets) >= s.nt) return;
+  uint32_t* st = s.state + 2 * (int64_t)i;
+  uint32_t* g = s.hist + (int64_t)i * 256;
+  const uint32_t rank = st[1];
+  uint32_t cum = 0u, bin = 255u;
+  for (int b = 0; b < 256; ++b) {
+    const uint32_t c = g[b];
+    if (rank < cum + c) {
+      bin = (uint32_t)b;
+      break;
+    }
+    cum += c;
+  }
+  st[0] |= bin << shift;
+  st[1] = rank - cum;
+  for (int b = 0; b < 256; ++b) g[b] = 0u;
+}
+
+int blocks_per_frame(int h) { return h < 64 ? h : 64; }
+
+}  // namespace
+
+size_t pool_ws_bytes(const ssimx_pool* pl, int w, int h, int batch) {
+  (void)w;
+  Ws ws;
+  const int nblk = blocks_per_frame(h);
+  ws.take(sizeof(double) * 2 * (size_t)batch * nblk);  // block sums
+  ws.take(sizeof(double) * 2 * (size_t)batch * nblk);  // second set (totals)
+  ws.take(sizeof(double) * (size_t)batch);              // per-frame mean
+  if (pl->kind == SSIMX_POOL_FIVE_NUMBER || pl->kind == SSIMX_POOL_PERCENTILE) {
+    ws.take(sizeof(uint32_t) * 2 * kMaxTargets * (size_t)batch);
+    ws.take(sizeof(uint32_t) * 256 * kMaxTargets * (size_t)batch);
+  }
+  return ws.used;
+}
+
+ssimx_status check_pool(const ssimx_pool* pl) {
+  if (!pl) return SSIMX_EINVAL;
+  if (!isfinite(pl->p) || !isfinite(pl->o) || !isfinite(pl->r)) return SSIMX_EINVAL;
+  switch (pl->kind) {
+    case SSIMX_POOL_MEAN:
+    case SSIMX_POOL_COV:
+    case SSIMX_POOL_FIVE_NUMBER: return SSIMX_OK;
+    case SSIMX_POOL_MEAN_DEV: return pl->p > 0.0 ? SSIMX_OK : SSIMX_EINVAL;
+    case SSIMX_POOL_MINKOWSKI: return pl->p > 0.0 ? SSIMX_OK : SSIMX_EINVAL;
+    case SSIMX_POOL_DIST_WEIGHTED: return pl->p >= 0.0 ? SSIMX_OK : SSIMX_EINVAL;
+    case SSIMX_POOL_PERCENTILE: return (pl->p >= 0.0 && pl->p <= 100.0 && pl->r > 0.0) ? SSIMX_OK : SSIMX_EINVAL;
+    default: return SSIMX_EINVAL;
+  }
+}
+
+static int int_power(double p) {
+  return (p == floor(p) && p >= 0.0 && p <= 16.0) ? (int)p : -1;
+}
+
+ssimx_status pool_run(const ssimx_pool* pl, const float* map, int w, int h, int64_t pitch, int64_t bstride,
+                      int batch, float* out, int64_t out_stride, void* ws, hipStream_t st) {
+  const int nblk = blocks_per_frame(h);
+  Ws lay;
+  double* partial = (double*)((char*)ws + lay.take(sizeof(double) * 2 * (size_t)batch * nblk));
+  double* total = (double*)((char*)ws + lay.take(sizeof(double) * 2 * (size_t)batch * nblk));
+  double* mu = (double*)((char*)ws + lay.take(sizeof(double) * (size_t)batch));
+  MapArg a{map, w, h, pitch, bstride};
+  const double n = (double)w * (double)h;
+  FinishArgs f{};
+  f.kind = pl->kind;
+  f.p = pl->p;
+  f.o = pl->o;
+  f.r = pl->r;
+  f.n = n;
+  const dim3 grid(nblk, batch), fin((batch + 63) / 64);
+  const int ip = int_power(pl->p);
+  int err = 0;
+  switch (pl->kind) {
+    case SSIMX_POOL_MEAN:
+    case SSIMX_POOL_COV:
+    case SSIMX_POOL_MINKOWSKI:
+    case SSIMX_POOL_DIST_WEIGHTED: {
+      const int k = pl->kind == SSIMX_POOL_MEAN ? 0 : pl->kind == SSIMX_POOL_COV ? 1
+                  : pl->kind == SSIMX_POOL_MINKOWSKI ? 3 : 4;
+      hipLaunchKernelGGL(pool_sums_kernel, grid, dim3(kPoolNT), 0, st, a, k, pl->p, ip, nullptr, nullptr, partial);
+      hipLaunchKernelGGL(pool_finish_kernel, fin, dim3(64), 0, st, partial, nullptr, nblk, batch, f, nullptr, nullptr,
+                         out, out_stride);
+      break;
+    }
+    case SSIMX_POOL_MEAN_DEV: {
+      hipLaunchKernelGGL(pool_sums_kernel, grid, dim3(kPoolNT), 0, st, a, 0, 0.0, 1, nullptr, nullptr, partial);
+      f.stage = 1;
+      hipLaunchKernelGGL(pool_finish_kernel, fin, dim3(64), 0, st, partial, nullptr, nblk, batch, f, nullptr, mu,
+                         out, out_stride);
+      hipLaunchKernelGGL(pool_sums_kernel, grid, dim3(kPoolNT), 0, st, a, 2, pl->p, ip, mu, nullptr, partial);
+      f.stage = 0;
+      hipLaunchKernelGGL(pool_finish_kernel, fin, dim3(64), 0, st, partial, nullptr, nblk, batch, f, nullptr, nullptr,
+                         out, out_stride);
+      break;
+    }
+    default: {  // order statistics
+      uint32_t* state = (uint32_t*)((char*)ws + lay.take(sizeof(uint32_t) * 2 * kMaxTargets * (size_t)batch));
+      uint32_t* hist = (uint32_t*)((char*)ws + lay.take(sizeof(uint32_t) * 256 * kMaxTargets * (size_t)batch));
+      uint32_t ranks[kMaxTargets] = {};
+      const uint32_t last = (uint32_t)(w * (int64_t)h - 1);
+      int nt = 0;
+      if (pl->kind == SSIMX_POOL_FIVE_NUMBER) {
+        ranks[0] = 0;
+        ranks[1] = last;
+        const double qs[3] = {0.25, 0.5, 0.75};
+        for (int j = 0; j < 3; ++j) {
+          const double hpos = (double)last * qs[j];
+          const uint32_t lo = (uint32_t)floor(hpos);
+          ranks[2 + 2 * j] = lo;
+          ranks[3 + 2 * j] = lo < last ? lo + 1 : lo;
+          f.frac[j] = hpos - (double)lo;
+        }
+        nt = 8;
+      } else {
+        f.m = (int)ceil(pl->p * n / 100.0);
+        if (f.m > (int)(last + 1)) f.m = (int)(last + 1);
+        ranks[0] = f.m > 0 ? (uint32_t)(f.m - 1) : 0u;
+        nt = 1;
+      }
+      f.nt = nt;
+      SelArgs s{a, nt, state, hist};
+      const int ninit = batch * kMaxTargets * 256;
+      Ranks rk{};
+      for (int t = 0; t < kMaxTargets; ++t) rk.r[t] = ranks[t];
+      hipLaunchKernelGGL(sel_init_kernel, dim3((ninit + 255) / 256), dim3(256), 0, st, s, batch, rk);
+      for (int shift = 24; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(sel_hist_kernel, grid, dim3(kPoolNT), 0, st, s, shift);
+        hipLaunchKernelGGL(sel_step_kernel, dim3((batch * kMaxTargets + 63) / 64), dim3(64), 0, st, s, batch, shift);
+      }
+      if (pl->kind == SSIMX_POOL_PERCENTILE) {
+        // totals, then the sum and count of the values below the threshold
+        hipLaunchKernelGGL(pool_sums_kernel, grid, dim3(kPoolNT), 0, st, a, 0, 0.0, 1, nullptr, nullptr, total);
+        hipLaunchKernelGGL(pool_sums_kernel, grid, dim3(kPoolNT), 0, st, a, 5, 0.0, 1, nullptr, state, partial);
+      }
+      hipLaunchKernelGGL(pool_finish_kernel, fin, dim3(64), 0, st,
+                         pl->kind == SSIMX_POOL_PERCENTILE ? partial : nullptr, total, nblk, batch, f, state, nullptr,
+                         out, out_stride);
+      break;
+    }
+  }
+  err = (int)hipGetLastError();
+  return hip_status(err);
+}
+
+}  // namespace ssimx
+
+using namespace ssimx;
+
+extern "C" {
+
+ssimx_status ssimx_pool_workspace_size(const ssimx_pool* pool, int w, int h, int batch, size_t* bytes) {
+  ssimx_status s;
+  if ((s = check_pool(pool)) != SSIMX_OK) return s;
+  if (!bytes || batch < 1) return SSIMX_EINVAL;
+  if (w < 1 || h < 1) return SSIMX_ETOOSMALL;
+  *bytes = pool_ws_bytes(pool, w, h, batch);
+  return SSIMX_OK;
+}
+
+ssimx_status ssimx_pool_map(const ssimx_pool* pool, const float* map, int w, int h, long long pitch,
+                            long long batch_stride, int batch, float* out, void* ws, size_t ws_bytes, void* stream) {
+  ssimx_status s;
+  if ((s = check_pool(pool)) != SSIMX_OK) return s;
+  if (!map || !out || batch < 1) return SSIMX_EINVAL;
+  if (w < 1 || h < 1) return SSIMX_ETOOSMALL;
+  if (pitch < w || (batch > 1 && batch_stride < pitch * (long long)h)) return SSIMX_EINVAL;
+  if ((long long)w * h >= (1ll << 31)) return SSIMX_ENOTSUP;
+  if (!ws || ws_bytes < pool_ws_bytes(pool, w, h, batch)) return SSIMX_EWORKSPACE;
+  return pool_run(pool, map, w, h, pitch, batch_stride, batch, out, 1, ws, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -227,6 +227,29 @@ def integral_images(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     return out
 
 
+_POOLS = {"mean": L.POOL_MEAN, "cov": L.POOL_COV, "mean_dev": L.POOL_MEAN_DEV, "minkowski": L.POOL_MINKOWSKI,
+          "dist_weighted": L.POOL_DIST_WEIGHTED, "five_number": L.POOL_FIVE_NUMBER, "percentile": L.POOL_PERCENTILE}
+
+
+def pool(qmap: torch.Tensor, kind: str = "cov", p: float = 0.0, o: float = 1.0, r: float = 1.0) -> torch.Tensor:
+    """Spatial pooling of quality maps (B, H, W) or (H, W), float32 on the
+    device -> float32 [B].  kind: mean | cov | mean_dev (p, o) | minkowski (p)
+    | dist_weighted (p) | five_number | percentile (p in percent, r)."""
+    m = qmap.unsqueeze(0) if qmap.dim() == 2 else qmap
+    if m.dim() != 3 or m.dtype != torch.float32 or not m.is_cuda or m.stride(2) != 1:
+        raise ValueError("qmap must be a float32 device tensor (B, H, W) with contiguous rows")
+    pl = L.Pool(_POOLS[kind], float(p), float(o), float(r))
+    b, h, w = m.shape
+    n = ctypes.c_size_t()
+    L.check(L.lib.ssimx_pool_workspace_size(ctypes.byref(pl), w, h, b, ctypes.byref(n)), "ssimx_pool_workspace_size")
+    ws = _workspace(n.value, m.device)
+    out = torch.empty(b, dtype=torch.float32, device=m.device)
+    st = L.lib.ssimx_pool_map(ctypes.byref(pl), m.data_ptr(), w, h, m.stride(1), m.stride(0), b, out.data_ptr(),
+                              ws.data_ptr(), ws.numel(), _stream(m))
+    L.check(st, "ssimx_pool_map")
+    return out
+
+
 def rgb_to_luma(rgb: torch.Tensor) -> torch.Tensor:
     """BT.601 luma of planar RGB (B, 3, H, W) or (3, H, W), float32/bfloat16
     -> float32 (B, H, W)."""

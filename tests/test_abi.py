@@ -153,3 +153,33 @@ def test_plan_create_validates_before_allocating(L):
     assert L.lib.ssimx_plan_create(arr, 1, None, ctypes.byref(h)) == L.EINVAL
     assert L.lib.ssimx_plan_create(arr, 0, None, ctypes.byref(h)) == L.EINVAL
     assert L.lib.ssimx_plan_destroy(None) == L.EINVAL
+
+
+def _pool(L, kind, p=0.0, o=1.0, r=1.0):
+    return L.Pool(kind, p, o, r)
+
+
+@pytest.mark.parametrize("kind,p,o,r", [(9, 0, 1, 1), (-1, 0, 1, 1), (2, 0.0, 1, 1), (3, -1.0, 1, 1),
+                                        (4, -0.5, 1, 1), (6, 101.0, 1, 1), (6, 5.0, 1, 0.0),
+                                        (1, float("nan"), 1, 1)])
+def test_pool_parameters_rejected_on_host(L, kind, p, o, r):
+    n = ctypes.c_size_t()
+    pl = _pool(L, kind, p, o, r)
+    assert L.lib.ssimx_pool_workspace_size(ctypes.byref(pl), 64, 64, 1, ctypes.byref(n)) == L.EINVAL
+    assert L.lib.ssimx_pool_map(ctypes.byref(pl), 12345, 64, 64, 64, 4096, 1, 12345, 12345, 1 << 20,
+                                None) == L.EINVAL
+
+
+def test_pool_map_validates_before_launch(L):
+    pl = _pool(L, L.POOL_COV)
+    n = ctypes.c_size_t()
+    assert L.lib.ssimx_pool_workspace_size(ctypes.byref(pl), 64, 64, 2, ctypes.byref(n)) == L.OK
+    assert n.value > 0
+    f = L.lib.ssimx_pool_map
+    assert f(ctypes.byref(pl), None, 64, 64, 64, 4096, 1, 12345, 12345, n.value, None) == L.EINVAL
+    assert f(ctypes.byref(pl), 12345, 64, 64, 32, 4096, 1, 12345, 12345, n.value, None) == L.EINVAL
+    assert f(ctypes.byref(pl), 12345, 64, 64, 64, 100, 2, 12345, 12345, n.value, None) == L.EINVAL
+    assert f(ctypes.byref(pl), 12345, 0, 64, 64, 4096, 1, 12345, 12345, n.value, None) == L.ETOOSMALL
+    assert f(ctypes.byref(pl), 12345, 64, 64, 64, 4096, 1, 12345, None, 0, None) == L.EWORKSPACE
+    big = _pool(L, L.POOL_FIVE_NUMBER)
+    assert L.lib.ssimx_pool_workspace_size(ctypes.byref(big), 64, 64, 2, ctypes.byref(n)) == L.OK
