@@ -46,6 +46,7 @@ __all__ = [
     "msssim_backward", "rgb_to_y_bt601", "y_grad_to_rgb_bt601",
     "MS_WEIGHTS", "pool_mean", "pool_cov", "pool_md", "pool_minkowski",
     "pool_distortion_weighted", "pool_five_number", "pool_percentile",
+    "scale_factor", "downsample_avg", "scaled_pooled_ssim", "enhanced_ssim",
 ]
 
 # Exponents of the original five-scale MS-SSIM, as used by the configurations
@@ -595,3 +596,55 @@ def pool_percentile(q: np.ndarray, p_s: float, r_s: float) -> float:
     s = np.sort(np.asarray(q, dtype=np.float64).ravel())
     m = int(math.ceil(p_s * s.size / 100.0))
     return (math.fsum(s[:m] / r_s) + math.fsum(s[m:])) / s.size
+
+
+# --------------------------------------------------------------------------
+# Pre-scaling and the "Enhanced SSIM" composition.
+#   * the down-sampling transform of the Transforming-across-Scales
+#     subsection: Z = max(1, ceil(H / 256)), an f x f block average with
+#     decimation by f (odd remainders dropped, as for the 2x2 pyramid);
+#   * Enhanced SSIM (closing recommendation of the aggregation section):
+#     luma, rectangular 11x11 windows, stride 5, pre-scaling, CoV pooling.
+#     The rule that infers the factor from D/H is not printed; the factor is
+#     an argument and defaults to Z.
+# --------------------------------------------------------------------------
+def scale_factor(h: int) -> int:
+    """Z = max(1, ceil(H / 256)) of the Transforming-across-Scales subsection."""
+    return max(1, -(-int(h) // 256))
+
+
+def downsample_avg(a: np.ndarray, f: int) -> np.ndarray:
+    """f x f block means over the aligned blocks that fit (decimation by f)."""
+    a = _as_f64(a)
+    if f == 1:
+        return a.copy()
+    h, w = a.shape[0] // f, a.shape[1] // f
+    return a[:h * f, :w * f].reshape(h, f, w, f).mean(axis=(1, 3))
+
+
+_POOLERS = {
+    "mean": lambda q, p, o, r: pool_mean(q),
+    "cov": lambda q, p, o, r: pool_cov(q),
+    "mean_dev": lambda q, p, o, r: pool_md(q, p, o),
+    "minkowski": lambda q, p, o, r: pool_minkowski(q, p),
+    "dist_weighted": lambda q, p, o, r: pool_distortion_weighted(q, p),
+    "five_number": lambda q, p, o, r: pool_five_number(q),
+    "percentile": lambda q, p, o, r: pool_percentile(q, p, r),
+}
+
+
+def scaled_pooled_ssim(x, y, p: SSIMParams | None = None, factor: int = 1, pool: str = "mean",
+                       pp: float = 0.0, po: float = 1.0, pr: float = 1.0) -> float:
+    """Down-sample by `factor`, take the SSIM map with parameters p, pool it."""
+    xs, ys = downsample_avg(x, factor), downsample_avg(y, factor)
+    q = ssim_map(xs, ys, p)["map"]
+    return _POOLERS[pool](q, pp, po, pr)
+
+
+def enhanced_ssim(x, y, factor: int | None = None, L: float = 255.0) -> float:
+    """Enhanced SSIM: 11x11 rectangular window at stride 5 on the pre-scaled
+    luma, pooled by the coefficient of variation."""
+    C1, C2 = constants(0.01, 0.03, L)
+    p = SSIMParams(window="box", k=11, C1=C1, C2=C2, stride=5)
+    f = scale_factor(np.asarray(x).shape[0]) if factor is None else factor
+    return scaled_pooled_ssim(x, y, p, f, "cov")

@@ -80,3 +80,33 @@ def test_percentile_pooling_brute_force():
         assert O.pool_percentile(q, p_s, r_s) == pytest.approx(want, rel=1e-13, abs=1e-15)
     # r_s = 1 leaves the map unchanged
     assert O.pool_percentile(q, 30, 1.0) == pytest.approx(q.mean(), abs=1e-15)
+
+
+def test_scale_factor_rule():
+    assert [O.scale_factor(h) for h in (1, 255, 256, 257, 512, 513, 1080, 2160)] == [1, 1, 1, 2, 2, 3, 5, 9]
+
+
+def test_block_average_downsampling():
+    a = np.arange(7 * 11, dtype=np.float64).reshape(7, 11)
+    d = O.downsample_avg(a, 3)
+    assert d.shape == (2, 3)
+    assert d[1, 2] == a[3:6, 6:9].mean()
+    # factor 2 is the pyramid's 2x2 average
+    np.testing.assert_array_equal(O.downsample_avg(a, 2), O.downsample2x2(a))
+    np.testing.assert_array_equal(O.downsample_avg(a, 1), a)
+    # a constant plane stays constant at every factor
+    assert np.all(O.downsample_avg(np.full((20, 30), 7.0), 4) == 7.0)
+
+
+def test_enhanced_ssim_composition():
+    rng = np.random.default_rng(9)
+    x = rng.integers(0, 256, (300, 400)).astype(np.uint8)
+    y = np.clip(x + rng.integers(-20, 21, x.shape), 0, 255).astype(np.uint8)
+    # identical inputs: a map of ones, CoV 0
+    assert O.enhanced_ssim(x, x) == 0.0
+    # written out: factor 2 (H = 300), 11x11 box at stride 5, CoV pooling
+    C1, C2 = O.constants(0.01, 0.03, 255.0)
+    xs, ys = O.downsample_avg(x, 2), O.downsample_avg(y, 2)
+    q = O.ssim_map(xs, ys, O.SSIMParams(window="box", k=11, C1=C1, C2=C2, stride=5))["map"]
+    assert q.shape == ((150 - 11) // 5 + 1, (200 - 11) // 5 + 1)
+    assert O.enhanced_ssim(x, y) == pytest.approx(np.std(q) / np.mean(q), rel=1e-12)
