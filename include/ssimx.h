@@ -224,6 +224,21 @@ ssimx_status ssimx_pool_workspace_size(const ssimx_pool* pool, int w, int h, int
 ssimx_status ssimx_pool_map(const ssimx_pool* pool, const float* map, int w, int h, long long pitch,
                             long long batch_stride, int batch, float* out, void* ws, size_t ws_bytes, void* stream);
 
+/* Pre-scaled, pooled SSIM (Transforming-across-Scales subsection and the
+ * aggregation section): both planes are down-sampled by f x f block averages
+ * (f = factor; 0 selects the subsection's max(1, ceil(height / 256)); 1 keeps
+ * the planes), the SSIM map with params p is formed on the float32 result,
+ * and each frame's map is pooled by `pool`.  score_out: float32 device
+ * [batch].  The paper's "Enhanced SSIM" composition is p = {BOX, k 11,
+ * stride 5}, factor 0, pool COV.  The integral-image method needs integer
+ * planes, so it is ENOTSUP with a factor other than 1.  Workspace: size from
+ * ssimx_scaled_pooled_workspace_size. */
+ssimx_status ssimx_scaled_pooled_workspace_size(const ssimx_params* p, int factor, const ssimx_pool* pool, int dtype,
+                                                int w, int h, int batch, size_t* bytes);
+ssimx_status ssimx_scaled_pooled_ssim(const ssimx_params* p, int factor, const ssimx_pool* pool,
+                                      const ssimx_image* ref, const ssimx_image* dis, int batch, float* score_out,
+                                      void* ws, size_t ws_bytes, void* stream);
+
 /* Colour front end of the differentiable-loss workload: BT.601 luma
  * Y = 0.299 R + 0.587 G + 0.114 B of planar RGB (the paper's Channel-wise SSIM
  * subsection prints the BT.709 matrix; BT.601 weights are used here).

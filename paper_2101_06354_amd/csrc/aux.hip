@@ -93,6 +93,52 @@ int launch_downsample(int dtype, PlaneArg in, int W, int H, float* outx, float* 
   return (int)hipGetLastError();
 }
 
+// f x f block means (pre-scaling by an integer factor; remainders dropped),
+// float32 [batch][H/f][W/f].  The block sum is exact for integer planes and is
+// divided once (correctly rounded mean).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void downsample_f_kernel(PlaneArg xa, PlaneArg ya, int Wf, int Hf, int f,
+                                                             float* ox, float* oy) {
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= Wf * Hf) return;
+  const int frame = blockIdx.y;
+  const int r = idx / Wf, c = idx - r * Wf;
+  const int64_t o = (int64_t)frame * Wf * Hf + idx;
+  const float ff = (float)(f * f);
+  for (int which = 0; which < 2; ++which) {
+    const PlaneArg& pa = which ? ya : xa;
+    const T* P = (const T*)pa.data + (int64_t)frame * pa.bstride + (int64_t)(f * r) * pa.pitch + f * c;
+    float s = 0.f;
+    for (int i = 0; i < f; ++i)
+      for (int j = 0; j < f; ++j) s += to_f32<T>(P[(int64_t)i * pa.pitch + j]);
+    (which ? oy : ox)[o] = s / ff;
+  }
+}
+
+int launch_downsample_f(int dtype, PlaneArg x, PlaneArg y, int W, int H, int f, float* outx, float* outy, int batch,
+                        hipStream_t st) {
+  const int Wf = W / f, Hf = H / f;
+  if (f < 1 || Wf < 1 || Hf < 1) return (int)hipErrorInvalidValue;
+  dim3 grid((Wf * Hf + BLOCK - 1) / BLOCK, batch);
+  switch (dtype) {
+    case SSIMX_U8:
+      hipLaunchKernelGGL(downsample_f_kernel<uint8_t>, grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
+      break;
+    case SSIMX_U16:
+      hipLaunchKernelGGL(downsample_f_kernel<uint16_t>, grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
+      break;
+    case SSIMX_F32:
+      hipLaunchKernelGGL(downsample_f_kernel<float>, grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
+      break;
+    case SSIMX_BF16:
+      hipLaunchKernelGGL(downsample_f_kernel<bf16_t>, grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
+      break;
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
 struct MsWeights {
   float w[MAX_SCALES];
 };

@@ -63,6 +63,12 @@ ssimx_status ms_forward(const ssimx_params* p, const float* w, int n_scales, int
                         const ssimx_image* dis, int batch, float* score_out, float* cs_out, void* ws,
                         const MsLayout& L, hipStream_t st);
 
+// Spatial pooling of float32 maps (pool.hip).
+ssimx_status check_pool(const ssimx_pool* pl);
+size_t pool_ws_bytes(const ssimx_pool* pl, int w, int h, int batch);
+ssimx_status pool_run(const ssimx_pool* pl, const float* map, int w, int h, int64_t pitch, int64_t bstride,
+                      int batch, float* out, int64_t out_stride, void* ws, hipStream_t st);
+
 // Tile configuration for a call: explicit override, else the autotune cache,
 // else the default (index 0).
 int pick_tile(const ssimx_params* p, int dtype, int W, int H, int batch);

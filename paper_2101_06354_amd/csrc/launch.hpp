@@ -22,6 +22,8 @@ int launch_finalize(const float* partial, int tiles, int batch, int count_per_fr
                     int64_t out_stride, hipStream_t st);
 int launch_downsample(int dtype, PlaneArg in, int W, int H, float* outx, float* outy, PlaneArg iny,
                       int batch, hipStream_t st);
+int launch_downsample_f(int dtype, PlaneArg x, PlaneArg y, int W, int H, int f, float* outx, float* outy, int batch,
+                        hipStream_t st);
 int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w, int flags, float* score_out,
                       float* cs_out, hipStream_t st);
 int launch_sat(int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, uint32_t* sat, hipStream_t st);

@@ -250,6 +250,33 @@ def pool(qmap: torch.Tensor, kind: str = "cov", p: float = 0.0, o: float = 1.0, 
     return out
 
 
+def scaled_pooled_ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, factor: int = 0,
+                       pool: str = "mean", p: float = 0.0, o: float = 1.0, r: float = 1.0, **kw) -> torch.Tensor:
+    """Down-sample by factor x factor block averages (0: max(1, ceil(H/256))),
+    SSIM map, spatial pooling -> float32 [B]."""
+    cfg = _cfg(cfg, kw)
+    xi, yi, b = _pair(x, y)
+    pc = cfg.to_c()
+    pl = L.Pool(_POOLS[pool], float(p), float(o), float(r))
+    n = ctypes.c_size_t()
+    L.check(L.lib.ssimx_scaled_pooled_workspace_size(ctypes.byref(pc), int(factor), ctypes.byref(pl), xi.dtype,
+                                                     xi.width, xi.height, b, ctypes.byref(n)),
+            "ssimx_scaled_pooled_workspace_size")
+    ws = _workspace(n.value, x.device)
+    out = torch.empty(b, dtype=torch.float32, device=x.device)
+    st = L.lib.ssimx_scaled_pooled_ssim(ctypes.byref(pc), int(factor), ctypes.byref(pl), ctypes.byref(xi),
+                                        ctypes.byref(yi), b, out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(x))
+    L.check(st, "ssimx_scaled_pooled_ssim")
+    return out
+
+
+def enhanced_ssim(x: torch.Tensor, y: torch.Tensor, L_: float = 255.0, factor: int = 0) -> torch.Tensor:
+    """The paper's Enhanced SSIM: 11x11 rectangular window at stride 5 on the
+    pre-scaled luma, CoV pooling -> float32 [B] (0 for identical frames)."""
+    cfg = SSIMConfig(window="box", k=11, stride=5, L=L_)
+    return scaled_pooled_ssim(x, y, cfg, factor=factor, pool="cov")
+
+
 def rgb_to_luma(rgb: torch.Tensor) -> torch.Tensor:
     """BT.601 luma of planar RGB (B, 3, H, W) or (3, H, W), float32/bfloat16
     -> float32 (B, H, W)."""
