@@ -47,6 +47,7 @@ __all__ = [
     "MS_WEIGHTS", "pool_mean", "pool_cov", "pool_md", "pool_minkowski",
     "pool_distortion_weighted", "pool_five_number", "pool_percentile",
     "scale_factor", "downsample_avg", "scaled_pooled_ssim", "enhanced_ssim",
+    "rgb_to_ycbcr_bt709", "color_ssim", "BT709_Y", "BT709_CB", "BT709_CR",
 ]
 
 # Exponents of the original five-scale MS-SSIM, as used by the configurations
@@ -648,3 +649,28 @@ def enhanced_ssim(x, y, factor: int | None = None, L: float = 255.0) -> float:
     p = SSIMParams(window="box", k=11, C1=C1, C2=C2, stride=5)
     f = scale_factor(np.asarray(x).shape[0]) if factor is None else factor
     return scaled_pooled_ssim(x, y, p, f, "cov")
+
+
+# --------------------------------------------------------------------------
+# Channel-wise colour SSIM (Channel-wise SSIM subsection): YCbCr by the BT.709
+# transform printed there, the pooled SSIM of each channel, and the weighted
+# average (f(Y) + alpha f(Cb) + beta f(Cr)) / (1 + alpha + beta).  Reading:
+# the same window and C1, C2 serve all three channels.
+# --------------------------------------------------------------------------
+BT709_Y = (0.213, 0.715, 0.072)
+BT709_CB, BT709_CR = 0.539, 0.635
+
+
+def rgb_to_ycbcr_bt709(rgb: np.ndarray) -> np.ndarray:
+    """(3, H, W) RGB -> (3, H, W) Y, Cb = 0.539 (B - Y), Cr = 0.635 (R - Y)."""
+    rgb = np.asarray(rgb, dtype=np.float64)
+    y = BT709_Y[0] * rgb[0] + BT709_Y[1] * rgb[1] + BT709_Y[2] * rgb[2]
+    return np.stack([y, BT709_CB * (rgb[2] - y), BT709_CR * (rgb[0] - y)])
+
+
+def color_ssim(x_rgb, y_rgb, p: SSIMParams | None = None, alpha: float = 0.125, beta: float = 0.125) -> dict:
+    """Per-channel pooled SSIM and their weighted average; alpha = beta =
+    0.125 gives the 0.8 / 0.1 / 0.1 weighting of the FFMPEG / Daala form."""
+    xs, ys = rgb_to_ycbcr_bt709(x_rgb), rgb_to_ycbcr_bt709(y_rgb)
+    s = [ssim_pooled(xs[c], ys[c], p) for c in range(3)]
+    return {"channels": s, "score": (s[0] + alpha * s[1] + beta * s[2]) / (1.0 + alpha + beta)}

@@ -110,3 +110,35 @@ def test_enhanced_ssim_composition():
     q = O.ssim_map(xs, ys, O.SSIMParams(window="box", k=11, C1=C1, C2=C2, stride=5))["map"]
     assert q.shape == ((150 - 11) // 5 + 1, (200 - 11) // 5 + 1)
     assert O.enhanced_ssim(x, y) == pytest.approx(np.std(q) / np.mean(q), rel=1e-12)
+
+
+def test_ycbcr_transform_closed_forms():
+    white = np.full((3, 2, 2), 255.0)
+    ycc = O.rgb_to_ycbcr_bt709(white)
+    assert np.allclose(ycc[0], 255.0) and np.allclose(ycc[1:], 0.0)  # Y weights sum to one: grey has no chroma
+    red = np.zeros((3, 1, 1))
+    red[0] = 100.0
+    ycc = O.rgb_to_ycbcr_bt709(red)
+    assert ycc[0, 0, 0] == pytest.approx(21.3)
+    assert ycc[1, 0, 0] == pytest.approx(0.539 * (0 - 21.3))
+    assert ycc[2, 0, 0] == pytest.approx(0.635 * (100 - 21.3))
+
+
+def test_color_ssim_reductions():
+    rng = np.random.default_rng(12)
+    g = rng.uniform(20, 230, (40, 50))
+    x = np.stack([g, g, g])
+    y = np.clip(x + rng.normal(0, 8, x.shape), 0, 255)
+    y_grey = np.stack([y[0], y[0], y[0]])
+    p = O.SSIMParams()
+    # grey inputs: zero chroma planes have SSIM 1 in both channels
+    r = O.color_ssim(x, y_grey, p, alpha=0.125, beta=0.125)
+    assert r["channels"][1] == 1.0 and r["channels"][2] == 1.0
+    assert r["score"] == pytest.approx((O.ssim_pooled(g, y[0], p) + 0.25) / 1.25, rel=1e-14)
+    # alpha = beta = 0 is SSIM of the luma plane
+    r = O.color_ssim(x, y, p, alpha=0.0, beta=0.0)
+    assert r["score"] == pytest.approx(O.ssim_pooled(O.rgb_to_ycbcr_bt709(x)[0], O.rgb_to_ycbcr_bt709(y)[0], p))
+    # the 0.8 / 0.1 / 0.1 weights
+    r = O.color_ssim(x, y, p)
+    s = r["channels"]
+    assert r["score"] == pytest.approx(0.8 * s[0] + 0.1 * s[1] + 0.1 * s[2], rel=1e-14)
