@@ -239,6 +239,23 @@ ssimx_status ssimx_scaled_pooled_ssim(const ssimx_params* p, int factor, const s
                                       const ssimx_image* ref, const ssimx_image* dis, int batch, float* score_out,
                                       void* ws, size_t ws_bytes, void* stream);
 
+/* Channel-wise colour SSIM (Channel-wise SSIM subsection): YCbCr by the BT.709
+ * transform printed there (Y = 0.213 R + 0.715 G + 0.072 B, Cb = 0.539 (B - Y),
+ * Cr = 0.635 (R - Y)), the pooled SSIM of each channel with params p (the same
+ * window and C1, C2 for all three), and
+ *   score = (SSIM_Y + alpha SSIM_Cb + beta SSIM_Cr) / (1 + alpha + beta);
+ * alpha = beta = 0.125 is the 0.8 / 0.1 / 0.1 weighting of FFMPEG and Daala.
+ * rgb: planar u8/u16/f32/bf16, element (b, c, r, col) at b*batch_stride +
+ * c*channel_stride + r*pitch + col.  score_out float32 [batch];
+ * channel_scores nullable float32 [batch][3].  EINVAL when 1 + alpha + beta
+ * is 0; ENOTSUP for the integral-image algorithm (channel planes are float32).
+ * Workspace: ssimx_color_workspace_size. */
+ssimx_status ssimx_color_workspace_size(const ssimx_params* p, int w, int h, int batch, size_t* bytes);
+ssimx_status ssimx_color_ssim(const ssimx_params* p, double alpha, double beta, const void* ref_rgb,
+                              const void* dis_rgb, int dtype, int w, int h, int64_t pitch, int64_t channel_stride,
+                              int64_t batch_stride, int batch, float* score_out, float* channel_scores, void* ws,
+                              size_t ws_bytes, void* stream);
+
 /* Colour front end of the differentiable-loss workload: BT.601 luma
  * Y = 0.299 R + 0.587 G + 0.114 B of planar RGB (the paper's Channel-wise SSIM
  * subsection prints the BT.709 matrix; BT.601 weights are used here).

@@ -101,6 +101,9 @@ _SIGS = {
                                                    POINTER(c_size_t)]),
     "ssimx_scaled_pooled_ssim": (c_int, [_P, c_int, POINTER(Pool), _I, _I, c_int, c_void_p, c_void_p, c_size_t,
                                          c_void_p]),
+    "ssimx_color_workspace_size": (c_int, [_P, c_int, c_int, c_int, POINTER(c_size_t)]),
+    "ssimx_color_ssim": (c_int, [_P, c_double, c_double, c_void_p, c_void_p, c_int, c_int, c_int, c_int64, c_int64,
+                                 c_int64, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ssimx_strerror": (c_char_p, [c_int]),
     "ssimx_last_hip_error": (c_int, []),
     "ssimx_version": (c_int, []),

@@ -277,6 +277,32 @@ def enhanced_ssim(x: torch.Tensor, y: torch.Tensor, L_: float = 255.0, factor: i
     return scaled_pooled_ssim(x, y, cfg, factor=factor, pool="cov")
 
 
+def color_ssim(x_rgb: torch.Tensor, y_rgb: torch.Tensor, cfg: SSIMConfig | None = None, alpha: float = 0.125,
+               beta: float = 0.125, return_channels: bool = False, **kw):
+    """Channel-wise colour SSIM of planar RGB (B, 3, H, W) or (3, H, W):
+    (SSIM_Y + alpha SSIM_Cb + beta SSIM_Cr) / (1 + alpha + beta) -> float32 [B]
+    (and the per-channel scores [B, 3] with return_channels)."""
+    cfg = _cfg(cfg, kw)
+    xs = x_rgb.unsqueeze(0) if x_rgb.dim() == 3 else x_rgb
+    ys = y_rgb.unsqueeze(0) if y_rgb.dim() == 3 else y_rgb
+    if xs.shape != ys.shape or xs.dim() != 4 or xs.shape[1] != 3 or xs.dtype != ys.dtype:
+        raise ValueError("x_rgb and y_rgb must be (B, 3, H, W) tensors of one shape and dtype")
+    if xs.stride() != ys.stride() or xs.stride(3) != 1 or not xs.is_cuda:
+        raise ValueError("planar device tensors with contiguous rows and equal strides expected")
+    b, _, h, w = xs.shape
+    pc = cfg.to_c()
+    n = ctypes.c_size_t()
+    L.check(L.lib.ssimx_color_workspace_size(ctypes.byref(pc), w, h, b, ctypes.byref(n)), "ssimx_color_workspace_size")
+    ws = _workspace(n.value, xs.device)
+    out = torch.empty(b, dtype=torch.float32, device=xs.device)
+    ch = torch.empty((b, 3), dtype=torch.float32, device=xs.device)
+    st = L.lib.ssimx_color_ssim(ctypes.byref(pc), float(alpha), float(beta), xs.data_ptr(), ys.data_ptr(),
+                                _DTYPES[xs.dtype], w, h, xs.stride(2), xs.stride(1), xs.stride(0), b, out.data_ptr(),
+                                ch.data_ptr(), ws.data_ptr(), ws.numel(), _stream(xs))
+    L.check(st, "ssimx_color_ssim")
+    return (out, ch) if return_channels else out
+
+
 def rgb_to_luma(rgb: torch.Tensor) -> torch.Tensor:
     """BT.601 luma of planar RGB (B, 3, H, W) or (3, H, W), float32/bfloat16
     -> float32 (B, H, W)."""
