@@ -283,10 +283,6 @@ def _time(fn, reps=10, warmup=2, stream=None):
 def variants(P, x, y, xt, yt, dev, stream, only=()):
     """Secondary workloads, each timed on device-resident inputs (all, or
     those whose names start with one of `only`)."""
-    import numpy as np
-    import torch
-
-    import synth
     out = {}
     B, H, W = x.shape
     px1 = B * H * W
@@ -321,6 +317,21 @@ def variants(P, x, y, xt, yt, dev, stream, only=()):
         ms_f = _time(lambda: [P.ssim(xt[f], yt[f], cfg, return_map=True) for f in range(B)], reps=3, stream=stream)
         rec("c1_batched_launch", ms_b, px1, "64 frames in one launch")
         rec("c1_per_frame_launches", ms_f, px1, "64 single-frame launches")
+    # spatial pooling of the 64 x 1080p Gaussian map; Enhanced SSIM; colour SSIM
+    if want("c1_pool_cov", "c1_pool_five_number"):
+        _, qm = P.ssim(xt, yt, cfg, return_map=True)
+        for kind in ("cov", "five_number"):
+            ms = _time(lambda k=kind: P.pool(qm, k), stream=stream)
+            rec(f"c1_pool_{kind}", ms, px1, f"{kind} pooling of the 64 x 1070x1910 map (map given)")
+        del qm
+    if want("c1_enhanced_ssim"):
+        ms = _time(lambda: P.enhanced_ssim(xt, yt), stream=stream)
+        rec("c1_enhanced_ssim", ms, px1, "pre-scaling by 5x5 means, 11x11 box at stride 5, CoV pooling")
+    if want("c1_color_ssim"):
+        xr, yr = xt[:63].reshape(21, 3, H, W), yt[:63].reshape(21, 3, H, W)
+        ms = _time(lambda: P.color_ssim(xr, yr, cfg), stream=stream)
+        rec("c1_color_ssim", ms, 21 * H * W, "21 RGB 1080p u8 frames (planes from the luma batch), BT.709 "
+            "YCbCr, Gaussian 11x11 per channel, 0.8/0.1/0.1")
     if want("c2_"):
         _variants_c2(P, dev, stream, rec)
     if want("c3_"):
