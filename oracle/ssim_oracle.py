@@ -356,15 +356,23 @@ def _ms_weights(weights, n_scales: int, renorm: bool) -> np.ndarray:
 
 
 def msssim(x, y, p: SSIMParams | None = None, weights=MS_WEIGHTS, n_scales: int = 5,
-           renorm: bool = False, cs_clamp: bool = False) -> dict:
+           renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product") -> dict:
     """Multi-scale SSIM: cs at every scale, luminance at the coarsest only,
     combined as an exponentially weighted product (Introduction; the
     'Product' aggregation of the Versions of SSIM section).
 
+    aggregation="sum" is the 'Sum' aggregation of the same section and of the
+    Scikit-Video notes in the Implementations section: the same per-scale
+    terms (CS_j for j < M, S_M at the coarsest scale) in a weighted average
+    whose weights are the exponents normalised to sum to one (always, so
+    `renorm` has no effect; `cs_clamp` has none either, as no power is taken).
+
     Returns {'score', 'cs' (list of CS_j, j < M), 's_M', 'weights'}.
     """
     p = p or SSIMParams()
-    w = _ms_weights(weights, n_scales, renorm)
+    if aggregation not in ("product", "sum"):
+        raise ValueError(f"unknown aggregation {aggregation!r}")
+    w = _ms_weights(weights, n_scales, renorm or aggregation == "sum")
     xs = pyramid(_as_f64(x), n_scales)
     ys = pyramid(_as_f64(y), n_scales)
     cs_vals = []
@@ -375,6 +383,9 @@ def msssim(x, y, p: SSIMParams | None = None, weights=MS_WEIGHTS, n_scales: int 
             cs_vals.append(mean_pool(r["cs"]))
         else:
             s_m = mean_pool(r["map"])
+    if aggregation == "sum":
+        score = math.fsum([w[j] * c for j, c in enumerate(cs_vals)] + [w[-1] * s_m])
+        return {"score": score, "cs": cs_vals, "s_M": s_m, "weights": w}
     score = 1.0
     with np.errstate(invalid="ignore"):
         for j, c in enumerate(cs_vals):
@@ -480,11 +491,12 @@ def _downsample_adjoint(gc: np.ndarray, fine_shape) -> np.ndarray:
 
 def msssim_backward(x, y, grad_score: float = 1.0, p: SSIMParams | None = None,
                     weights=MS_WEIGHTS, n_scales: int = 5, renorm: bool = False,
-                    cs_clamp: bool = False) -> np.ndarray:
+                    cs_clamp: bool = False, aggregation: str = "product") -> np.ndarray:
     """dL/dy for L = grad_score * MS-SSIM(x, y), by the chain rule through the
-    weighted product and the 2x2 pyramid, coarse to fine."""
+    weighted product (or, for the 'Sum' aggregation, the weighted average) and
+    the 2x2 pyramid, coarse to fine."""
     p = p or SSIMParams()
-    fwd = msssim(x, y, p, weights, n_scales, renorm, cs_clamp)
+    fwd = msssim(x, y, p, weights, n_scales, renorm, cs_clamp, aggregation)
     w = fwd["weights"]
     ms = fwd["score"]
     xs = pyramid(_as_f64(x), n_scales)
@@ -496,7 +508,9 @@ def msssim_backward(x, y, grad_score: float = 1.0, p: SSIMParams | None = None,
             val, term = fwd["s_M"], "ssim"
         else:
             val, term = fwd["cs"][j], "cs"
-        if cs_clamp and val <= 0:
+        if aggregation == "sum":
+            dval = grad_score * w[j]
+        elif cs_clamp and val <= 0:
             dval = 0.0
         else:
             dval = grad_score * ms * w[j] / val

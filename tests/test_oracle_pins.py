@@ -287,6 +287,51 @@ def test_msssim_negative_cs_nan_or_clamped():
     assert O.msssim(x, y, p, n_scales=2, cs_clamp=True)["score"] == 0.0
 
 
+def _block2(a):
+    """2x2 block means by reshaping (odd trailing row / column dropped)."""
+    h, w = a.shape[0] // 2 * 2, a.shape[1] // 2 * 2
+    return a[:h, :w].astype(np.float64).reshape(h // 2, 2, w // 2, 2).mean(axis=(1, 3))
+
+
+def test_msssim_sum_aggregation_pins():
+    """'Sum' aggregation: a convex combination of the product's per-scale
+    terms with the exponents normalised to sum to one."""
+    rng = np.random.default_rng(40)
+    x = synth.smooth_field(rng, 90, 96, 20, 230)
+    y = np.clip(x + rng.normal(0, 12, x.shape), 0, 255)
+    p = O.SSIMParams()
+    # one scale: plain mean SSIM
+    assert abs(O.msssim(x, y, p, (0.7,), 1, aggregation="sum")["score"] - O.ssim_pooled(x, y, p)) < 1e-15
+    # one-hot weights pick one scale's term: CS at the finest, S_M at the coarsest
+    cs0 = O.ssim_map(x, y, p)["cs"].mean()
+    assert abs(O.msssim(x, y, p, (2.0, 0.0, 0.0), 3, aggregation="sum")["score"] - cs0) < 1e-14
+    x2, y2 = _block2(_block2(x)), _block2(_block2(y))
+    s2 = O.ssim_pooled(x2, y2, p)
+    assert abs(O.msssim(x, y, p, (0.0, 0.0, 5.0), 3, aggregation="sum")["score"] - s2) < 1e-14
+    # weighted AM-GM: the product with the same normalised weights is never larger
+    r_sum = O.msssim(x, y, p, n_scales=3, aggregation="sum")
+    r_prod = O.msssim(x, y, p, n_scales=3, renorm=True)
+    terms = r_sum["cs"] + [r_sum["s_M"]]
+    assert min(terms) > 0 and max(terms) - min(terms) > 1e-3
+    assert r_prod["score"] < r_sum["score"] - 1e-6
+    assert min(terms) <= r_sum["score"] <= max(terms)
+    # renorm has no effect on the sum; identity gives one
+    assert O.msssim(x, y, p, n_scales=3, renorm=False, aggregation="sum")["score"] == r_sum["score"]
+    assert abs(O.msssim(x, x, p, n_scales=3, aggregation="sum")["score"] - 1.0) < 1e-13
+
+
+def test_msssim_sum_gradient_matches_fd():
+    rng = np.random.default_rng(41)
+    x = synth.smooth_field(rng, 64, 70, 16 / 255, 235 / 255)
+    y = x + rng.normal(0, 0.05, x.shape)
+    C1, C2 = O.constants(0.01, 0.03, 1.0)
+    p = O.SSIMParams(C1=C1, C2=C2, k=7, sigma=1.0)
+    g = O.msssim_backward(x, y, 1.0, p, n_scales=3, aggregation="sum")
+    f = lambda yy: O.msssim(x, yy, p, n_scales=3, aggregation="sum")["score"]  # noqa: E731
+    for idx in [(0, 0), (31, 40), (63, 69), (10, 50)]:
+        assert abs(_fd(f, y, idx, 1e-5) - g[idx]) <= 1e-6 * abs(g).max(), idx
+
+
 # ---------------------------------------------------------------- adjoint
 def _fd(f, y, idx, h=1e-3):
     yp = y.copy()
