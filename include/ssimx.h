@@ -103,6 +103,13 @@ typedef struct {
 #define SSIMX_MS_RENORM 1   /* divide the n_scales weights by their sum */
 #define SSIMX_MS_CS_CLAMP 2 /* use max(CS_j, 0) (and max(S_M, 0)); default lets a
                                negative value with a fractional exponent give NaN */
+#define SSIMX_MS_SUM 4      /* 'Sum' aggregation (Versions of SSIM section; the
+                               Scikit-Video notes of the Implementations section):
+                               score = sum_j w_j T_j over the same terms T_j (CS_j,
+                               j < M; S_M) with the weights divided by their sum
+                               (implies RENORM; CS_CLAMP has no effect).
+                               Other flag bits: EINVAL.  RENORM or SUM with
+                               weights summing to zero: EINVAL. */
 
 /* Operation selector for ssimx_workspace_size(). */
 typedef enum {
@@ -133,7 +140,8 @@ ssimx_status ssim_pooled(const ssimx_params* p, const ssimx_image* ref, const ss
 
 /* MS-SSIM over n_scales (1..8) dyadic scales built by 2x2 averaging (odd
  * sizes floored).  weights: HOST float [n_scales] exponents.
- * score_out: float32 [batch] = S_M^{w_M} prod_{j<M} CS_j^{w_j}.
+ * score_out: float32 [batch] = S_M^{w_M} prod_{j<M} CS_j^{w_j} (with
+ * SSIMX_MS_SUM: w_M S_M + sum_{j<M} w_j CS_j, weights normalised).
  * cs_out (nullable): float32 [batch][n_scales]; entries 0..M-2 hold CS_j (mean
  * cs map), entry M-1 holds S_M (mean l*cs at the coarsest scale).
  * Every scale must hold at least one window (else ETOOSMALL). */

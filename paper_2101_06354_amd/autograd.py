@@ -25,20 +25,21 @@ class SSIMFunction(torch.autograd.Function):
 
 class MSSSIMFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x, y, cfg, weights, n_scales, renorm, cs_clamp):
+    def forward(ctx, x, y, cfg, weights, n_scales, renorm, cs_clamp, aggregation):
         ctx.save_for_backward(x, y)
-        ctx.args = (cfg, tuple(weights), n_scales, renorm, cs_clamp)
-        return ops.ms_ssim(x, y, cfg, weights=weights, n_scales=n_scales, renorm=renorm, cs_clamp=cs_clamp)
+        ctx.args = (cfg, tuple(weights), n_scales, renorm, cs_clamp, aggregation)
+        return ops.ms_ssim(x, y, cfg, weights=weights, n_scales=n_scales, renorm=renorm, cs_clamp=cs_clamp,
+                           aggregation=aggregation)
 
     @staticmethod
     def backward(ctx, g):
         x, y = ctx.saved_tensors
-        cfg, weights, n_scales, renorm, cs_clamp = ctx.args
+        cfg, weights, n_scales, renorm, cs_clamp, aggregation = ctx.args
         gy = None
         if ctx.needs_input_grad[1]:
             gy = ops.ms_ssim_backward(x, y, g, cfg, weights=weights, n_scales=n_scales, renorm=renorm,
-                                      cs_clamp=cs_clamp).to(y.dtype)
-        return None, gy, None, None, None, None, None
+                                      cs_clamp=cs_clamp, aggregation=aggregation).to(y.dtype)
+        return None, gy, None, None, None, None, None, None
 
 
 class LumaFunction(torch.autograd.Function):
@@ -58,9 +59,10 @@ def ssim(x, y, cfg: ops.SSIMConfig | None = None, **kw):
 
 
 def ms_ssim(x, y, cfg: ops.SSIMConfig | None = None, weights=ops.MS_WEIGHTS, n_scales: int = 5,
-            renorm: bool = False, cs_clamp: bool = False, **kw):
-    """Differentiable MS-SSIM per frame, float32 [B]."""
-    return MSSSIMFunction.apply(x, y, ops._cfg(cfg, kw), tuple(weights), n_scales, renorm, cs_clamp)
+            renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product", **kw):
+    """Differentiable MS-SSIM per frame, float32 [B] (weighted product, or
+    aggregation="sum" for the weighted average)."""
+    return MSSSIMFunction.apply(x, y, ops._cfg(cfg, kw), tuple(weights), n_scales, renorm, cs_clamp, aggregation)
 
 
 def luma(rgb):

@@ -146,14 +146,20 @@ struct MsWeights {
 // score = S_M^{w_M} * prod_{j<M} CS_j^{w_j}; vals[frame][j] holds CS_j for
 // j < M-1 and S_M at M-1.  powf of a negative base with a fractional exponent
 // is NaN, which propagates unless clamping is asked for.
-__global__ void ms_combine_kernel(const float* vals, int n_scales, int batch, MsWeights w, int clamp,
+// Weighted product S_M^{w_M} prod CS_j^{w_j}, or (sum != 0) the weighted
+// average sum w_j T_j of the same terms with weights that sum to one.
+__global__ void ms_combine_kernel(const float* vals, int n_scales, int batch, MsWeights w, int clamp, int sum,
                                   float* score_out, float* cs_out) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= batch) return;
-  float score = 1.f;
+  float score = sum ? 0.f : 1.f;
   for (int j = 0; j < n_scales; ++j) {
     float v = vals[(int64_t)f * n_scales + j];
     if (cs_out) cs_out[(int64_t)f * n_scales + j] = v;
+    if (sum) {
+      score = fmaf(w.w[j], v, score);
+      continue;
+    }
     if (clamp) v = fmaxf(v, 0.f);
     score *= powf(v, w.w[j]);
   }
@@ -165,7 +171,7 @@ int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w
   MsWeights mw{};
   for (int j = 0; j < n_scales && j < MAX_SCALES; ++j) mw.w[j] = w[j];
   hipLaunchKernelGGL(ms_combine_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, vals, n_scales, batch, mw,
-                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, score_out, cs_out);
+                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, score_out, cs_out);
   return (int)hipGetLastError();
 }
 

@@ -225,16 +225,17 @@ struct UpArgs {
   float inv_count[MAX_SCALES];
 };
 
-// dL/dT for the pooled term of each scale: grad * MS * w_j / val_j / N_j
-// (zero where a clamped value is not positive).
+// dL/dT for the pooled term of each scale: grad * MS * w_j / val_j / N_j for
+// the weighted product (zero where a clamped value is not positive), grad *
+// w_j / N_j for the weighted average.
 __global__ void ms_upstream_kernel(const float* vals, const float* ms, const float* gscore, UpArgs u, int M,
-                                   int clamp, int batch, float* up) {
+                                   int clamp, int sum, int batch, float* up) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= batch) return;
   for (int j = 0; j < M; ++j) {
     const float v = vals[(int64_t)f * M + j];
-    float r = gscore[f] * ms[f] * u.w[j] / v * u.inv_count[j];
-    if (clamp && !(v > 0.f)) r = 0.f;
+    float r = sum ? gscore[f] * u.w[j] * u.inv_count[j] : gscore[f] * ms[f] * u.w[j] / v * u.inv_count[j];
+    if (!sum && clamp && !(v > 0.f)) r = 0.f;
     up[(int64_t)f * M + j] = r;
   }
 }
@@ -498,7 +499,7 @@ ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_
   ssimx_status s = check_bwd(p, ref, dis, batch, grad_dis, grad_pitch, grad_batch_stride);
   if (s != SSIMX_OK) return s;
   if (!grad_score) return SSIMX_EINVAL;
-  if ((s = check_ms(p, weights, n_scales, ref->width, ref->height)) != SSIMX_OK) return s;
+  if ((s = check_ms(p, weights, n_scales, flags, ref->width, ref->height)) != SSIMX_OK) return s;
   if ((s = check_path(p, ref->dtype)) != SSIMX_OK) return s;
   if ((s = check_path(p, SSIMX_F32)) != SSIMX_OK) return s;
   const MsBwdLayout L = ms_bwd_layout(p, ref->dtype, ref->width, ref->height, batch, n_scales);
@@ -519,7 +520,7 @@ ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_
   float* up = (float*)(base + L.up);
   hipLaunchKernelGGL(ms_upstream_kernel, dim3((batch + 63) / 64), dim3(64), 0, st,
                      (const float*)(base + L.fwd.vals_off), (const float*)(base + L.msval), grad_score, u, n_scales,
-                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, batch, up);
+                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, batch, up);
   int err = (int)hipGetLastError();
   if (err) return hip_status(err);
   for (int j = n_scales - 1; j >= 0; --j) {

@@ -309,10 +309,15 @@ MsLayout ms_layout(const ssimx_params* p, int dtype, int W, int H, int batch, in
   return L;
 }
 
-ssimx_status check_ms(const ssimx_params* p, const float* weights, int n_scales, int W, int H) {
+ssimx_status check_ms(const ssimx_params* p, const float* weights, int n_scales, int flags, int W, int H) {
   if (!weights || n_scales < 1 || n_scales > MAX_SCALES) return SSIMX_EINVAL;
-  for (int j = 0; j < n_scales; ++j)
+  if (flags & ~(SSIMX_MS_RENORM | SSIMX_MS_CS_CLAMP | SSIMX_MS_SUM)) return SSIMX_EINVAL;
+  double sum = 0.0;
+  for (int j = 0; j < n_scales; ++j) {
     if (!isfinite(weights[j])) return SSIMX_EINVAL;
+    sum += weights[j];
+  }
+  if ((flags & (SSIMX_MS_RENORM | SSIMX_MS_SUM)) && !(sum != 0.0)) return SSIMX_EINVAL;
   int Wj[MAX_SCALES], Hj[MAX_SCALES];
   scale_dims(W, H, n_scales, Wj, Hj);
   for (int j = 0; j < n_scales; ++j) {
@@ -327,7 +332,8 @@ ssimx_status check_ms(const ssimx_params* p, const float* weights, int n_scales,
 void ms_weights(const float* weights, int n_scales, int flags, float* w) {
   double sum = 0.0;
   for (int j = 0; j < n_scales; ++j) sum += weights[j];
-  for (int j = 0; j < n_scales; ++j) w[j] = (flags & SSIMX_MS_RENORM) ? (float)(weights[j] / sum) : weights[j];
+  const bool norm = (flags & (SSIMX_MS_RENORM | SSIMX_MS_SUM)) != 0;
+  for (int j = 0; j < n_scales; ++j) w[j] = norm ? (float)(weights[j] / sum) : weights[j];
 }
 
 // ---------------------------------------------------------------- forward core
@@ -526,7 +532,7 @@ ssimx_status msssim(const ssimx_params* p, const float* weights, int n_scales, i
   if ((s = check_params(p)) != SSIMX_OK) return s;
   if ((s = check_images(ref, dis, batch)) != SSIMX_OK) return s;
   if (!score_out) return SSIMX_EINVAL;
-  if ((s = check_ms(p, weights, n_scales, ref->width, ref->height)) != SSIMX_OK) return s;
+  if ((s = check_ms(p, weights, n_scales, flags, ref->width, ref->height)) != SSIMX_OK) return s;
   if ((s = check_path(p, ref->dtype)) != SSIMX_OK) return s;
   if ((s = check_path(p, SSIMX_F32)) != SSIMX_OK) return s;
   const MsLayout L = ms_layout(p, ref->dtype, ref->width, ref->height, batch, n_scales);

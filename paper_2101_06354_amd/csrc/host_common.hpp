@@ -19,7 +19,7 @@ ssimx_status hip_status(int err);
 ssimx_status check_params(const ssimx_params* p);
 ssimx_status check_images(const ssimx_image* a, const ssimx_image* b, int batch);
 ssimx_status check_path(const ssimx_params* p, int dtype);
-ssimx_status check_ms(const ssimx_params* p, const float* weights, int n_scales, int W, int H);
+ssimx_status check_ms(const ssimx_params* p, const float* weights, int n_scales, int flags, int W, int H);
 bool is_integer(int dtype);
 Path choose_path(const ssimx_params* p, int dtype);
 void map_dims(const ssimx_params* p, int W, int H, int& Wo, int& Ho);

@@ -27,6 +27,13 @@ namespace {
 constexpr int kPoolNT = 256;
 constexpr int kMaxTargets = 8;
 
+// Per-frame selection state, kStateWords uint32 words: the targets' key
+// prefixes and remaining ranks, the histogram slot of each target, and the
+// distinct prefixes (one histogram each).  Distinct prefixes of the same
+// length select disjoint key sets, so every key adds to at most one histogram.
+constexpr int kStateWords = 64;
+constexpr int kPre = 0, kRank = 8, kSlot = 16, kUniq = 24, kNUniq = 32;
+
 struct MapArg {
   const float* map;
   int w, h;
@@ -66,32 +73,40 @@ __global__ __launch_bounds__(kPoolNT) void pool_sums_kernel(MapArg a, int kind, 
   const int frame = blockIdx.y;
   const float* m = a.map + (int64_t)frame * a.bstride;
   const double muf = mu ? mu[frame] : 0.0;
-  const uint32_t tk = thr_key ? thr_key[(int64_t)frame * 2 * kMaxTargets] : 0u;  // target 0's key
+  const uint32_t tk = thr_key ? thr_key[(int64_t)frame * kStateWords + kPre] : 0u;  // target 0's key
   double s0 = 0.0, s1 = 0.0;
+  auto acc = [&](float qf) {
+    const double q = (double)qf;
+    switch (kind) {
+      case 0: s0 += q; break;
+      case 1: s0 += q; s1 += q * q; break;
+      case 2: s0 += pow_term(fabs(q - muf), p, ip); break;
+      case 3: s0 += pow_term(1.0 - q, p, ip); break;
+      case 4: {
+        const double wgt = pow_term(1.0 - q, p, ip);
+        s0 += wgt * q;
+        s1 += wgt;
+        break;
+      }
+      default:  // below the m-th smallest value of the frame
+        if (ordered_key(qf) < tk) {
+          s0 += q;
+          s1 += 1.0;
+        }
+        break;
+    }
+  };
   for (int r = blockIdx.x; r < a.h; r += gridDim.x) {
     const float* row = m + (int64_t)r * a.pitch;
-    for (int c = threadIdx.x; c < a.w; c += kPoolNT) {
-      const float qf = row[c];
-      const double q = (double)qf;
-      switch (kind) {
-        case 0: s0 += q; break;
-        case 1: s0 += q; s1 += q * q; break;
-        case 2: s0 += pow_term(fabs(q - muf), p, ip); break;
-        case 3: s0 += pow_term(1.0 - q, p, ip); break;
-        case 4: {
-          const double wgt = pow_term(1.0 - q, p, ip);
-          s0 += wgt * q;
-          s1 += wgt;
-          break;
-        }
-        default:  // below the m-th smallest value of the frame
-          if (ordered_key(qf) < tk) {
-            s0 += q;
-            s1 += 1.0;
-          }
-          break;
-      }
+    int c = threadIdx.x;
+    for (; c + 3 * kPoolNT < a.w; c += 4 * kPoolNT) {  // four loads in flight
+      const float v0 = row[c], v1 = row[c + kPoolNT], v2 = row[c + 2 * kPoolNT], v3 = row[c + 3 * kPoolNT];
+      acc(v0);
+      acc(v1);
+      acc(v2);
+      acc(v3);
     }
+    for (; c < a.w; c += kPoolNT) acc(row[c]);
   }
   s0 = wave_sum_d(s0);
   s1 = wave_sum_d(s1);
@@ -158,9 +173,9 @@ __global__ void pool_finish_kernel(const double* partial, const double* total, i
     case SSIMX_POOL_MINKOWSKI: v = s0 / f.n; break;
     case SSIMX_POOL_DIST_WEIGHTED: v = s1 == 0.0 ? 1.0 : s0 / s1; break;
     case SSIMX_POOL_FIVE_NUMBER: {
-      const uint32_t* k = keys + (int64_t)frame * 2 * kMaxTargets;  // (prefix, rank) pairs
+      const uint32_t* k = keys + (int64_t)frame * kStateWords + kPre;  // selected keys
       double q[kMaxTargets];
-      for (int t = 0; t < f.nt; ++t) q[t] = (double)key_value(k[2 * t]);
+      for (int t = 0; t < f.nt; ++t) q[t] = (double)key_value(k[t]);
       // targets: min, max, then (lo, hi) pairs of Q1, median, Q3
       double acc = q[0] + q[1];
       for (int j = 0; j < 3; ++j) acc += q[2 + 2 * j] + f.frac[j] * (q[3 + 2 * j] - q[2 + 2 * j]);
@@ -173,7 +188,7 @@ __global__ void pool_finish_kernel(const double* partial, const double* total, i
       if (f.m == 0) {
         v = tot / f.n;
       } else {
-        const double thr = (double)key_value(keys[(int64_t)frame * 2 * kMaxTargets]);
+        const double thr = (double)key_value(keys[(int64_t)frame * kStateWords + kPre]);
         // s0 = sum of the values strictly below the m-th smallest, s1 = their count
         const double low = s0 + ((double)f.m - s1) * thr;
         v = (low / f.r + (tot - low)) / f.n;
@@ -189,7 +204,7 @@ __global__ void pool_finish_kernel(const double* partial, const double* total, i
 struct SelArgs {
   MapArg a;
   int nt;
-  uint32_t* state;  // [batch][kMaxTargets][2] = (prefix, remaining rank)
+  uint32_t* state;  // [batch][kStateWords]
   uint32_t* hist;   // [batch][kMaxTargets][256]
 };
 
@@ -200,58 +215,130 @@ struct Ranks {
 __global__ void sel_init_kernel(SelArgs s, int batch, Ranks ranks) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < batch * kMaxTargets * 256) s.hist[i] = 0u;
-  if (i < batch * kMaxTargets) {
-    s.state[2 * i] = 0u;
-    s.state[2 * i + 1] = ranks.r[i % kMaxTargets];
+  if (i < batch) {
+    uint32_t* st = s.state + (int64_t)i * kStateWords;
+    for (int t = 0; t < kMaxTargets; ++t) {
+      st[kPre + t] = 0u;
+      st[kRank + t] = ranks.r[t];
+      st[kSlot + t] = 0u;
+      st[kUniq + t] = 0u;
+    }
+    st[kNUniq] = 1u;
   }
 }
 
+// Adds `cnt` to LDS bin `idx` (skipped for idx < 0).
+__device__ __forceinline__ void flush_run(uint32_t* h, int idx, uint32_t cnt) {
+  if (idx >= 0) atomicAdd(&h[idx], cnt);
+}
+
 __global__ __launch_bounds__(kPoolNT) void sel_hist_kernel(SelArgs s, int shift) {
-  __shared__ uint32_t h[kMaxTargets][256];
-  __shared__ uint32_t pre[kMaxTargets];
+  __shared__ uint32_t h[kMaxTargets * 256];
+  __shared__ uint32_t uq[kMaxTargets];
+  __shared__ int nu_s;
   const int frame = blockIdx.y;
-  for (int i = threadIdx.x; i < kMaxTargets * 256; i += kPoolNT) (&h[0][0])[i] = 0u;
-  if (threadIdx.x < kMaxTargets) pre[threadIdx.x] = s.state[((int64_t)frame * kMaxTargets + threadIdx.x) * 2];
+  const uint32_t* st = s.state + (int64_t)frame * kStateWords;
+  for (int i = threadIdx.x; i < kMaxTargets * 256; i += kPoolNT) h[i] = 0u;
+  if (threadIdx.x < kMaxTargets) uq[threadIdx.x] = st[kUniq + threadIdx.x];
+  if (threadIdx.x == 0) nu_s = (int)st[kNUniq];
   __syncthreads();
+  const int nu = nu_s;
   const uint32_t himask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
   const float* m = s.a.map + (int64_t)frame * s.a.bstride;
+  // Neighbouring map values are strongly correlated, so runs of equal bins in
+  // a thread's keys are merged before they reach the (contended) LDS bins.
+  int cur = -1;
+  uint32_t cnt = 0u;
+  auto add = [&](float v) {
+    const uint32_t k = ordered_key(v);
+    int idx = -1;
+    for (int u = 0; u < nu; ++u)
+      if (((k ^ uq[u]) & himask) == 0u) {
+        idx = u * 256 + (int)((k >> shift) & 255u);
+        break;
+      }
+    if (idx != cur) {
+      flush_run(h, cur, cnt);
+      cur = idx;
+      cnt = 0u;
+    }
+    ++cnt;
+  };
   for (int r = blockIdx.x; r < s.a.h; r += gridDim.x) {
     const float* row = m + (int64_t)r * s.a.pitch;
-    for (int c = threadIdx.x; c < s.a.w; c += kPoolNT) {
-      const uint32_t k = ordered_key(row[c]);
-      const uint32_t bin = (k >> shift) & 255u;
-      for (int t = 0; t < s.nt; ++t)
-        if (((k ^ pre[t]) & himask) == 0u) atomicAdd(&h[t][bin], 1u);
+    int c = threadIdx.x;
+    // four loads in flight, then their keys in order
+    for (; c + 3 * kPoolNT < s.a.w; c += 4 * kPoolNT) {
+      const float v0 = row[c], v1 = row[c + kPoolNT], v2 = row[c + 2 * kPoolNT], v3 = row[c + 3 * kPoolNT];
+      add(v0);
+      add(v1);
+      add(v2);
+      add(v3);
     }
+    for (; c < s.a.w; c += kPoolNT) add(row[c]);
   }
+  flush_run(h, cur, cnt);
   __syncthreads();
   uint32_t* g = s.hist + (int64_t)frame * kMaxTargets * 256;
-  for (int i = threadIdx.x; i < s.nt * 256; i += kPoolNT) {
-    const uint32_t v = (&h[0][0])[i];
+  for (int i = threadIdx.x; i < nu * 256; i += kPoolNT) {
+    const uint32_t v = h[i];
     if (v) atomicAdd(&g[i], v);
   }
 }
 
-// One thread per (frame, target): find the bin holding the remaining rank,
-// extend the prefix, clear the histogram row for the next pass.
-__global__ void sel_step_kernel(SelArgs s, int batch, int shift) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= batch * kMaxTargets || (i % kMaxTargets) >= s.nt) return;
-  uint32_t* st = s.state + 2 * (int64_t)i;
-  uint32_t* g = s.hist + (int64_t)i * 256;
-  const uint32_t rank = st[1];
-  uint32_t cum = 0u, bin = 255u;
-  for (int b = 0; b < 256; ++b) {
-    const uint32_t c = g[b];
-    if (rank < cum + c) {
-      bin = (uint32_t)b;
-      break;
-    }
-    cum += c;
+// One block of 256 threads per frame, one thread per bin: scan each distinct
+// prefix's histogram, extend the prefix of every target that uses it by the
+// bin holding its remaining rank, clear the histogram, then regroup the new
+// prefixes into distinct histograms for the next pass.
+__global__ __launch_bounds__(256) void sel_step_kernel(SelArgs s, int shift) {
+  __shared__ uint32_t wtot[4];
+  __shared__ uint32_t npre[kMaxTargets], nrank[kMaxTargets];
+  const int frame = blockIdx.x, b = threadIdx.x, lane = b & 63, wid = b >> 6;
+  uint32_t* st = s.state + (int64_t)frame * kStateWords;
+  uint32_t* g = s.hist + (int64_t)frame * kMaxTargets * 256;
+  const int nu = (int)st[kNUniq];
+  if (b < s.nt) {  // fallback, replaced below by the thread whose bin holds the rank
+    npre[b] = st[kPre + b] | (255u << shift);
+    nrank[b] = st[kRank + b];
   }
-  st[0] |= bin << shift;
-  st[1] = rank - cum;
-  for (int b = 0; b < 256; ++b) g[b] = 0u;
+  __syncthreads();
+  for (int u = 0; u < nu; ++u) {
+    const uint32_t c = g[u * 256 + b];
+    uint32_t v = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(v, o, 64);
+      if (lane >= o) v += t;
+    }
+    if (lane == 63) wtot[wid] = v;
+    __syncthreads();
+    for (int w = 0; w < wid; ++w) v += wtot[w];
+    const uint32_t incl = v, excl = v - c;
+    for (int t = 0; t < s.nt; ++t) {
+      if ((int)st[kSlot + t] != u) continue;
+      const uint32_t r = st[kRank + t];
+      if (r >= excl && r < incl) {
+        npre[t] = st[kPre + t] | ((uint32_t)b << shift);
+        nrank[t] = r - excl;
+      }
+    }
+    g[u * 256 + b] = 0u;
+    __syncthreads();
+  }
+  if (b == 0) {
+    uint32_t uqv[kMaxTargets];
+    int n = 0;
+    for (int t = 0; t < s.nt; ++t) {
+      int j = 0;
+      while (j < n && uqv[j] != npre[t]) ++j;
+      if (j == n) uqv[n++] = npre[t];
+      st[kPre + t] = npre[t];
+      st[kRank + t] = nrank[t];
+      st[kSlot + t] = (uint32_t)j;
+    }
+    for (int j = 0; j < n; ++j) st[kUniq + j] = uqv[j];
+    st[kNUniq] = (uint32_t)n;
+  }
 }
 
 int blocks_per_frame(int h) { return h < 64 ? h : 64; }
@@ -266,7 +353,7 @@ size_t pool_ws_bytes(const ssimx_pool* pl, int w, int h, int batch) {
   ws.take(sizeof(double) * 2 * (size_t)batch * nblk);  // second set (totals)
   ws.take(sizeof(double) * (size_t)batch);              // per-frame mean
   if (pl->kind == SSIMX_POOL_FIVE_NUMBER || pl->kind == SSIMX_POOL_PERCENTILE) {
-    ws.take(sizeof(uint32_t) * 2 * kMaxTargets * (size_t)batch);
+    ws.take(sizeof(uint32_t) * kStateWords * (size_t)batch);
     ws.take(sizeof(uint32_t) * 256 * kMaxTargets * (size_t)batch);
   }
   return ws.used;
@@ -333,7 +420,7 @@ ssimx_status pool_run(const ssimx_pool* pl, const float* map, int w, int h, int6
       break;
     }
     default: {  // order statistics
-      uint32_t* state = (uint32_t*)((char*)ws + lay.take(sizeof(uint32_t) * 2 * kMaxTargets * (size_t)batch));
+      uint32_t* state = (uint32_t*)((char*)ws + lay.take(sizeof(uint32_t) * kStateWords * (size_t)batch));
       uint32_t* hist = (uint32_t*)((char*)ws + lay.take(sizeof(uint32_t) * 256 * kMaxTargets * (size_t)batch));
       uint32_t ranks[kMaxTargets] = {};
       const uint32_t last = (uint32_t)(w * (int64_t)h - 1);
@@ -364,7 +451,7 @@ ssimx_status pool_run(const ssimx_pool* pl, const float* map, int w, int h, int6
       hipLaunchKernelGGL(sel_init_kernel, dim3((ninit + 255) / 256), dim3(256), 0, st, s, batch, rk);
       for (int shift = 24; shift >= 0; shift -= 8) {
         hipLaunchKernelGGL(sel_hist_kernel, grid, dim3(kPoolNT), 0, st, s, shift);
-        hipLaunchKernelGGL(sel_step_kernel, dim3((batch * kMaxTargets + 63) / 64), dim3(64), 0, st, s, batch, shift);
+        hipLaunchKernelGGL(sel_step_kernel, dim3(batch), dim3(256), 0, st, s, shift);
       }
       if (pl->kind == SSIMX_POOL_PERCENTILE) {
         // totals, then the sum and count of the values below the threshold

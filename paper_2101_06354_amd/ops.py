@@ -137,14 +137,24 @@ def _weights(weights, n_scales):
     return (ctypes.c_float * n_scales)(*[float(v) for v in weights[:n_scales]])
 
 
+def _ms_flags(renorm: bool, cs_clamp: bool, aggregation: str) -> int:
+    if aggregation not in ("product", "sum"):
+        raise ValueError(f"aggregation must be 'product' or 'sum', not {aggregation!r}")
+    return ((L.MS_RENORM if renorm else 0) | (L.MS_CS_CLAMP if cs_clamp else 0)
+            | (L.MS_SUM if aggregation == "sum" else 0))
+
+
 def ms_ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, weights=MS_WEIGHTS,
-            n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, return_cs: bool = False, **kw):
+            n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, return_cs: bool = False,
+            aggregation: str = "product", **kw):
     """MS-SSIM per frame (float32 [B]); with return_cs also [B, n_scales]
-    holding CS_1..CS_{M-1} and S_M."""
+    holding CS_1..CS_{M-1} and S_M.  aggregation="sum" takes the weighted
+    average of the same terms with normalised weights instead of the
+    weighted product."""
     cfg = _cfg(cfg, kw)
     xi, yi, b = _pair(x, y)
     p = cfg.to_c()
-    flags = (L.MS_RENORM if renorm else 0) | (L.MS_CS_CLAMP if cs_clamp else 0)
+    flags = _ms_flags(renorm, cs_clamp, aggregation)
     ws = _workspace(workspace_size(cfg, L.OP_MSSSIM, xi.dtype, xi.height, xi.width, b, n_scales), x.device)
     score = torch.empty(b, dtype=torch.float32, device=x.device)
     cs = torch.empty((b, n_scales), dtype=torch.float32, device=x.device) if return_cs else None
@@ -187,11 +197,12 @@ def ssim_map_backward(x: torch.Tensor, y: torch.Tensor, grad_map: torch.Tensor, 
 
 
 def ms_ssim_backward(x: torch.Tensor, y: torch.Tensor, grad_score: torch.Tensor, cfg: SSIMConfig | None = None,
-                     weights=MS_WEIGHTS, n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, **kw):
+                     weights=MS_WEIGHTS, n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False,
+                     aggregation: str = "product", **kw):
     cfg = _cfg(cfg, kw)
     xi, yi, b = _pair(x, y)
     p = cfg.to_c()
-    flags = (L.MS_RENORM if renorm else 0) | (L.MS_CS_CLAMP if cs_clamp else 0)
+    flags = _ms_flags(renorm, cs_clamp, aggregation)
     g = grad_score.to(device=x.device, dtype=torch.float32).reshape(b).contiguous()
     out = torch.empty(_as3(y).shape, dtype=torch.float32, device=x.device)
     ws = _workspace(workspace_size(cfg, L.OP_MSSSIM_BACKWARD, xi.dtype, xi.height, xi.width, b, n_scales),

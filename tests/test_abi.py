@@ -122,6 +122,17 @@ def test_msssim_scale_validation(L):
                         None) == L.EINVAL
     assert L.lib.msssim(ctypes.byref(p), w, 5, 0, ctypes.byref(ok), ctypes.byref(ok), 1, s, None, None, 0,
                         None) == L.EWORKSPACE
+    # unknown flag bits; normalised weights that sum to zero
+    assert L.lib.msssim(ctypes.byref(p), w, 5, 8, ctypes.byref(ok), ctypes.byref(ok), 1, s, None, None, 0,
+                        None) == L.EINVAL
+    wz = (ctypes.c_float * 2)(1.0, -1.0)
+    for fl in (L.MS_RENORM, L.MS_SUM):
+        assert L.lib.msssim(ctypes.byref(p), wz, 2, fl, ctypes.byref(ok), ctypes.byref(ok), 1, s, None, None, 0,
+                            None) == L.EINVAL
+    assert L.lib.msssim(ctypes.byref(p), wz, 2, 0, ctypes.byref(ok), ctypes.byref(ok), 1, s, None, None, 0,
+                        None) == L.EWORKSPACE
+    assert L.lib.msssim(ctypes.byref(p), w, 5, L.MS_SUM | L.MS_CS_CLAMP, ctypes.byref(ok), ctypes.byref(ok), 1, s,
+                        None, None, 0, None) == L.EWORKSPACE
 
 
 def test_workspace_size_and_tile_api(L):

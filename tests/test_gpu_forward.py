@@ -184,6 +184,26 @@ def test_msssim_float_rgb_luma_planes(P, dev):
         assert abs(s[f] - O.msssim(x[f], y[f], oparams(cfg), n_scales=3, renorm=True)["score"]) <= SCORE_TOL
 
 
+@pytest.mark.parametrize("n_scales", [5, 3])
+def test_msssim_sum_aggregation(P, dev, n_scales):
+    x, y = synth.config2(frames=2, h=270, w=480)
+    cfg = P.SSIMConfig(L=1023.0)
+    s, cs = P.ms_ssim(to_dev(x, dev), to_dev(y, dev), cfg, n_scales=n_scales, aggregation="sum", return_cs=True)
+    s, cs = s.cpu().numpy(), cs.cpu().numpy()
+    for f in range(2):
+        r = O.msssim(x[f], y[f], oparams(cfg), P.MS_WEIGHTS, n_scales, aggregation="sum")
+        assert abs(s[f] - r["score"]) <= SCORE_TOL
+        np.testing.assert_allclose(cs[f, :-1], r["cs"], rtol=0, atol=SCORE_TOL)
+    # same per-scale terms as the product; identity gives exactly one
+    _, cs_p = P.ms_ssim(to_dev(x, dev), to_dev(y, dev), cfg, n_scales=n_scales, return_cs=True)
+    assert torch.equal(cs_p.cpu(), torch.from_numpy(cs))
+    xi = to_dev(x, dev)
+    one = P.ms_ssim(xi, xi, cfg, n_scales=n_scales, aggregation="sum").cpu().numpy()
+    assert np.all(np.abs(one - 1.0) <= 1e-6)
+    with pytest.raises(ValueError):
+        P.ms_ssim(xi, xi, cfg, aggregation="mean")
+
+
 def test_msssim_identity_and_clamp(P, dev):
     x, _ = synth.config0()
     cfg = P.SSIMConfig()
