@@ -48,6 +48,7 @@ __all__ = [
     "pool_distortion_weighted", "pool_five_number", "pool_percentile",
     "scale_factor", "downsample_avg", "scaled_pooled_ssim", "enhanced_ssim",
     "rgb_to_ycbcr_bt709", "color_ssim", "BT709_Y", "BT709_CB", "BT709_CR",
+    "box_sums3d", "ssim3d_map", "ssim3d", "msssim3d",
 ]
 
 # Exponents of the original five-scale MS-SSIM, as used by the configurations
@@ -383,9 +384,14 @@ def msssim(x, y, p: SSIMParams | None = None, weights=MS_WEIGHTS, n_scales: int 
             cs_vals.append(mean_pool(r["cs"]))
         else:
             s_m = mean_pool(r["map"])
+    score = _ms_combine(cs_vals, s_m, w, cs_clamp, aggregation)
+    return {"score": score, "cs": cs_vals, "s_M": s_m, "weights": w}
+
+
+def _ms_combine(cs_vals, s_m, w, cs_clamp: bool, aggregation: str) -> float:
+    """S_M^{w_M} prod_j CS_j^{w_j}, or sum_j w_j CS_j + w_M S_M ('Sum')."""
     if aggregation == "sum":
-        score = math.fsum([w[j] * c for j, c in enumerate(cs_vals)] + [w[-1] * s_m])
-        return {"score": score, "cs": cs_vals, "s_M": s_m, "weights": w}
+        return math.fsum([w[j] * c for j, c in enumerate(cs_vals)] + [w[-1] * s_m])
     score = 1.0
     with np.errstate(invalid="ignore"):
         for j, c in enumerate(cs_vals):
@@ -393,7 +399,7 @@ def msssim(x, y, p: SSIMParams | None = None, weights=MS_WEIGHTS, n_scales: int 
             score *= float(np.power(c, w[j])) if c >= 0 else float("nan")
         sm = max(s_m, 0.0) if cs_clamp else s_m
         score *= float(np.power(sm, w[-1])) if sm >= 0 else float("nan")
-    return {"score": score, "cs": cs_vals, "s_M": s_m, "weights": w}
+    return score
 
 
 # --------------------------------------------------------------------------
@@ -688,3 +694,103 @@ def color_ssim(x_rgb, y_rgb, p: SSIMParams | None = None, alpha: float = 0.125, 
     xs, ys = rgb_to_ycbcr_bt709(x_rgb), rgb_to_ycbcr_bt709(y_rgb)
     s = [ssim_pooled(xs[c], ys[c], p) for c in range(3)]
     return {"channels": s, "score": (s[0] + alpha * s[1] + beta * s[2]) / (1.0 + alpha + beta)}
+
+
+# --------------------------------------------------------------------------
+# SSIM-3D and MS-SSIM-3D (Spatio-Temporal SSIM subsection).  SSIM whose mean,
+# variance and covariance are taken over k x k x kt spatio-temporal boxes with
+# equal weights; MS-SSIM-3D applies it at every scale of a spatial pyramid
+# (each frame down-sampled on its own, the temporal extent unchanged).
+#
+# Readings: the box (t, i, j) covers frames t .. t+kt-1, rows i .. i+k-1 and
+# columns j .. j+k-1 (top-left anchoring as for 2-D windows; the paper's
+# trailing-window sums differ only in the index of the output); boxes lie
+# inside the clip in all three axes, so a clip of T frames gives T-kt+1 map
+# frames; each map frame is pooled by its mean, and MS-SSIM-3D combines the
+# per-scale means of the same map frame as MS-SSIM does.
+# --------------------------------------------------------------------------
+def box_sums3d(x, y, k: int, kt: int):
+    """Window sums S1x, S1y, S2x, S2y, S12 over every k x k x kt box, by
+    adding every (frame, row, column) offset of the box: exact int64 for
+    integer clips, float64 otherwise.  x, y: [T, H, W]."""
+    integer = np.issubdtype(np.asarray(x).dtype, np.integer) and np.issubdtype(np.asarray(y).dtype, np.integer)
+    dt = np.int64 if integer else np.float64
+    x = np.asarray(x).astype(dt)
+    y = np.asarray(y).astype(dt)
+    T, H, W = x.shape
+    to, ho, wo = T - kt + 1, H - k + 1, W - k + 1
+    if to < 1 or ho < 1 or wo < 1:
+        raise ValueError("clip smaller than the box")
+    acc = [np.zeros((to, ho, wo), dtype=dt) for _ in range(5)]
+    for o in range(kt):
+        for m in range(k):
+            for n in range(k):
+                xs = x[o:o + to, m:m + ho, n:n + wo]
+                ys = y[o:o + to, m:m + ho, n:n + wo]
+                acc[0] += xs
+                acc[1] += ys
+                acc[2] += xs * xs
+                acc[3] += ys * ys
+                acc[4] += xs * ys
+    return tuple(acc)
+
+
+def ssim3d_map(x, y, p: SSIMParams | None = None, kt: int = 1) -> dict:
+    """SSIM-3D map [T-kt+1, H-k+1, W-k+1] of two clips [T, H, W] with the
+    rectangular k x k x kt box (p.window must be 'box', stride 1, valid).
+    Statistics from the window sums as in eqs. mean_from_sum .. corr_from_sum
+    with N = k*k*kt samples; the numerators N S2 - S1^2 are exact integers for
+    integer clips."""
+    p = p or SSIMParams(window="box", k=11)
+    p.check()
+    if p.window != "box" or p.stride != 1 or p.padding != "valid":
+        raise ValueError("SSIM-3D uses a rectangular box, stride 1, valid borders")
+    if kt < 1:
+        raise ValueError("kt must be positive")
+    s1x, s1y, s2x, s2y, s12 = box_sums3d(x, y, p.k, kt)
+    n = p.k * p.k * kt
+    n2 = float(n) * float(n)
+    mu_x = s1x.astype(np.float64) / n
+    mu_y = s1y.astype(np.float64) / n
+    sxx = (n * s2x - s1x * s1x).astype(np.float64) / n2
+    syy = (n * s2y - s1y * s1y).astype(np.float64) / n2
+    sxy = (n * s12 - s1x * s1y).astype(np.float64) / n2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l = (2.0 * mu_x * mu_y + p.C1) / (mu_x * mu_x + mu_y * mu_y + p.C1)
+        cs = (2.0 * sxy + p.C2) / (sxx + syy + p.C2)
+    return {"map": l * cs, "l": l, "cs": cs, "mu_x": mu_x, "mu_y": mu_y, "sxx": sxx, "syy": syy, "sxy": sxy}
+
+
+def ssim3d(x, y, p: SSIMParams | None = None, kt: int = 1) -> np.ndarray:
+    """Mean of every SSIM-3D map frame, float64 [T-kt+1]."""
+    m = ssim3d_map(x, y, p, kt)["map"]
+    return np.array([mean_pool(m[t]) for t in range(m.shape[0])])
+
+
+def msssim3d(x, y, p: SSIMParams | None = None, kt: int = 1, weights=MS_WEIGHTS, n_scales: int = 5,
+             renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product") -> dict:
+    """MS-SSIM-3D per map frame: every frame of both clips is reduced by the
+    2x2 pyramid of MS-SSIM; at each scale the SSIM-3D maps give CS_j(t) (mean
+    cs, j < M) and S_M(t) (mean l*cs at the coarsest scale), combined per map
+    frame t as in msssim.  Returns {'score' [T-kt+1], 'cs' [T-kt+1, M-1],
+    's_M' [T-kt+1]}."""
+    p = p or SSIMParams(window="box", k=11)
+    if aggregation not in ("product", "sum"):
+        raise ValueError(f"unknown aggregation {aggregation!r}")
+    w = _ms_weights(weights, n_scales, renorm or aggregation == "sum")
+    xf = _as_f64(x)
+    yf = _as_f64(y)
+    xs = [np.stack(v) for v in zip(*[pyramid(f, n_scales) for f in xf])]
+    ys = [np.stack(v) for v in zip(*[pyramid(f, n_scales) for f in yf])]
+    to = xf.shape[0] - kt + 1
+    cs = np.zeros((to, n_scales - 1))
+    s_m = np.zeros(to)
+    for j in range(n_scales):
+        r = ssim3d_map(xs[j], ys[j], p, kt)
+        for t in range(to):
+            if j < n_scales - 1:
+                cs[t, j] = mean_pool(r["cs"][t])
+            else:
+                s_m[t] = mean_pool(r["map"][t])
+    score = np.array([_ms_combine(list(cs[t]), s_m[t], w, cs_clamp, aggregation) for t in range(to)])
+    return {"score": score, "cs": cs, "s_M": s_m, "weights": w}
