@@ -332,6 +332,15 @@ def variants(P, x, y, xt, yt, dev, stream, only=()):
         ms = _time(lambda: P.color_ssim(xr, yr, cfg), stream=stream)
         rec("c1_color_ssim", ms, 21 * H * W, "21 RGB 1080p u8 frames (planes from the luma batch), BT.709 "
             "YCbCr, Gaussian 11x11 per channel, 0.8/0.1/0.1")
+    if want("c1_ssim3d_kt5", "c1_msssim3d_kt5"):
+        # the 64 frames as one clip; 60 map frames of the 11 x 11 x 5 box
+        kt, n_out = 5, xt.shape[0] - 4
+        box = P.SSIMConfig(window="box", k=11)
+        ms = _time(lambda: P.ssim3d(xt, yt, kt, box), stream=stream)
+        rec("c1_ssim3d_kt5", ms, n_out * H * W, "SSIM-3D, 64-frame 1080p u8 clip, 11x11x5 box, rolling "
+            "temporal sums, per-frame means (60 map frames)")
+        ms = _time(lambda: P.ms_ssim3d(xt, yt, kt, box), stream=stream)
+        rec("c1_msssim3d_kt5", ms, n_out * H * W, "MS-SSIM-3D, same clip, 5 scales, 11x11x5 box")
     if want("c2_"):
         _variants_c2(P, dev, stream, rec)
     if want("c3_"):

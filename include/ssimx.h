@@ -264,6 +264,46 @@ ssimx_status ssimx_color_ssim(const ssimx_params* p, double alpha, double beta, 
                               int64_t batch_stride, int batch, float* score_out, float* channel_scores, void* ws,
                               size_t ws_bytes, void* stream);
 
+/* ---------------- SSIM-3D / MS-SSIM-3D ------------------------------------
+ * Spatio-Temporal SSIM subsection: SSIM whose mean, variance and covariance
+ * are taken over k x k x kt rectangular spatio-temporal boxes (equal weights,
+ * N = k^2 kt samples).  Map frame t, position (i, j) covers frames t..t+kt-1,
+ * rows i..i+k-1 and columns j..j+k-1 of the clip; boxes lie inside the clip in
+ * every axis, so a clip of `frames` frames gives frames-kt+1 map frames of
+ * (height-k+1) x (width-k+1).  Computed with rolling temporal sums (add the
+ * entering frame, drop the leaving one), so the cost per frame is independent
+ * of kt.
+ *
+ * p: window must be SSIMX_WIN_BOX, stride 1, SSIMX_PAD_VALID, k <= 16
+ *    (else ENOTSUP); algo is ignored.  kt: 1..64 (else EINVAL).
+ * ref, dis: clips of `frames` frames; frame f of a clip is its image `f`
+ *    (batch_stride apart).  Any dtype: 8-bit clips use exact uint32 sums,
+ *    others float64 sums.
+ * map_out (nullable): float32 [frames-kt+1][height-k+1][map_pitch] with frame
+ *    stride map_frame_stride; score_out (nullable, not both null): float32
+ *    [frames-kt+1] mean of each map frame.
+ * frames < kt or a frame smaller than the window: ETOOSMALL.
+ * Workspace: ssimx_ssim3d_workspace_size. */
+ssimx_status ssimx_ssim3d_workspace_size(const ssimx_params* p, int kt, int dtype, int width, int height, int frames,
+                                         size_t* bytes);
+ssimx_status ssimx_ssim3d(const ssimx_params* p, int kt, const ssimx_image* ref, const ssimx_image* dis, int frames,
+                          float* map_out, long long map_pitch, long long map_frame_stride, float* score_out,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* MS-SSIM-3D: every frame of both clips is reduced by the 2x2-average pyramid
+ * of msssim (the temporal extent is unchanged); at each scale the SSIM-3D map
+ * frames give CS_j(t) (mean cs, j < M) and S_M(t) (mean l*cs at the coarsest
+ * scale), combined per map frame t exactly as msssim combines them (weights
+ * and flags as for msssim, SSIMX_MS_SUM included).  Every scale must hold at
+ * least one window.  score_out: float32 [frames-kt+1]; cs_out (nullable):
+ * float32 [frames-kt+1][n_scales] in the layout of msssim.
+ * Workspace: ssimx_msssim3d_workspace_size. */
+ssimx_status ssimx_msssim3d_workspace_size(const ssimx_params* p, int kt, int n_scales, int dtype, int width,
+                                           int height, int frames, size_t* bytes);
+ssimx_status ssimx_msssim3d(const ssimx_params* p, int kt, const float* weights, int n_scales, int flags,
+                            const ssimx_image* ref, const ssimx_image* dis, int frames, float* score_out,
+                            float* cs_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Colour front end of the differentiable-loss workload: BT.601 luma
  * Y = 0.299 R + 0.587 G + 0.114 B of planar RGB (the paper's Channel-wise SSIM
  * subsection prints the BT.709 matrix; BT.601 weights are used here).

@@ -104,6 +104,12 @@ _SIGS = {
     "ssimx_color_workspace_size": (c_int, [_P, c_int, c_int, c_int, POINTER(c_size_t)]),
     "ssimx_color_ssim": (c_int, [_P, c_double, c_double, c_void_p, c_void_p, c_int, c_int, c_int, c_int64, c_int64,
                                  c_int64, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ssimx_ssim3d_workspace_size": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, POINTER(c_size_t)]),
+    "ssimx_ssim3d": (c_int, [_P, c_int, _I, _I, c_int, c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_size_t,
+                             c_void_p]),
+    "ssimx_msssim3d_workspace_size": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, c_int, POINTER(c_size_t)]),
+    "ssimx_msssim3d": (c_int, [_P, c_int, _F, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_void_p, c_size_t,
+                               c_void_p]),
     "ssimx_strerror": (c_char_p, [c_int]),
     "ssimx_last_hip_error": (c_int, []),
     "ssimx_version": (c_int, []),

@@ -314,6 +314,62 @@ def color_ssim(x_rgb: torch.Tensor, y_rgb: torch.Tensor, cfg: SSIMConfig | None 
     return (out, ch) if return_channels else out
 
 
+def _clip_pair(x: torch.Tensor, y: torch.Tensor):
+    if x.dim() != 3:
+        raise ValueError("clips must be (T, H, W) tensors")
+    return _pair(x, y)
+
+
+def ssim3d(x: torch.Tensor, y: torch.Tensor, kt: int, cfg: SSIMConfig | None = None, return_map: bool = False,
+           **kw):
+    """SSIM-3D of two clips (T, H, W) with the k x k x kt rectangular box:
+    float32 [T-kt+1] mean of each map frame; with return_map also the float32
+    map [T-kt+1, H-k+1, W-k+1].  The window defaults to the 11 x 11 box."""
+    if cfg is None:
+        kw.setdefault("window", "box")
+    cfg = _cfg(cfg, kw)
+    xi, yi, t = _clip_pair(x, y)
+    p = cfg.to_c()
+    n = ctypes.c_size_t()
+    L.check(L.lib.ssimx_ssim3d_workspace_size(ctypes.byref(p), kt, xi.dtype, xi.width, xi.height, t, ctypes.byref(n)),
+            "ssimx_ssim3d_workspace_size")
+    ws = _workspace(n.value, x.device)
+    to, ho, wo = t - kt + 1, xi.height - cfg.k + 1, xi.width - cfg.k + 1
+    score = torch.empty(to, dtype=torch.float32, device=x.device)
+    m = torch.empty((to, ho, wo), dtype=torch.float32, device=x.device) if return_map else None
+    st = L.lib.ssimx_ssim3d(ctypes.byref(p), kt, ctypes.byref(xi), ctypes.byref(yi), t,
+                            m.data_ptr() if m is not None else None, wo, ho * wo, score.data_ptr(),
+                            ws.data_ptr(), ws.numel(), _stream(x))
+    L.check(st, "ssimx_ssim3d")
+    return (score, m) if return_map else score
+
+
+def ms_ssim3d(x: torch.Tensor, y: torch.Tensor, kt: int, cfg: SSIMConfig | None = None, weights=MS_WEIGHTS,
+              n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product",
+              return_cs: bool = False, **kw):
+    """MS-SSIM-3D of two clips (T, H, W): float32 [T-kt+1] (and, with
+    return_cs, [T-kt+1, n_scales] holding CS_1..CS_{M-1} and S_M per map
+    frame).  The window defaults to the 11 x 11 box."""
+    if cfg is None:
+        kw.setdefault("window", "box")
+    cfg = _cfg(cfg, kw)
+    xi, yi, t = _clip_pair(x, y)
+    p = cfg.to_c()
+    flags = _ms_flags(renorm, cs_clamp, aggregation)
+    n = ctypes.c_size_t()
+    L.check(L.lib.ssimx_msssim3d_workspace_size(ctypes.byref(p), kt, n_scales, xi.dtype, xi.width, xi.height, t,
+                                                ctypes.byref(n)), "ssimx_msssim3d_workspace_size")
+    ws = _workspace(n.value, x.device)
+    to = t - kt + 1
+    score = torch.empty(to, dtype=torch.float32, device=x.device)
+    cs = torch.empty((to, n_scales), dtype=torch.float32, device=x.device) if return_cs else None
+    st = L.lib.ssimx_msssim3d(ctypes.byref(p), kt, _weights(weights, n_scales), n_scales, flags, ctypes.byref(xi),
+                              ctypes.byref(yi), t, score.data_ptr(), cs.data_ptr() if cs is not None else None,
+                              ws.data_ptr(), ws.numel(), _stream(x))
+    L.check(st, "ssimx_msssim3d")
+    return (score, cs) if return_cs else score
+
+
 def rgb_to_luma(rgb: torch.Tensor) -> torch.Tensor:
     """BT.601 luma of planar RGB (B, 3, H, W) or (3, H, W), float32/bfloat16
     -> float32 (B, H, W)."""

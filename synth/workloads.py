@@ -27,6 +27,10 @@ Recipes (all numpy float64 before the final rounding):
                  window (Gaussian 11 or box 8) and stride (1 or 4).
   config 4       B x 3 x H x W float32 RGB fields in [16/255, 235/255];
                  dis = ref + N(0, 0.05^2), not clipped.
+  video clip     T frames HxW u8 panning across one field (frame f is the crop
+                 at (f*vy, f*vx), a constant integer pan), dis = config-1 DCT
+                 quantisation per frame with q ~ U{qlo..qhi}; the clips of
+                 SSIM-3D (temporally correlated, as in the video databases).
 """
 from __future__ import annotations
 
@@ -169,3 +173,19 @@ def stress_pairs(h: int = 61, w: int = 77, stream: int = 0):
     cases["blocky_flat"] = (np.where((yy // 16 + xx // 16) % 2 == 0, 20, 230).astype(np.uint8),
                             np.where((yy // 16 + xx // 16) % 2 == 0, 22, 229).astype(np.uint8))
     return cases
+
+
+def video_clip(frames: int = 16, h: int = 270, w: int = 480, vy: int = 1, vx: int = 2, qlo: int = 16,
+               qhi: int = 48, stream: int = 0):
+    rng = rng_for(5, stream)
+    field = smooth_field(rng, h + abs(vy) * frames, w + abs(vx) * frames, 16, 235)
+    base = _round_clip(field, 0, 255, np.uint8)
+    ref = np.empty((frames, h, w), np.uint8)
+    dis = np.empty((frames, h, w), np.uint8)
+    oy = 0 if vy >= 0 else abs(vy) * frames
+    ox = 0 if vx >= 0 else abs(vx) * frames
+    for f in range(frames):
+        r0, c0 = oy + f * vy, ox + f * vx
+        ref[f] = base[r0:r0 + h, c0:c0 + w]
+        dis[f] = dct_quantise(ref[f], int(rng.integers(qlo, qhi + 1)))
+    return ref, dis

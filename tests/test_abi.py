@@ -194,3 +194,36 @@ def test_pool_map_validates_before_launch(L):
     assert f(ctypes.byref(pl), 12345, 64, 64, 64, 4096, 1, 12345, None, 0, None) == L.EWORKSPACE
     big = _pool(L, L.POOL_FIVE_NUMBER)
     assert L.lib.ssimx_pool_workspace_size(ctypes.byref(big), 64, 64, 2, ctypes.byref(n)) == L.OK
+
+
+def test_ssim3d_validates_before_launch(L):
+    box = _params(L, window=L.WIN_BOX, k=11)
+    clip = L.Image(12345, L.U8, 64, 48, 64, 64 * 48)
+    s = ctypes.c_void_p(1)
+    n = ctypes.c_size_t()
+
+    def call(p, kt, frames=8, m=None, sc=s, ws=None, nb=0):
+        return L.lib.ssimx_ssim3d(ctypes.byref(p), kt, ctypes.byref(clip), ctypes.byref(clip), frames, m, 64,
+                                  64 * 48, sc, ws, nb, None)
+
+    assert call(_params(L, window=L.WIN_GAUSSIAN, k=11), 3) == L.ENOTSUP
+    assert call(_params(L, window=L.WIN_BOX, k=11, stride=2), 3) == L.ENOTSUP
+    assert call(_params(L, window=L.WIN_BOX, k=11, padding=L.PAD_ZERO), 3) == L.ENOTSUP
+    assert call(_params(L, window=L.WIN_BOX, k=17), 3) == L.ENOTSUP
+    assert call(box, 0) == L.EINVAL and call(box, 65) == L.EINVAL
+    assert call(box, 9, frames=8) == L.ETOOSMALL
+    assert call(box, 3, sc=None) == L.EINVAL          # neither map nor scores
+    assert call(box, 3) == L.EWORKSPACE
+    assert L.lib.ssimx_ssim3d_workspace_size(ctypes.byref(box), 3, L.U8, 64, 48, 8, ctypes.byref(n)) == L.OK
+    assert n.value > 0
+    assert call(box, 3, ws=ctypes.c_void_p(1), nb=n.value - 1) == L.EWORKSPACE
+    assert L.lib.ssimx_ssim3d_workspace_size(ctypes.byref(box), 3, L.U8, 10, 48, 8, ctypes.byref(n)) == L.ETOOSMALL
+    w = (ctypes.c_float * 3)(0.2, 0.3, 0.5)
+    # 48 -> 24 -> 12 rows: three scales hold an 11 x 11 box, four do not
+    assert L.lib.ssimx_msssim3d_workspace_size(ctypes.byref(box), 3, 3, L.U8, 64, 48, 8, ctypes.byref(n)) == L.OK
+    assert L.lib.ssimx_msssim3d_workspace_size(ctypes.byref(box), 3, 4, L.U8, 64, 48, 8,
+                                               ctypes.byref(n)) == L.ETOOSMALL
+    assert L.lib.ssimx_msssim3d(ctypes.byref(box), 3, w, 3, 8, ctypes.byref(clip), ctypes.byref(clip), 8, s, None,
+                                None, 0, None) == L.EINVAL
+    assert L.lib.ssimx_msssim3d(ctypes.byref(box), 3, w, 3, 0, ctypes.byref(clip), ctypes.byref(clip), 8, s, None,
+                                None, 0, None) == L.EWORKSPACE
