@@ -100,9 +100,11 @@ __device__ __forceinline__ float vol_value(double sx, double sy, double sxx, dou
   return ssim_value(t, mode);
 }
 
-template <typename T, typename Acc, int OH, int KCAP>
+// KC > 0: the window size is the compile-time constant KC (loops unroll);
+// KC == 0: runtime k <= KCAP.
+template <typename T, typename Acc, int OH, int KC, int KCAP>
 __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
-  using S = VolShape<Acc, OH, KCAP>;
+  using S = VolShape<Acc, OH, (KC > 0 ? KC : KCAP)>;
   using RawT = Raw<T, Acc>;
   __shared__ Acc tsum[S::T_WORDS];  // [5][IH][IWP] temporal sums of the footprint
   __shared__ Acc hsum[S::H_WORDS];  // [5][IH][HSP] k-wide row sums
@@ -115,7 +117,8 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
   if (nseg <= 0) return;  // uniform over the workgroup
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int col0 = tx * kVolOW, row0 = ty * OH;
-  const int k = a.k, kt = a.kt;
+  const int k = KC > 0 ? KC : a.k;
+  const int kt = a.kt;
   const int IW = kVolOW + k - 1, IH = OH + k - 1;
   const int npx = IW * IH;
   const int tid = threadIdx.x;
@@ -200,7 +203,9 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
       const Acc* src = tsum + (m * IH + r) * S::IWP + sg * kVolSeg;
       Acc* dst = hsum + (m * IH + r) * S::HSP + sg * kVolSeg;
       Acc s = (Acc)0;
-      for (int c = 0; c < k; ++c) s += src[c];
+#pragma unroll
+      for (int c = 0; c < (KC > 0 ? KC : KCAP); ++c)
+        if (KC > 0 || c < k) s += src[c];
       dst[0] = s;
 #pragma unroll
       for (int j = 1; j < kVolSeg; ++j) {
@@ -220,7 +225,9 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
       for (int m = 0; m < 5; ++m) {
         const Acc* col = hsum + (m * IH + 4 * g) * S::HSP + j;
         Acc s = (Acc)0;
-        for (int r = 0; r < k; ++r) s += col[r * S::HSP];
+#pragma unroll
+        for (int r = 0; r < (KC > 0 ? KC : KCAP); ++r)
+          if (KC > 0 || r < k) s += col[r * S::HSP];
         acc[0][m] = s;
 #pragma unroll
         for (int i = 1; i < 4; ++i) {
@@ -255,10 +262,12 @@ template <typename T, typename Acc>
 int launch_vol_t(const VolArgs& a, int nsegs, hipStream_t st) {
   constexpr int OH = vol_oh<Acc>();
   const dim3 grid(a.tiles_x * a.tiles_y, nsegs);
-  if (a.k <= 11)
-    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 11>), grid, dim3(kVolNT), 0, st, a);
+  if (a.k == 11)
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 11, 11>), grid, dim3(kVolNT), 0, st, a);
+  else if (a.k < 11)
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 0, 11>), grid, dim3(kVolNT), 0, st, a);
   else
-    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, kVolKMax>), grid, dim3(kVolNT), 0, st, a);
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 0, kVolKMax>), grid, dim3(kVolNT), 0, st, a);
   return (int)hipGetLastError();
 }
 
