@@ -49,6 +49,7 @@ __all__ = [
     "scale_factor", "downsample_avg", "scaled_pooled_ssim", "enhanced_ssim",
     "rgb_to_ycbcr_bt709", "color_ssim", "BT709_Y", "BT709_CB", "BT709_CR",
     "box_sums3d", "ssim3d_map", "ssim3d", "msssim3d",
+    "pool_geometric", "pool_harmonic", "pool_median", "pool_windowed",
 ]
 
 # Exponents of the original five-scale MS-SSIM, as used by the configurations
@@ -602,6 +603,50 @@ def _percentile_linear(sorted_v: np.ndarray, frac: float) -> float:
     lo = int(math.floor(h))
     hi = min(lo + 1, sorted_v.size - 1)
     return float(sorted_v[lo] + (h - lo) * (sorted_v[hi] - sorted_v[lo]))
+
+
+# Moment-based and windowed pooling (Moment-Based Pooling subsection and the
+# windowed means after the CoV equation).  The paper applies them to the
+# series of frame scores (temporal pooling); every pooling above applies to
+# such a series too (a 1 x T map).  Readings: the geometric mean of values
+# with a zero is 0 and with a negative value NaN; the harmonic mean of values
+# with a zero is 0; windows of w consecutive values lie inside the series (T -
+# w + 1 of them) and their local values are averaged with equal weights.
+def pool_geometric(q: np.ndarray) -> float:
+    """Geometric mean exp((1/n) sum log Q)."""
+    v = np.asarray(q, dtype=np.float64).ravel()
+    if np.any(v < 0) or np.any(np.isnan(v)):
+        return float("nan")
+    if np.any(v == 0):
+        return 0.0
+    return math.exp(math.fsum(np.log(v)) / v.size)
+
+
+def pool_harmonic(q: np.ndarray) -> float:
+    """Harmonic mean n / sum (1/Q)."""
+    v = np.asarray(q, dtype=np.float64).ravel()
+    if np.any(v == 0):
+        return 0.0
+    return v.size / math.fsum(1.0 / v)
+
+
+def pool_median(q: np.ndarray) -> float:
+    """Sample median (mean of the two middle values for even n)."""
+    s = np.sort(np.asarray(q, dtype=np.float64).ravel())
+    return _percentile_linear(s, 0.5)
+
+
+_WINDOW_MEANS = {"am": pool_mean, "gm": pool_geometric, "hm": pool_harmonic, "cov": pool_cov}
+
+
+def pool_windowed(q: np.ndarray, w: int, mean: str) -> float:
+    """Windowed pooling W-AM / W-GM / W-HM / W-CoV: the mean over every window
+    of w consecutive values of the window's AM, GM, HM or CoV."""
+    v = np.asarray(q, dtype=np.float64).ravel()
+    if not 1 <= w <= v.size:
+        raise ValueError("window length must be in 1..n")
+    f = _WINDOW_MEANS[mean]
+    return math.fsum(f(v[t:t + w]) for t in range(v.size - w + 1)) / (v.size - w + 1)
 
 
 def pool_five_number(q: np.ndarray) -> float:

@@ -142,3 +142,54 @@ def test_color_ssim_reductions():
     r = O.color_ssim(x, y, p)
     s = r["channels"]
     assert r["score"] == pytest.approx(0.8 * s[0] + 0.1 * s[1] + 0.1 * s[2], rel=1e-14)
+
+
+# ---------------------------------------------------------------- temporal pooling
+def _series(n, seed, lo=0.3, hi=1.0):
+    return np.random.default_rng(seed).uniform(lo, hi, n)
+
+
+def test_pythagorean_means_against_scipy_and_closed_forms():
+    from scipy import stats
+    s = _series(257, 50)
+    assert abs(O.pool_geometric(s) - stats.gmean(s)) < 1e-14
+    assert abs(O.pool_harmonic(s) - stats.hmean(s)) < 1e-14
+    assert O.pool_mean(s) > O.pool_geometric(s) > O.pool_harmonic(s)
+    a, b = 0.36, 0.81
+    assert abs(O.pool_geometric(np.array([a, b])) - math.sqrt(a * b)) < 1e-15
+    assert abs(O.pool_harmonic(np.array([a, b])) - 2 * a * b / (a + b)) < 1e-15
+    c = np.full(9, 0.7)
+    assert abs(O.pool_geometric(c) - 0.7) < 1e-15 and abs(O.pool_harmonic(c) - 0.7) < 1e-15
+    assert O.pool_geometric(np.array([0.5, 0.0])) == 0.0 and O.pool_harmonic(np.array([0.5, 0.0])) == 0.0
+    assert math.isnan(O.pool_geometric(np.array([0.5, -0.1])))
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 100])
+def test_median_against_numpy(n):
+    s = _series(n, 51 + n)
+    assert O.pool_median(s) == float(np.median(s))
+
+
+def test_windowed_means_reduce_at_the_ends():
+    from numpy.lib.stride_tricks import sliding_window_view
+    from scipy import stats
+    s = _series(60, 52)
+    n = s.size
+    for m in ("am", "gm", "hm"):
+        assert abs(O.pool_windowed(s, 1, m) - s.mean()) < 1e-14
+    assert O.pool_windowed(s, 1, "cov") == 0.0
+    assert abs(O.pool_windowed(s, n, "am") - s.mean()) < 1e-14
+    assert abs(O.pool_windowed(s, n, "gm") - stats.gmean(s)) < 1e-14
+    assert abs(O.pool_windowed(s, n, "hm") - stats.hmean(s)) < 1e-14
+    assert abs(O.pool_windowed(s, n, "cov") - s.std() / s.mean()) < 1e-13
+    # brute force with library windows at an interior length
+    win = sliding_window_view(s, 9)
+    assert abs(O.pool_windowed(s, 9, "gm") - stats.gmean(win, axis=1).mean()) < 1e-14
+    assert abs(O.pool_windowed(s, 9, "hm") - stats.hmean(win, axis=1).mean()) < 1e-14
+    assert abs(O.pool_windowed(s, 9, "cov") - (win.std(axis=1) / win.mean(axis=1)).mean()) < 1e-13
+    # windowed AM weights interior values more than the ends
+    w = np.zeros(n)
+    w[0] = 1.0
+    assert abs(O.pool_windowed(w, 5, "am") - 1.0 / (5 * (n - 4))) < 1e-16
+    with pytest.raises(ValueError):
+        O.pool_windowed(s, n + 1, "am")
