@@ -202,6 +202,17 @@ ssimx_status ssimx_integral_images(const ssimx_image* ref, const ssimx_image* di
  *                    floor((n-1) q) and the next one
  *   PERCENTILE       the m = ceil(p n / 100) smallest values divided by r,
  *                    then the mean                          (0 <= p <= 100, r > 0)
+ * and, from the Moment-Based Pooling subsection and the windowed means after
+ * the CoV equation (the paper uses them on the series of frame scores: pass
+ * a batch of 1 x T maps, one row of T frame scores per video):
+ *   GEOMETRIC        exp((1/n) sum log Q); 0 with a zero value, NaN with a
+ *                    negative one
+ *   HARMONIC         n / sum (1/Q); 0 with a zero value
+ *   MEDIAN           the interpolated median (rank (n-1)/2)
+ *   WIN_AM, WIN_GM,  mean over the n-p+1 windows of p consecutive values of
+ *   WIN_HM, WIN_COV  the window's arithmetic / geometric / harmonic mean or
+ *                    CoV; p an integer in 1..n (ETOOSMALL if p > n), the map
+ *                    must be a single row (h == 1, else EINVAL)
  * Sums are accumulated in float64 in a fixed order (deterministic); order
  * statistics are exact (radix select on the float bit patterns). */
 typedef enum {
@@ -211,7 +222,14 @@ typedef enum {
   SSIMX_POOL_MINKOWSKI = 3,
   SSIMX_POOL_DIST_WEIGHTED = 4,
   SSIMX_POOL_FIVE_NUMBER = 5,
-  SSIMX_POOL_PERCENTILE = 6
+  SSIMX_POOL_PERCENTILE = 6,
+  SSIMX_POOL_GEOMETRIC = 7,
+  SSIMX_POOL_HARMONIC = 8,
+  SSIMX_POOL_MEDIAN = 9,
+  SSIMX_POOL_WIN_AM = 10,
+  SSIMX_POOL_WIN_GM = 11,
+  SSIMX_POOL_WIN_HM = 12,
+  SSIMX_POOL_WIN_COV = 13
 } ssimx_pool_kind;
 
 typedef struct {

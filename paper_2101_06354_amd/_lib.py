@@ -43,7 +43,8 @@ class Pool(ctypes.Structure):
     _fields_ = [("kind", c_int), ("p", c_double), ("o", c_double), ("r", c_double)]
 
 
-POOL_MEAN, POOL_COV, POOL_MEAN_DEV, POOL_MINKOWSKI, POOL_DIST_WEIGHTED, POOL_FIVE_NUMBER, POOL_PERCENTILE = range(7)
+(POOL_MEAN, POOL_COV, POOL_MEAN_DEV, POOL_MINKOWSKI, POOL_DIST_WEIGHTED, POOL_FIVE_NUMBER, POOL_PERCENTILE,
+ POOL_GEOMETRIC, POOL_HARMONIC, POOL_MEDIAN, POOL_WIN_AM, POOL_WIN_GM, POOL_WIN_HM, POOL_WIN_COV) = range(14)
 
 
 class SSIMXError(RuntimeError):

@@ -66,7 +66,8 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 // kind: 0 sum Q | 1 sum Q, Q^2 | 2 sum |Q - mu|^p | 3 sum (1-Q)^p | 4 sum (1-Q)^p Q, (1-Q)^p
-// | 5 sum of Q below the per-frame threshold, and their count
+// | 5 sum of Q below the per-frame threshold, and their count | 6 sum log Q | 7 sum 1/Q over
+// the non-zero values, and the number of zeros
 __global__ __launch_bounds__(kPoolNT) void pool_sums_kernel(MapArg a, int kind, double p, int ip, const double* mu,
                                                             const uint32_t* thr_key, double* partial) {
   __shared__ double red[2][kPoolNT / 64];
@@ -88,11 +89,18 @@ __global__ __launch_bounds__(kPoolNT) void pool_sums_kernel(MapArg a, int kind, 
         s1 += wgt;
         break;
       }
-      default:  // below the m-th smallest value of the frame
+      case 5:  // below the m-th smallest value of the frame
         if (ordered_key(qf) < tk) {
           s0 += q;
           s1 += 1.0;
         }
+        break;
+      case 6: s0 += (double)logf(qf); break;
+      default:  // reciprocals; zeros (of either sign) are counted instead
+        if (q == 0.0)
+          s1 += 1.0;
+        else
+          s0 += 1.0 / q;
         break;
     }
   };
@@ -180,6 +188,14 @@ __global__ void pool_finish_kernel(const double* partial, const double* total, i
       double acc = q[0] + q[1];
       for (int j = 0; j < 3; ++j) acc += q[2 + 2 * j] + f.frac[j] * (q[3 + 2 * j] - q[2 + 2 * j]);
       v = acc / 5.0;
+      break;
+    }
+    case SSIMX_POOL_GEOMETRIC: v = exp(s0 / f.n); break;
+    case SSIMX_POOL_HARMONIC: v = s1 > 0.0 ? 0.0 : f.n / s0; break;
+    case SSIMX_POOL_MEDIAN: {
+      const uint32_t* k = keys + (int64_t)frame * kStateWords + kPre;
+      const double lo = (double)key_value(k[0]), hi = (double)key_value(k[1]);
+      v = lo + f.frac[0] * (hi - lo);
       break;
     }
     case SSIMX_POOL_PERCENTILE: {
@@ -341,6 +357,65 @@ __global__ __launch_bounds__(256) void sel_step_kernel(SelArgs s, int shift) {
   }
 }
 
+// Windowed means of a single-row map (a series of frame scores): one block
+// per series, thread t takes the windows t, t + NT, ...; every window value is
+// summed directly in float64, then the block adds its windows in a fixed order.
+// mean: 0 AM | 1 GM | 2 HM | 3 CoV.
+__global__ __launch_bounds__(kPoolNT) void pool_window_kernel(MapArg a, int win, int mean, float* out,
+                                                              int64_t out_stride) {
+  __shared__ double red[kPoolNT / 64];
+  const int frame = blockIdx.x;
+  const float* s = a.map + (int64_t)frame * a.bstride;
+  const int nw = a.w - win + 1;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < nw; t += kPoolNT) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < win; ++i) {
+      const float vf = s[t + i];
+      const double v = (double)vf;
+      if (mean == 0) {
+        s1 += v;
+      } else if (mean == 1) {
+        s1 += (double)logf(vf);
+      } else if (mean == 2) {
+        if (v == 0.0)
+          s2 += 1.0;  // zeros counted
+        else
+          s1 += 1.0 / v;
+      } else {
+        s1 += v;
+        s2 += v * v;
+      }
+    }
+    double r;
+    if (mean == 0) {
+      r = s1 / win;
+    } else if (mean == 1) {
+      r = exp(s1 / win);
+    } else if (mean == 2) {
+      r = s2 > 0.0 ? 0.0 : win / s1;
+    } else {
+      const double mu = s1 / win;
+      r = sqrt(fmax(s2 / win - mu * mu, 0.0)) / mu;
+    }
+    acc += r;
+  }
+  acc = wave_sum_d(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kPoolNT / 64; ++w) t += red[w];
+    out[(int64_t)frame * out_stride] = (float)(t / nw);
+  }
+}
+
+bool windowed(int kind) { return kind >= SSIMX_POOL_WIN_AM && kind <= SSIMX_POOL_WIN_COV; }
+
+bool order_stat(int kind) {
+  return kind == SSIMX_POOL_FIVE_NUMBER || kind == SSIMX_POOL_PERCENTILE || kind == SSIMX_POOL_MEDIAN;
+}
+
 int blocks_per_frame(int h) { return h < 64 ? h : 64; }
 
 }  // namespace
@@ -352,7 +427,7 @@ size_t pool_ws_bytes(const ssimx_pool* pl, int w, int h, int batch) {
   ws.take(sizeof(double) * 2 * (size_t)batch * nblk);  // block sums
   ws.take(sizeof(double) * 2 * (size_t)batch * nblk);  // second set (totals)
   ws.take(sizeof(double) * (size_t)batch);              // per-frame mean
-  if (pl->kind == SSIMX_POOL_FIVE_NUMBER || pl->kind == SSIMX_POOL_PERCENTILE) {
+  if (order_stat(pl->kind)) {
     ws.take(sizeof(uint32_t) * kStateWords * (size_t)batch);
     ws.take(sizeof(uint32_t) * 256 * kMaxTargets * (size_t)batch);
   }
@@ -370,6 +445,14 @@ ssimx_status check_pool(const ssimx_pool* pl) {
     case SSIMX_POOL_MINKOWSKI: return pl->p > 0.0 ? SSIMX_OK : SSIMX_EINVAL;
     case SSIMX_POOL_DIST_WEIGHTED: return pl->p >= 0.0 ? SSIMX_OK : SSIMX_EINVAL;
     case SSIMX_POOL_PERCENTILE: return (pl->p >= 0.0 && pl->p <= 100.0 && pl->r > 0.0) ? SSIMX_OK : SSIMX_EINVAL;
+    case SSIMX_POOL_GEOMETRIC:
+    case SSIMX_POOL_HARMONIC:
+    case SSIMX_POOL_MEDIAN: return SSIMX_OK;
+    case SSIMX_POOL_WIN_AM:
+    case SSIMX_POOL_WIN_GM:
+    case SSIMX_POOL_WIN_HM:
+    case SSIMX_POOL_WIN_COV: return (pl->p >= 1.0 && pl->p == floor(pl->p) && pl->p < 2147483648.0) ? SSIMX_OK
+                                                                                                  : SSIMX_EINVAL;
     default: return SSIMX_EINVAL;
   }
 }
@@ -397,12 +480,22 @@ ssimx_status pool_run(const ssimx_pool* pl, const float* map, int w, int h, int6
   const int ip = int_power(pl->p);
   int err = 0;
   switch (pl->kind) {
+    case SSIMX_POOL_WIN_AM:
+    case SSIMX_POOL_WIN_GM:
+    case SSIMX_POOL_WIN_HM:
+    case SSIMX_POOL_WIN_COV:
+      hipLaunchKernelGGL(pool_window_kernel, dim3(batch), dim3(kPoolNT), 0, st, a, (int)pl->p,
+                         (int)pl->kind - SSIMX_POOL_WIN_AM, out, out_stride);
+      break;
     case SSIMX_POOL_MEAN:
     case SSIMX_POOL_COV:
     case SSIMX_POOL_MINKOWSKI:
-    case SSIMX_POOL_DIST_WEIGHTED: {
+    case SSIMX_POOL_DIST_WEIGHTED:
+    case SSIMX_POOL_GEOMETRIC:
+    case SSIMX_POOL_HARMONIC: {
       const int k = pl->kind == SSIMX_POOL_MEAN ? 0 : pl->kind == SSIMX_POOL_COV ? 1
-                  : pl->kind == SSIMX_POOL_MINKOWSKI ? 3 : 4;
+                  : pl->kind == SSIMX_POOL_MINKOWSKI ? 3 : pl->kind == SSIMX_POOL_DIST_WEIGHTED ? 4
+                  : pl->kind == SSIMX_POOL_GEOMETRIC ? 6 : 7;
       hipLaunchKernelGGL(pool_sums_kernel, grid, dim3(kPoolNT), 0, st, a, k, pl->p, ip, nullptr, nullptr, partial);
       hipLaunchKernelGGL(pool_finish_kernel, fin, dim3(64), 0, st, partial, nullptr, nblk, batch, f, nullptr, nullptr,
                          out, out_stride);
@@ -437,6 +530,13 @@ ssimx_status pool_run(const ssimx_pool* pl, const float* map, int w, int h, int6
           f.frac[j] = hpos - (double)lo;
         }
         nt = 8;
+      } else if (pl->kind == SSIMX_POOL_MEDIAN) {
+        const double hpos = (double)last * 0.5;
+        const uint32_t lo = (uint32_t)floor(hpos);
+        ranks[0] = lo;
+        ranks[1] = lo < last ? lo + 1 : lo;
+        f.frac[0] = hpos - (double)lo;
+        nt = 2;
       } else {
         f.m = (int)ceil(pl->p * n / 100.0);
         if (f.m > (int)(last + 1)) f.m = (int)(last + 1);
@@ -491,6 +591,10 @@ ssimx_status ssimx_pool_map(const ssimx_pool* pool, const float* map, int w, int
   if (w < 1 || h < 1) return SSIMX_ETOOSMALL;
   if (pitch < w || (batch > 1 && batch_stride < pitch * (long long)h)) return SSIMX_EINVAL;
   if ((long long)w * h >= (1ll << 31)) return SSIMX_ENOTSUP;
+  if (windowed(pool->kind)) {
+    if (h != 1) return SSIMX_EINVAL;
+    if (pool->p > (double)w) return SSIMX_ETOOSMALL;
+  }
   if (!ws || ws_bytes < pool_ws_bytes(pool, w, h, batch)) return SSIMX_EWORKSPACE;
   return pool_run(pool, map, w, h, pitch, batch_stride, batch, out, 1, ws, (hipStream_t)stream);
 }

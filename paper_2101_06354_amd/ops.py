@@ -239,13 +239,17 @@ def integral_images(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
 
 
 _POOLS = {"mean": L.POOL_MEAN, "cov": L.POOL_COV, "mean_dev": L.POOL_MEAN_DEV, "minkowski": L.POOL_MINKOWSKI,
-          "dist_weighted": L.POOL_DIST_WEIGHTED, "five_number": L.POOL_FIVE_NUMBER, "percentile": L.POOL_PERCENTILE}
+          "dist_weighted": L.POOL_DIST_WEIGHTED, "five_number": L.POOL_FIVE_NUMBER, "percentile": L.POOL_PERCENTILE,
+          "geometric": L.POOL_GEOMETRIC, "harmonic": L.POOL_HARMONIC, "median": L.POOL_MEDIAN,
+          "w_am": L.POOL_WIN_AM, "w_gm": L.POOL_WIN_GM, "w_hm": L.POOL_WIN_HM, "w_cov": L.POOL_WIN_COV}
 
 
 def pool(qmap: torch.Tensor, kind: str = "cov", p: float = 0.0, o: float = 1.0, r: float = 1.0) -> torch.Tensor:
-    """Spatial pooling of quality maps (B, H, W) or (H, W), float32 on the
-    device -> float32 [B].  kind: mean | cov | mean_dev (p, o) | minkowski (p)
-    | dist_weighted (p) | five_number | percentile (p in percent, r)."""
+    """Pooling of quality maps (B, H, W) or (H, W), float32 on the device ->
+    float32 [B].  kind: mean | cov | mean_dev (p, o) | minkowski (p) |
+    dist_weighted (p) | five_number | percentile (p in percent, r) | geometric
+    | harmonic | median | w_am, w_gm, w_hm, w_cov (windows of p values; single
+    row maps, see temporal_pool)."""
     m = qmap.unsqueeze(0) if qmap.dim() == 2 else qmap
     if m.dim() != 3 or m.dtype != torch.float32 or not m.is_cuda or m.stride(2) != 1:
         raise ValueError("qmap must be a float32 device tensor (B, H, W) with contiguous rows")
@@ -259,6 +263,17 @@ def pool(qmap: torch.Tensor, kind: str = "cov", p: float = 0.0, o: float = 1.0, 
                               ws.data_ptr(), ws.numel(), _stream(m))
     L.check(st, "ssimx_pool_map")
     return out
+
+
+def temporal_pool(scores: torch.Tensor, kind: str = "mean", p: float = 0.0, o: float = 1.0,
+                  r: float = 1.0) -> torch.Tensor:
+    """Temporal pooling of frame scores (B, T) or (T,), float32 on the device
+    -> float32 [B]: any pool kind applied to each row of T frame scores (for
+    the windowed kinds p is the window length in frames)."""
+    s = scores.unsqueeze(0) if scores.dim() == 1 else scores
+    if s.dim() != 2:
+        raise ValueError("scores must be (B, T) or (T,)")
+    return pool(s.unsqueeze(1), kind, p, o, r)
 
 
 def scaled_pooled_ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, factor: int = 0,

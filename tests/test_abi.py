@@ -170,9 +170,10 @@ def _pool(L, kind, p=0.0, o=1.0, r=1.0):
     return L.Pool(kind, p, o, r)
 
 
-@pytest.mark.parametrize("kind,p,o,r", [(9, 0, 1, 1), (-1, 0, 1, 1), (2, 0.0, 1, 1), (3, -1.0, 1, 1),
+@pytest.mark.parametrize("kind,p,o,r", [(14, 0, 1, 1), (-1, 0, 1, 1), (2, 0.0, 1, 1), (3, -1.0, 1, 1),
                                         (4, -0.5, 1, 1), (6, 101.0, 1, 1), (6, 5.0, 1, 0.0),
-                                        (1, float("nan"), 1, 1)])
+                                        (1, float("nan"), 1, 1), (10, 0.0, 1, 1), (11, 2.5, 1, 1),
+                                        (13, -3.0, 1, 1)])
 def test_pool_parameters_rejected_on_host(L, kind, p, o, r):
     n = ctypes.c_size_t()
     pl = _pool(L, kind, p, o, r)
@@ -194,6 +195,12 @@ def test_pool_map_validates_before_launch(L):
     assert f(ctypes.byref(pl), 12345, 64, 64, 64, 4096, 1, 12345, None, 0, None) == L.EWORKSPACE
     big = _pool(L, L.POOL_FIVE_NUMBER)
     assert L.lib.ssimx_pool_workspace_size(ctypes.byref(big), 64, 64, 2, ctypes.byref(n)) == L.OK
+    # windowed means: single-row maps, window no longer than the row
+    wp = _pool(L, L.POOL_WIN_GM, 8.0)
+    assert L.lib.ssimx_pool_workspace_size(ctypes.byref(wp), 300, 1, 2, ctypes.byref(n)) == L.OK
+    assert f(ctypes.byref(wp), 12345, 300, 2, 300, 600, 1, 12345, 12345, n.value, None) == L.EINVAL
+    assert f(ctypes.byref(wp), 12345, 7, 1, 7, 7, 1, 12345, 12345, n.value, None) == L.ETOOSMALL
+    assert f(ctypes.byref(wp), 12345, 300, 1, 300, 300, 2, 12345, None, 0, None) == L.EWORKSPACE
 
 
 def test_ssim3d_validates_before_launch(L):

@@ -24,7 +24,10 @@ KINDS = [("mean", {}, lambda q: O.pool_mean(q)),
          ("percentile", {"p": 6, "r": 4000}, lambda q: O.pool_percentile(q, 6, 4000)),
          ("percentile", {"p": 25, "r": 2}, lambda q: O.pool_percentile(q, 25, 2)),
          ("percentile", {"p": 0, "r": 2}, lambda q: O.pool_percentile(q, 0, 2)),
-         ("percentile", {"p": 100, "r": 3}, lambda q: O.pool_percentile(q, 100, 3))]
+         ("percentile", {"p": 100, "r": 3}, lambda q: O.pool_percentile(q, 100, 3)),
+         ("geometric", {}, lambda q: O.pool_geometric(q)),
+         ("harmonic", {}, lambda q: O.pool_harmonic(q)),
+         ("median", {}, lambda q: O.pool_median(q))]
 
 
 @pytest.fixture(scope="module")
@@ -88,3 +91,54 @@ def test_pooling_pitched_batch_and_identity(P, dev):
     assert P.pool(ones, "cov").cpu().tolist() == [0.0, 0.0]
     assert P.pool(ones, "dist_weighted", p=2).cpu().tolist() == [1.0, 1.0]
     assert P.pool(ones, "five_number").cpu().tolist() == [1.0, 1.0]
+
+
+# ---------------------------------------------------------------- temporal pooling
+def _score_series(n_series, T, seed):
+    """Frame-score series: a slow drift with dips, in (0.3, 1)."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(T)
+    base = 0.85 + 0.08 * np.sin(2 * np.pi * t[None, :] / rng.uniform(40, 120, (n_series, 1)))
+    dips = (rng.random((n_series, T)) < 0.05) * rng.uniform(0.1, 0.4, (n_series, T))
+    return np.clip(base - dips + rng.normal(0, 0.01, (n_series, T)), 0.3, 0.999).astype(np.float32)
+
+
+TEMPORAL = [("mean", {}, O.pool_mean), ("geometric", {}, O.pool_geometric), ("harmonic", {}, O.pool_harmonic),
+            ("median", {}, O.pool_median), ("cov", {}, O.pool_cov), ("five_number", {}, O.pool_five_number),
+            ("percentile", {"p": 10, "r": 3}, lambda q: O.pool_percentile(q, 10, 3)),
+            ("minkowski", {"p": 2}, lambda q: O.pool_minkowski(q, 2)),
+            ("dist_weighted", {"p": 0.5}, lambda q: O.pool_distortion_weighted(q, 0.5))]
+WINDOWED = [(m, w) for m in ("am", "gm", "hm", "cov") for w in (1, 7, 80, 301)]
+
+
+@pytest.mark.parametrize("kind,kw,ref", TEMPORAL, ids=[k for k, _, _ in TEMPORAL])
+def test_temporal_pooling_of_frame_scores(P, dev, kind, kw, ref):
+    s = _score_series(5, 301, 60)
+    got = P.temporal_pool(to_dev(s, dev), kind, **kw).cpu().numpy()
+    for b in range(5):
+        want = ref(s[b].astype(np.float64))
+        assert abs(got[b] - want) <= _tol(want), (b, got[b], want)
+
+
+@pytest.mark.parametrize("mean,w", WINDOWED, ids=[f"w_{m}-{w}" for m, w in WINDOWED])
+def test_windowed_temporal_pooling(P, dev, mean, w):
+    s = _score_series(4, 301, 61)
+    got = P.temporal_pool(to_dev(s, dev), f"w_{mean}", p=w).cpu().numpy()
+    for b in range(4):
+        want = O.pool_windowed(s[b].astype(np.float64), w, mean)
+        assert abs(got[b] - want) <= _tol(want), (b, got[b], want)
+
+
+def test_temporal_pooling_edge_values(P, dev):
+    s = np.array([[0.9, 0.0, 0.8, 0.7], [0.9, -0.2, 0.8, 0.7], [0.5, 0.5, 0.5, 0.5]], np.float32)
+    st = to_dev(s, dev)
+    gm = P.temporal_pool(st, "geometric").cpu().numpy()
+    hm = P.temporal_pool(st, "harmonic").cpu().numpy()
+    assert gm[0] == 0.0 and np.isnan(gm[1]) and abs(gm[2] - 0.5) <= 1e-7
+    assert hm[0] == 0.0 and abs(hm[2] - 0.5) <= 1e-7
+    med = P.temporal_pool(to_dev(np.array([[0.2, 0.9, 0.4]], np.float32), dev), "median").cpu().numpy()
+    assert med[0] == np.float32(0.4)
+    one = P.temporal_pool(to_dev(np.array([0.75], np.float32), dev), "w_gm", p=1).cpu().numpy()
+    assert abs(one[0] - 0.75) <= 1e-7
+    with pytest.raises(Exception):
+        P.temporal_pool(st, "w_am", p=5)  # window longer than the series
