@@ -276,12 +276,18 @@ struct VolGeom {
   int Wo, Ho, n_out, tiles_x, tiles_y, seg_len, nsegs;
 };
 
+// Internal plane kind of the second MS-SSIM-3D scale of 8-bit clips: uint16
+// sums of 2x2 blocks (four times the 2x2 mean), accumulated in uint32.
+constexpr int kVolU16Sum = 100;
+
+bool vol_int_acc(int dtype) { return dtype == SSIMX_U8 || dtype == kVolU16Sum; }
+
 VolGeom vol_geom(int W, int H, int frames, int k, int kt, int dtype) {
   VolGeom g{};
   g.Wo = W - k + 1;
   g.Ho = H - k + 1;
   g.n_out = frames - kt + 1;
-  const int OH = dtype == SSIMX_U8 ? vol_oh<uint32_t>() : vol_oh<double>();
+  const int OH = vol_int_acc(dtype) ? vol_oh<uint32_t>() : vol_oh<double>();
   g.tiles_x = (g.Wo + kVolOW - 1) / kVolOW;
   g.tiles_y = (g.Ho + OH - 1) / OH;
   // Split the frames into runs so that the grid holds about 4096 workgroups,
@@ -305,9 +311,11 @@ ssimx_status check_vol(const ssimx_params* p, int kt) {
   return SSIMX_OK;
 }
 
-ssimx_status vol_pass(const ssimx_params* p, int kt, int dtype, PlaneArg x, PlaneArg y, int W, int H, int frames,
-                      int mode, float* map, int64_t map_pitch, int64_t map_fstride, float* out, int64_t out_stride,
-                      float* partial, hipStream_t st) {
+// cscale multiplies C1 and C2: planes holding s times the pixel values give
+// the same SSIM with the constants scaled by s^2.
+ssimx_status vol_pass(const ssimx_params* p, int kt, int dtype, double cscale, PlaneArg x, PlaneArg y, int W, int H,
+                      int frames, int mode, float* map, int64_t map_pitch, int64_t map_fstride, float* out,
+                      int64_t out_stride, float* partial, hipStream_t st) {
   const VolGeom g = vol_geom(W, H, frames, p->k, kt, dtype);
   VolArgs a{};
   a.x = x;
@@ -324,8 +332,8 @@ ssimx_status vol_pass(const ssimx_params* p, int kt, int dtype, PlaneArg x, Plan
   a.seg_len = g.seg_len;
   a.N = (double)p->k * p->k * kt;
   a.invN2 = (float)(1.0 / (a.N * a.N));
-  a.C1 = (float)p->C1;
-  a.C2 = (float)p->C2;
+  a.C1 = (float)(p->C1 * cscale);
+  a.C2 = (float)(p->C2 * cscale);
   a.mode = mode;
   a.map = map;
   a.map_pitch = map_pitch;
@@ -337,6 +345,7 @@ ssimx_status vol_pass(const ssimx_params* p, int kt, int dtype, PlaneArg x, Plan
     case SSIMX_U16: err = launch_vol_t<uint16_t, double>(a, g.nsegs, st); break;
     case SSIMX_F32: err = launch_vol_t<float, double>(a, g.nsegs, st); break;
     case SSIMX_BF16: err = launch_vol_t<bf16_t, double>(a, g.nsegs, st); break;
+    case kVolU16Sum: err = launch_vol_t<uint16_t, uint32_t>(a, g.nsegs, st); break;
     default: return SSIMX_EDTYPE;
   }
   if (err) return hip_status(err);
@@ -367,23 +376,47 @@ ssimx_status check_vol_images(const ssimx_params* p, int kt, const ssimx_image* 
   return SSIMX_OK;
 }
 
+// 2x2 block sums of 8-bit planes as uint16 (exact): four times the 2x2 mean.
+__global__ __launch_bounds__(BLOCK) void sum4_kernel(PlaneArg xa, PlaneArg ya, int W2, int H2, uint16_t* ox,
+                                                     uint16_t* oy) {
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= W2 * H2) return;
+  const int frame = blockIdx.y;
+  const int r = idx / W2, c = idx - r * W2;
+  const uint8_t* px = (const uint8_t*)xa.data + (int64_t)frame * xa.bstride + (int64_t)(2 * r) * xa.pitch + 2 * c;
+  const uint8_t* py = (const uint8_t*)ya.data + (int64_t)frame * ya.bstride + (int64_t)(2 * r) * ya.pitch + 2 * c;
+  const int64_t o = (int64_t)frame * W2 * H2 + idx;
+  ox[o] = (uint16_t)(px[0] + px[1] + px[xa.pitch] + px[xa.pitch + 1]);
+  oy[o] = (uint16_t)(py[0] + py[1] + py[ya.pitch] + py[ya.pitch + 1]);
+}
+
 struct Ms3Layout {
   int W[MAX_SCALES], H[MAX_SCALES];
+  int dt[MAX_SCALES];         // plane kind of each scale
+  double cscale[MAX_SCALES];  // C1, C2 multiplier of each scale
   size_t lvl_x[MAX_SCALES], lvl_y[MAX_SCALES];
   size_t partial, vals, total;
 };
 
+// For 8-bit clips the second scale is kept as exact uint16 2x2 sums (4x the
+// means) and accumulated in uint32 while k^2 kt 1020^2 < 2^32; the coarser
+// scales are float 2x2 means of it (still 4x the pixel values), so their
+// constants are scaled by 16.  Everything else uses float 2x2 means.
 Ms3Layout ms3_layout(const ssimx_params* p, int kt, int dtype, int W, int H, int frames, int M) {
   Ms3Layout L{};
   scale_dims(W, H, M, L.W, L.H);
+  const bool sum16 = dtype == SSIMX_U8 && M > 1 && (double)p->k * p->k * kt * 1020.0 * 1020.0 < 4294967296.0;
   Ws ws;
   size_t np = 0;
   for (int j = 0; j < M; ++j) {
+    L.dt[j] = j == 0 ? dtype : (j == 1 && sum16) ? kVolU16Sum : SSIMX_F32;
+    L.cscale[j] = (sum16 && j > 0) ? 16.0 : 1.0;
     if (j > 0) {
-      L.lvl_x[j] = ws.take(sizeof(float) * (size_t)frames * L.W[j] * L.H[j]);
-      L.lvl_y[j] = ws.take(sizeof(float) * (size_t)frames * L.W[j] * L.H[j]);
+      const size_t es = L.dt[j] == kVolU16Sum ? sizeof(uint16_t) : sizeof(float);
+      L.lvl_x[j] = ws.take(es * (size_t)frames * L.W[j] * L.H[j]);
+      L.lvl_y[j] = ws.take(es * (size_t)frames * L.W[j] * L.H[j]);
     }
-    np = std::max(np, vol_partial_floats(L.W[j], L.H[j], frames, p->k, kt, j == 0 ? dtype : SSIMX_F32));
+    np = std::max(np, vol_partial_floats(L.W[j], L.H[j], frames, p->k, kt, L.dt[j]));
   }
   L.partial = ws.take(sizeof(float) * np);
   L.vals = ws.take(sizeof(float) * (size_t)(frames - kt + 1) * M);
@@ -422,7 +455,7 @@ ssimx_status ssimx_ssim3d(const ssimx_params* p, int kt, const ssimx_image* ref,
   const size_t need = vol_ws_bytes(ref->width, ref->height, frames, p->k, kt, ref->dtype);
   if (!ws || ws_bytes < need) return SSIMX_EWORKSPACE;
   PlaneArg x{ref->data, ref->pitch, ref->batch_stride}, y{dis->data, dis->pitch, dis->batch_stride};
-  return vol_pass(p, kt, ref->dtype, x, y, ref->width, ref->height, frames, 0, map_out, map_pitch, map_frame_stride,
+  return vol_pass(p, kt, ref->dtype, 1.0, x, y, ref->width, ref->height, frames, 0, map_out, map_pitch, map_frame_stride,
                   score_out, 1, (float*)ws, (hipStream_t)stream);
 }
 
@@ -457,23 +490,29 @@ ssimx_status ssimx_msssim3d(const ssimx_params* p, int kt, const float* weights,
   float* vals = (float*)(base + L.vals);
   for (int j = 0; j < n_scales; ++j) {
     PlaneArg x, y;
-    int dt;
+    const int dt = L.dt[j];
     if (j == 0) {
       x = PlaneArg{ref->data, ref->pitch, ref->batch_stride};
       y = PlaneArg{dis->data, dis->pitch, dis->batch_stride};
-      dt = ref->dtype;
     } else {
       x = PlaneArg{base + L.lvl_x[j], L.W[j], (int64_t)L.W[j] * L.H[j]};
       y = PlaneArg{base + L.lvl_y[j], L.W[j], (int64_t)L.W[j] * L.H[j]};
-      dt = SSIMX_F32;
     }
     if (j + 1 < n_scales) {
-      const int err = launch_downsample(dt, x, L.W[j], L.H[j], (float*)(base + L.lvl_x[j + 1]),
-                                        (float*)(base + L.lvl_y[j + 1]), y, frames, st);
+      int err;
+      if (L.dt[j + 1] == kVolU16Sum) {
+        const int W2 = L.W[j + 1], H2 = L.H[j + 1];
+        hipLaunchKernelGGL(sum4_kernel, dim3((W2 * H2 + BLOCK - 1) / BLOCK, frames), dim3(BLOCK), 0, st, x, y, W2,
+                           H2, (uint16_t*)(base + L.lvl_x[j + 1]), (uint16_t*)(base + L.lvl_y[j + 1]));
+        err = (int)hipGetLastError();
+      } else {
+        err = launch_downsample(dt == kVolU16Sum ? SSIMX_U16 : dt, x, L.W[j], L.H[j],
+                                (float*)(base + L.lvl_x[j + 1]), (float*)(base + L.lvl_y[j + 1]), y, frames, st);
+      }
       if (err) return hip_status(err);
     }
-    s = vol_pass(p, kt, dt, x, y, L.W[j], L.H[j], frames, j + 1 < n_scales ? 1 : 0, nullptr, 0, 0, vals + j,
-                 n_scales, (float*)(base + L.partial), st);
+    s = vol_pass(p, kt, dt, L.cscale[j], x, y, L.W[j], L.H[j], frames, j + 1 < n_scales ? 1 : 0, nullptr, 0, 0,
+                 vals + j, n_scales, (float*)(base + L.partial), st);
     if (s != SSIMX_OK) return s;
   }
   const int err = launch_ms_combine(vals, n_scales, frames - kt + 1, w, flags, score_out, cs_out, st);

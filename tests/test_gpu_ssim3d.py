@@ -155,3 +155,18 @@ def test_ssim3d_1080p_clip_sampled(P, dev):
     for t in (0, to - 1):
         ref = O.ssim3d_map(x[t:t + kt], y[t:t + kt], p, kt)["map"][0]
         assert np.abs(m[t] - ref).max() <= MAP_TOL
+
+
+@pytest.mark.parametrize("kt,T,dtype", [(36, 38, "u8"), (3, 7, "u16")])
+def test_msssim3d_float_pyramid_cases(P, dev, kt, T, dtype):
+    """MS-SSIM-3D where the second scale is not kept as exact 8-bit block sums:
+    kt too long for uint32 sums of 2x2 sums, and 10-bit clips."""
+    x, y = synth.video_clip(T, 64, 80, stream=9)
+    cfg = _box(P, 11)
+    if dtype == "u16":
+        x, y = x.astype(np.uint16) * 4 + 1, y.astype(np.uint16) * 4
+        cfg = _box(P, 11, 1023.0)
+    s, cs = P.ms_ssim3d(to_dev(x, dev), to_dev(y, dev), kt, cfg, n_scales=2, renorm=True, return_cs=True)
+    r = O.msssim3d(x, y, oparams(cfg), kt, P.MS_WEIGHTS, 2, renorm=True)
+    np.testing.assert_allclose(s.cpu().numpy(), r["score"], rtol=0, atol=SCORE_TOL)
+    np.testing.assert_allclose(cs.cpu().numpy()[:, 0], r["cs"][:, 0], rtol=0, atol=SCORE_TOL)
