@@ -142,3 +142,16 @@ def test_temporal_pooling_edge_values(P, dev):
     assert abs(one[0] - 0.75) <= 1e-7
     with pytest.raises(Exception):
         P.temporal_pool(st, "w_am", p=5)  # window longer than the series
+
+
+def test_temporal_pooling_long_series(P, dev):
+    """Series longer than a block: every thread walks several windows."""
+    s = _score_series(2, 20000, 62)
+    st = to_dev(s, dev)
+    for kind, kw, ref in [("w_gm", {"p": 50}, lambda v: O.pool_windowed(v, 50, "gm")),
+                          ("w_cov", {"p": 3}, lambda v: O.pool_windowed(v, 3, "cov")),
+                          ("median", {}, O.pool_median), ("harmonic", {}, O.pool_harmonic)]:
+        got = P.temporal_pool(st, kind, **kw).cpu().numpy()
+        for b in range(2):
+            want = ref(s[b].astype(np.float64))
+            assert abs(got[b] - want) <= _tol(want), (kind, b, got[b], want)

@@ -170,3 +170,28 @@ def test_msssim3d_float_pyramid_cases(P, dev, kt, T, dtype):
     r = O.msssim3d(x, y, oparams(cfg), kt, P.MS_WEIGHTS, 2, renorm=True)
     np.testing.assert_allclose(s.cpu().numpy(), r["score"], rtol=0, atol=SCORE_TOL)
     np.testing.assert_allclose(cs.cpu().numpy()[:, 0], r["cs"][:, 0], rtol=0, atol=SCORE_TOL)
+
+
+@pytest.mark.parametrize("T,H,W,k,kt", [(5, 11, 11, 11, 5), (64, 24, 70, 3, 64), (3, 40, 64, 11, 1),
+                                        (70, 30, 300, 11, 2)])
+def test_ssim3d_edge_shapes(P, dev, T, H, W, k, kt):
+    """One-position maps, a single map frame, kt at its limit, many frame runs."""
+    x, y = synth.video_clip(T, H, W, stream=10 + T)
+    cfg = _box(P, k)
+    s, m = P.ssim3d(to_dev(x, dev), to_dev(y, dev), kt, cfg, return_map=True)
+    r = O.ssim3d_map(x, y, oparams(cfg), kt)
+    assert np.abs(m.cpu().numpy() - r["map"]).max() <= MAP_TOL
+    np.testing.assert_allclose(s.cpu().numpy(), [O.mean_pool(r["map"][t]) for t in range(m.shape[0])], rtol=0,
+                               atol=SCORE_TOL)
+
+
+def test_msssim3d_bf16_clip(P, dev):
+    x, y = synth.video_clip(6, 100, 120, stream=12)
+    xa = bf16_round(x.astype(np.float32) / 255)
+    ya = bf16_round(y.astype(np.float32) / 255)
+    cfg = _box(P, 11, 1.0)
+    xt = torch.from_numpy(xa).to(dev).to(torch.bfloat16)
+    yt = torch.from_numpy(ya).to(dev).to(torch.bfloat16)
+    s = P.ms_ssim3d(xt, yt, 3, cfg, n_scales=3, renorm=True).cpu().numpy()
+    r = O.msssim3d(xa, ya, oparams(cfg), 3, P.MS_WEIGHTS, 3, renorm=True)
+    np.testing.assert_allclose(s, r["score"], rtol=0, atol=SCORE_TOL)
