@@ -15,7 +15,8 @@ using namespace fast;
 // planes arrive (A = A_u - A_v, B_u, B_v), each with a row pitch that is a
 // multiple of 4; the footprint origin is aligned to 4 map columns so that an
 // interior footprint quad is one aligned 16-byte load per plane.  The next
-// chunk's quads are fetched into registers before the column pass.
+// chunk's quads are fetched into registers as soon as the current chunk is
+// staged, so the loads overlap both passes.
 namespace {
 
 constexpr int kNM = 3;  // coefficient planes
@@ -211,13 +212,15 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
       XY[0][threadIdx.x * fast::Quad<T>::NW + w] = px4.w[w];
       XY[1][threadIdx.x * fast::Quad<T>::NW + w] = py4.w[w];
     }
-    __syncthreads();
-    coef_row_pass<K>(taps, C, S::CH, HM, S::HALO);
-    __syncthreads();
+    // the next chunk's quads are loaded while this chunk's row and column
+    // passes run (the registers were just staged)
     if (cy + S::CH < qy_end) {
       fetch_coef<K>(a, frame, cy + S::CH, c0, S::CH, q);
       fetch_xy<T>(a, X, Y, cy + S::CH, qx0, px4, py4);
     }
+    __syncthreads();
+    coef_row_pass<K>(taps, C, S::CH, HM, S::HALO);
+    __syncthreads();
     for (int it = threadIdx.x; it < (S::CH / 4) * kTW; it += kNT) {
       const int gr = it / kTW, c = it - gr * kTW;
       const int px = qx0 + c;

@@ -316,11 +316,12 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
   for (int cy = oy0; cy < oy_end; cy += kCH) {
     __syncthreads();  // U, V free; band rows [0, HALO) ready
     store_chunk<K, T>(qx, qy, U, V);
+    // the next chunk's pixels are loaded while this chunk's row and column
+    // passes run (the registers were just staged)
+    if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
     __syncthreads();
     row_pass<K>(taps, U, V, kCH, HM, S::HALO);
     __syncthreads();
-    // the next chunk's pixels are loaded while this chunk's column pass runs
-    if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
     // column pass: item = (4 output rows, 1 column)
     for (int it = threadIdx.x; it < (kCH / 4) * kTW; it += kNT) {
       const int gr = it / kTW, c = it - gr * kTW;
