@@ -358,7 +358,8 @@ def _ms_weights(weights, n_scales: int, renorm: bool) -> np.ndarray:
 
 
 def msssim(x, y, p: SSIMParams | None = None, weights=MS_WEIGHTS, n_scales: int = 5,
-           renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product") -> dict:
+           renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product",
+           coarse_separate: bool = False) -> dict:
     """Multi-scale SSIM: cs at every scale, luminance at the coarsest only,
     combined as an exponentially weighted product (Introduction; the
     'Product' aggregation of the Versions of SSIM section).
@@ -368,6 +369,10 @@ def msssim(x, y, p: SSIMParams | None = None, weights=MS_WEIGHTS, n_scales: int 
     terms (CS_j for j < M, S_M at the coarsest scale) in a weighted average
     whose weights are the exponents normalised to sum to one (always, so
     `renorm` has no effect; `cs_clamp` has none either, as no power is taken).
+
+    The paper describes the coarsest term without printing it; by default it
+    is the mean of l*cs there.  coarse_separate=True takes the other reading,
+    mean(l) * mean(cs) at the coarsest scale.
 
     Returns {'score', 'cs' (list of CS_j, j < M), 's_M', 'weights'}.
     """
@@ -383,6 +388,8 @@ def msssim(x, y, p: SSIMParams | None = None, weights=MS_WEIGHTS, n_scales: int 
         r = ssim_map(xs[j], ys[j], p)
         if j < n_scales - 1:
             cs_vals.append(mean_pool(r["cs"]))
+        elif coarse_separate:
+            s_m = mean_pool(r["l"]) * mean_pool(r["cs"])
         else:
             s_m = mean_pool(r["map"])
     score = _ms_combine(cs_vals, s_m, w, cs_clamp, aggregation)
@@ -463,6 +470,10 @@ def ssim_map_backward(x, y, grad_map: np.ndarray, p: SSIMParams | None = None,
         a = g * (2 * mu_y * cs - 2 * mu_x) / b2
         b = g * 2 / b2
         c = -g * cs / b2
+    elif term == "l":
+        a = g * (2 * mu_x - 2 * mu_y * l) / b1
+        b = np.zeros_like(a)
+        c = np.zeros_like(a)
     else:
         raise ValueError(term)
     ho, wo = q.shape
@@ -498,12 +509,13 @@ def _downsample_adjoint(gc: np.ndarray, fine_shape) -> np.ndarray:
 
 def msssim_backward(x, y, grad_score: float = 1.0, p: SSIMParams | None = None,
                     weights=MS_WEIGHTS, n_scales: int = 5, renorm: bool = False,
-                    cs_clamp: bool = False, aggregation: str = "product") -> np.ndarray:
+                    cs_clamp: bool = False, aggregation: str = "product",
+                    coarse_separate: bool = False) -> np.ndarray:
     """dL/dy for L = grad_score * MS-SSIM(x, y), by the chain rule through the
     weighted product (or, for the 'Sum' aggregation, the weighted average) and
     the 2x2 pyramid, coarse to fine."""
     p = p or SSIMParams()
-    fwd = msssim(x, y, p, weights, n_scales, renorm, cs_clamp, aggregation)
+    fwd = msssim(x, y, p, weights, n_scales, renorm, cs_clamp, aggregation, coarse_separate)
     w = fwd["weights"]
     ms = fwd["score"]
     xs = pyramid(_as_f64(x), n_scales)
@@ -521,8 +533,15 @@ def msssim_backward(x, y, grad_score: float = 1.0, p: SSIMParams | None = None,
             dval = 0.0
         else:
             dval = grad_score * ms * w[j] / val
-        gm = np.full((ho, wo), dval / (ho * wo))
-        gj = ssim_map_backward(xs[j], ys[j], gm, p, term)
+        if j == n_scales - 1 and coarse_separate:
+            # S_M = mean(l) mean(cs): dS_M = mean(cs) dmean(l) + mean(l) dmean(cs)
+            r = ssim_map(xs[j], ys[j], p)
+            lm, cm = mean_pool(r["l"]), mean_pool(r["cs"])
+            gj = (ssim_map_backward(xs[j], ys[j], np.full((ho, wo), dval * cm / (ho * wo)), p, "l")
+                  + ssim_map_backward(xs[j], ys[j], np.full((ho, wo), dval * lm / (ho * wo)), p, "cs"))
+        else:
+            gm = np.full((ho, wo), dval / (ho * wo))
+            gj = ssim_map_backward(xs[j], ys[j], gm, p, term)
         if g_next is not None:
             gj = gj + _downsample_adjoint(g_next, xs[j].shape)
         g_next = gj
@@ -813,7 +832,8 @@ def ssim3d(x, y, p: SSIMParams | None = None, kt: int = 1) -> np.ndarray:
 
 
 def msssim3d(x, y, p: SSIMParams | None = None, kt: int = 1, weights=MS_WEIGHTS, n_scales: int = 5,
-             renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product") -> dict:
+             renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product",
+             coarse_separate: bool = False) -> dict:
     """MS-SSIM-3D per map frame: every frame of both clips is reduced by the
     2x2 pyramid of MS-SSIM; at each scale the SSIM-3D maps give CS_j(t) (mean
     cs, j < M) and S_M(t) (mean l*cs at the coarsest scale), combined per map
@@ -835,6 +855,8 @@ def msssim3d(x, y, p: SSIMParams | None = None, kt: int = 1, weights=MS_WEIGHTS,
         for t in range(to):
             if j < n_scales - 1:
                 cs[t, j] = mean_pool(r["cs"][t])
+            elif coarse_separate:
+                s_m[t] = mean_pool(r["l"][t]) * mean_pool(r["cs"][t])
             else:
                 s_m[t] = mean_pool(r["map"][t])
     score = np.array([_ms_combine(list(cs[t]), s_m[t], w, cs_clamp, aggregation) for t in range(to)])

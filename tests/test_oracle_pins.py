@@ -332,6 +332,41 @@ def test_msssim_sum_gradient_matches_fd():
         assert abs(_fd(f, y, idx, 1e-5) - g[idx]) <= 1e-6 * abs(g).max(), idx
 
 
+def test_msssim_coarse_separate_reading():
+    """Coarsest term mean(l) * mean(cs) instead of mean(l * cs): the two differ
+    by exactly the population covariance of the l and cs maps."""
+    rng = np.random.default_rng(42)
+    x = synth.smooth_field(rng, 80, 90, 20, 230)
+    y = np.clip(0.7 * x + 40 + rng.normal(0, 10, x.shape), 0, 255)
+    p = O.SSIMParams()
+    r = O.ssim_map(x, y, p)
+    cov = np.cov(r["l"].ravel(), r["cs"].ravel(), bias=True)[0, 1]
+    assert abs(cov) > 1e-5
+    d = O.msssim(x, y, p, (1.0,), 1)["score"]
+    sep = O.msssim(x, y, p, (1.0,), 1, coarse_separate=True)["score"]
+    assert abs((d - sep) - cov) < 1e-13
+    # spatially constant luminance term: both readings agree
+    xc = np.full((60, 60), 70.0)
+    yc = np.full((60, 60), 90.0)
+    assert abs(O.msssim(xc, yc, p, n_scales=2, renorm=True)["score"]
+               - O.msssim(xc, yc, p, n_scales=2, renorm=True, coarse_separate=True)["score"]) < 1e-15
+    assert abs(O.msssim(x, x, p, n_scales=3, coarse_separate=True)["score"] - 1.0) < 1e-13
+
+
+def test_msssim_coarse_separate_gradient_matches_fd():
+    rng = np.random.default_rng(43)
+    x = synth.smooth_field(rng, 64, 70, 16 / 255, 235 / 255)
+    y = x + rng.normal(0, 0.05, x.shape)
+    C1, C2 = O.constants(0.01, 0.03, 1.0)
+    p = O.SSIMParams(C1=C1, C2=C2, k=7, sigma=1.0)
+    for agg in ("product", "sum"):
+        g = O.msssim_backward(x, y, 1.0, p, n_scales=3, renorm=True, aggregation=agg, coarse_separate=True)
+        f = lambda yy: O.msssim(x, yy, p, n_scales=3, renorm=True, aggregation=agg,  # noqa: E731
+                                coarse_separate=True)["score"]
+        for idx in [(0, 0), (31, 40), (63, 69), (10, 50)]:
+            assert abs(_fd(f, y, idx, 1e-5) - g[idx]) <= 1e-6 * abs(g).max(), (agg, idx)
+
+
 # ---------------------------------------------------------------- adjoint
 def _fd(f, y, idx, h=1e-3):
     yp = y.copy()
