@@ -110,6 +110,11 @@ typedef struct {
                                (implies RENORM; CS_CLAMP has no effect).
                                Other flag bits: EINVAL.  RENORM or SUM with
                                weights summing to zero: EINVAL. */
+#define SSIMX_MS_COARSE_SEPARATE 8 /* coarsest term mean(l) * mean(cs) instead of
+                               the default mean(l * cs) (the paper describes the
+                               combination without printing it; both readings
+                               are offered).  Supported by msssim,
+                               msssim_backward and ssimx_msssim3d. */
 
 /* Operation selector for ssimx_workspace_size(). */
 typedef enum {
@@ -143,7 +148,8 @@ ssimx_status ssim_pooled(const ssimx_params* p, const ssimx_image* ref, const ss
  * score_out: float32 [batch] = S_M^{w_M} prod_{j<M} CS_j^{w_j} (with
  * SSIMX_MS_SUM: w_M S_M + sum_{j<M} w_j CS_j, weights normalised).
  * cs_out (nullable): float32 [batch][n_scales]; entries 0..M-2 hold CS_j (mean
- * cs map), entry M-1 holds S_M (mean l*cs at the coarsest scale).
+ * cs map), entry M-1 holds S_M (mean l*cs at the coarsest scale, or
+ * mean(l) * mean(cs) with SSIMX_MS_COARSE_SEPARATE).
  * Every scale must hold at least one window (else ETOOSMALL). */
 ssimx_status msssim(const ssimx_params* p, const float* weights, int n_scales, int flags,
                     const ssimx_image* ref, const ssimx_image* dis, int batch,

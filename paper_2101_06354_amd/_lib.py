@@ -21,7 +21,7 @@ U8, U16, F32, BF16 = 0, 1, 2, 3
 WIN_GAUSSIAN, WIN_BOX = 0, 1
 ALGO_AUTO, ALGO_SEPARABLE, ALGO_INTEGRAL_IMAGE = 0, 1, 2
 PAD_VALID, PAD_ZERO, PAD_REFLECT = 0, 1, 2
-MS_RENORM, MS_CS_CLAMP, MS_SUM = 1, 2, 4
+MS_RENORM, MS_CS_CLAMP, MS_SUM, MS_COARSE_SEPARATE = 1, 2, 4, 8
 OP_MAP, OP_POOLED, OP_MSSSIM, OP_MAP_BACKWARD, OP_POOLED_BACKWARD, OP_MSSSIM_BACKWARD = range(6)
 
 

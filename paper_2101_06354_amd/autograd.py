@@ -25,21 +25,22 @@ class SSIMFunction(torch.autograd.Function):
 
 class MSSSIMFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x, y, cfg, weights, n_scales, renorm, cs_clamp, aggregation):
+    def forward(ctx, x, y, cfg, weights, n_scales, renorm, cs_clamp, aggregation, coarse_separate):
         ctx.save_for_backward(x, y)
-        ctx.args = (cfg, tuple(weights), n_scales, renorm, cs_clamp, aggregation)
+        ctx.args = (cfg, tuple(weights), n_scales, renorm, cs_clamp, aggregation, coarse_separate)
         return ops.ms_ssim(x, y, cfg, weights=weights, n_scales=n_scales, renorm=renorm, cs_clamp=cs_clamp,
-                           aggregation=aggregation)
+                           aggregation=aggregation, coarse_separate=coarse_separate)
 
     @staticmethod
     def backward(ctx, g):
         x, y = ctx.saved_tensors
-        cfg, weights, n_scales, renorm, cs_clamp, aggregation = ctx.args
+        cfg, weights, n_scales, renorm, cs_clamp, aggregation, coarse_separate = ctx.args
         gy = None
         if ctx.needs_input_grad[1]:
             gy = ops.ms_ssim_backward(x, y, g, cfg, weights=weights, n_scales=n_scales, renorm=renorm,
-                                      cs_clamp=cs_clamp, aggregation=aggregation).to(y.dtype)
-        return None, gy, None, None, None, None, None, None
+                                      cs_clamp=cs_clamp, aggregation=aggregation,
+                                      coarse_separate=coarse_separate).to(y.dtype)
+        return None, gy, None, None, None, None, None, None, None
 
 
 class LumaFunction(torch.autograd.Function):
@@ -59,10 +60,12 @@ def ssim(x, y, cfg: ops.SSIMConfig | None = None, **kw):
 
 
 def ms_ssim(x, y, cfg: ops.SSIMConfig | None = None, weights=ops.MS_WEIGHTS, n_scales: int = 5,
-            renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product", **kw):
+            renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product", coarse_separate: bool = False,
+            **kw):
     """Differentiable MS-SSIM per frame, float32 [B] (weighted product, or
     aggregation="sum" for the weighted average)."""
-    return MSSSIMFunction.apply(x, y, ops._cfg(cfg, kw), tuple(weights), n_scales, renorm, cs_clamp, aggregation)
+    return MSSSIMFunction.apply(x, y, ops._cfg(cfg, kw), tuple(weights), n_scales, renorm, cs_clamp, aggregation,
+                                coarse_separate)
 
 
 def luma(rgb):

@@ -147,14 +147,16 @@ struct MsWeights {
 // j < M-1 and S_M at M-1.  powf of a negative base with a fractional exponent
 // is NaN, which propagates unless clamping is asked for.
 // Weighted product S_M^{w_M} prod CS_j^{w_j}, or (sum != 0) the weighted
-// average sum w_j T_j of the same terms with weights that sum to one.
+// average sum w_j T_j of the same terms with weights that sum to one.  lvals
+// (nullable): the coarsest term is vals * lvals (mean(l) * mean(cs)).
 __global__ void ms_combine_kernel(const float* vals, int n_scales, int batch, MsWeights w, int clamp, int sum,
-                                  float* score_out, float* cs_out) {
+                                  const float* lvals, float* score_out, float* cs_out) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= batch) return;
   float score = sum ? 0.f : 1.f;
   for (int j = 0; j < n_scales; ++j) {
     float v = vals[(int64_t)f * n_scales + j];
+    if (lvals && j == n_scales - 1) v *= lvals[f];
     if (cs_out) cs_out[(int64_t)f * n_scales + j] = v;
     if (sum) {
       score = fmaf(w.w[j], v, score);
@@ -167,11 +169,11 @@ __global__ void ms_combine_kernel(const float* vals, int n_scales, int batch, Ms
 }
 
 int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w, int flags, float* score_out,
-                      float* cs_out, hipStream_t st) {
+                      float* cs_out, const float* lvals, hipStream_t st) {
   MsWeights mw{};
   for (int j = 0; j < n_scales && j < MAX_SCALES; ++j) mw.w[j] = w[j];
   hipLaunchKernelGGL(ms_combine_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, vals, n_scales, batch, mw,
-                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, score_out, cs_out);
+                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, lvals, score_out, cs_out);
   return (int)hipGetLastError();
 }
 

@@ -35,11 +35,13 @@ struct CoefArgs {
   PlaneArg x, y;
   Geom g;
   float C1, C2;
-  int mode;  // 0: Q, 1: cs
+  int mode;  // 0: Q, 1: cs, 3: g_l l + g_cs cs with per-frame upstreams
   const float* grad_map;
   int64_t gm_pitch, gm_bstride;
-  const float* gscale;  // per-frame upstream scalars, gscale[frame * gscale_stride] * gmul
+  const float* gscale;  // per-frame upstream scalars, gscale[frame * gscale_stride] * gmul (of cs in mode 3)
   int gscale_stride;
+  const float* gscale2;  // mode 3: per-frame upstream of l
+  int gscale2_stride;
   float gmul;
   float tu, tv;
   float* coef;  // planes A = A_u - A_v, B_u, B_v, each [batch][Ho][cpitch]
@@ -57,6 +59,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_coef_kernel(CoefArgs a) {
   const int ox0 = txi * a.g.TW, oy0 = tyi * a.g.TH;
   sep_tile_rows<T>(a.g, a.taps, a.x, a.y, frame, ox0, oy0, lds);
   const float gframe = a.grad_map ? 0.f : a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul;
+  const float gl_frame = a.mode == 3 ? a.gscale2[(int64_t)frame * a.gscale2_stride] * a.gmul : 0.f;
   for (int idx = threadIdx.x; idx < a.g.TH * a.g.TW; idx += BLOCK) {
     const int i = idx / a.g.TW, j = idx - i * a.g.TW;
     const int oi = oy0 + i, oj = ox0 + j;
@@ -67,23 +70,29 @@ __global__ __launch_bounds__(BLOCK) void bwd_coef_kernel(CoefArgs a) {
     const float ib2 = 1.f / t.B2;
     const float dcs_du = 0.5f * st.var_v * ib2 * ib2;        // d cs / d var_u
     const float dcs_dv = -0.5f * (t.A2 + t.B2) * ib2 * ib2;  // d cs / d var_v
-    float au = 0.f, av = 0.f, bu, bv;
-    if (a.mode == 0) {
-      const float ib1 = 1.f / t.B1;
-      const float l = t.A1 * ib1, cs = t.A2 * ib2;
-      au = cs * st.mean_u * (st.mean_v * st.mean_v) * ib1 * ib1;  // cs * d l / d mean_u
-      av = -cs * st.mean_v * (t.A1 + t.B1) * ib1 * ib1;           // cs * d l / d mean_v
-      bu = l * dcs_du;
-      bv = l * dcs_dv;
-    } else {
+    float au = 0.f, av = 0.f, bu, bv, gg = g;
+    if (a.mode == 1) {
       bu = dcs_du;
       bv = dcs_dv;
+    } else {
+      // d(fl l + fc cs): Q = l cs takes fl = cs, fc = l; mode 3 the two upstreams
+      const float ib1 = 1.f / t.B1;
+      float fl = t.A2 * ib2, fc = t.A1 * ib1;
+      if (a.mode == 3) {
+        fl = gl_frame;
+        fc = g;
+        gg = 1.f;
+      }
+      au = fl * st.mean_u * (st.mean_v * st.mean_v) * ib1 * ib1;  // fl * d l / d mean_u
+      av = -fl * st.mean_v * (t.A1 + t.B1) * ib1 * ib1;           // fl * d l / d mean_v
+      bu = fc * dcs_du;
+      bv = fc * dcs_dv;
     }
     const int64_t o = ((int64_t)frame * a.g.Ho + oi) * a.cpitch + oj;
     const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
-    a.coef[o] = g * ((au - 2.f * bu * (st.mean_u - a.tu)) - (av - 2.f * bv * (st.mean_v - a.tv)));
-    a.coef[qs + o] = 2.f * g * bu;
-    a.coef[2 * qs + o] = 2.f * g * bv;
+    a.coef[o] = gg * ((au - 2.f * bu * (st.mean_u - a.tu)) - (av - 2.f * bv * (st.mean_v - a.tv)));
+    a.coef[qs + o] = 2.f * gg * bu;
+    a.coef[2 * qs + o] = 2.f * gg * bv;
   }
 }
 
@@ -227,16 +236,25 @@ struct UpArgs {
 
 // dL/dT for the pooled term of each scale: grad * MS * w_j / val_j / N_j for
 // the weighted product (zero where a clamped value is not positive), grad *
-// w_j / N_j for the weighted average.
+// w_j / N_j for the weighted average.  With lv (the coarsest term read as
+// mean(l) * mean(cs), lv = mean(l)), the coarsest upstream is split: up holds
+// that of mean(cs) (dS * mean(l)) and up2 that of mean(l) (dS * mean(cs)).
 __global__ void ms_upstream_kernel(const float* vals, const float* ms, const float* gscore, UpArgs u, int M,
-                                   int clamp, int sum, int batch, float* up) {
+                                   int clamp, int sum, int batch, const float* lv, float* up, float* up2) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= batch) return;
   for (int j = 0; j < M; ++j) {
-    const float v = vals[(int64_t)f * M + j];
+    const float c = vals[(int64_t)f * M + j];
+    const bool split = lv && j == M - 1;
+    const float v = split ? c * lv[f] : c;
     float r = sum ? gscore[f] * u.w[j] * u.inv_count[j] : gscore[f] * ms[f] * u.w[j] / v * u.inv_count[j];
     if (!sum && clamp && !(v > 0.f)) r = 0.f;
-    up[(int64_t)f * M + j] = r;
+    if (split) {
+      up[(int64_t)f * M + j] = r * lv[f];
+      up2[f] = r * c;
+    } else {
+      up[(int64_t)f * M + j] = r;
+    }
   }
 }
 
@@ -274,7 +292,7 @@ struct BwdLevel {
 // Coefficients + transposed filter (+ fold) for one scale.
 static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int batch, int mode, const float* grad_map,
                               int64_t gm_pitch, int64_t gm_bstride, const float* gscale, int gscale_stride,
-                              float gmul, float* coef, float* gpad, float* out, int64_t out_pitch,
+                              const float* gscale2, float gmul, float* coef, float* gpad, float* out, int64_t out_pitch,
                               int64_t out_bstride, const float* coarse, int Wc, int Hc, hipStream_t st) {
   ssimx_params pf = *p;
   pf.algo = SSIMX_ALGO_SEPARABLE;
@@ -294,6 +312,8 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     fa.gm_bstride = gm_bstride;
     fa.gscale = gscale;
     fa.gscale_stride = gscale_stride;
+    fa.gscale2 = gscale2;
+    fa.gscale2_stride = 1;
     fa.gmul = gmul;
     fa.tu = tu;
     fa.tv = tv;
@@ -315,6 +335,8 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     ca.gm_bstride = gm_bstride;
     ca.gscale = gscale;
     ca.gscale_stride = gscale_stride;
+    ca.gscale2 = gscale2;
+    ca.gscale2_stride = 1;
     ca.gmul = gmul;
     ca.tu = tu;
     ca.tv = tv;
@@ -425,7 +447,7 @@ static SsimBwdLayout ssim_bwd_layout(const ssimx_params* p, int W, int H, int ba
 
 struct MsBwdLayout {
   MsLayout fwd;
-  size_t msval, up, coef, gpad, glev[MAX_SCALES], total;
+  size_t msval, up, up2, coef, gpad, glev[MAX_SCALES], total;
 };
 
 static MsBwdLayout ms_bwd_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int M) {
@@ -435,6 +457,7 @@ static MsBwdLayout ms_bwd_layout(const ssimx_params* p, int dtype, int W, int H,
   ws.used = L.fwd.total;
   L.msval = ws.take(sizeof(float) * batch);
   L.up = ws.take(sizeof(float) * batch * M);
+  L.up2 = ws.take(sizeof(float) * batch);
   int Wo, Ho;
   map_dims(p, W, H, Wo, Ho);
   L.coef = ws.take(sizeof(float) * 3 * (size_t)batch * ((Wo + 3) & ~3) * Ho);
@@ -465,7 +488,8 @@ static ssimx_status ssim_bwd_entry(const ssimx_params* p, const ssimx_image* ref
   BwdLevel lv{ref->dtype, PlaneArg{ref->data, ref->pitch, ref->batch_stride},
               PlaneArg{dis->data, dis->pitch, dis->batch_stride}, ref->width, ref->height};
   char* base = (char*)ws;
-  return bwd_level(p, lv, batch, 0, grad_map, gm_pitch, gm_bstride, grad_score, 1, 1.f / ((float)Wo * (float)Ho),
+  return bwd_level(p, lv, batch, 0, grad_map, gm_pitch, gm_bstride, grad_score, 1, nullptr,
+                   1.f / ((float)Wo * (float)Ho),
                    (float*)(base + L.coef), (float*)(base + L.gpad), grad, gp, gb, nullptr, 0, 0, st);
 }
 
@@ -518,9 +542,12 @@ ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_
     u.inv_count[j] = (float)(1.0 / ((double)Wo * Ho));
   }
   float* up = (float*)(base + L.up);
+  float* up2 = (float*)(base + L.up2);
+  const bool sep = (flags & SSIMX_MS_COARSE_SEPARATE) != 0;
   hipLaunchKernelGGL(ms_upstream_kernel, dim3((batch + 63) / 64), dim3(64), 0, st,
                      (const float*)(base + L.fwd.vals_off), (const float*)(base + L.msval), grad_score, u, n_scales,
-                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, batch, up);
+                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, batch,
+                     sep ? (const float*)(base + L.fwd.lvals_off) : nullptr, up, up2);
   int err = (int)hipGetLastError();
   if (err) return hip_status(err);
   for (int j = n_scales - 1; j >= 0; --j) {
@@ -543,8 +570,9 @@ ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_
     }
     const float* coarse = j + 1 < n_scales ? (const float*)(base + L.glev[j + 1]) : nullptr;
     const int Wc = j + 1 < n_scales ? L.fwd.W[j + 1] : 0, Hc = j + 1 < n_scales ? L.fwd.H[j + 1] : 0;
-    const int mode = j == n_scales - 1 ? 0 : 1;
-    s = bwd_level(p, lv, batch, mode, nullptr, 0, 0, up + j, n_scales, 1.f, (float*)(base + L.coef),
+    const int mode = j == n_scales - 1 ? (sep ? 3 : 0) : 1;
+    s = bwd_level(p, lv, batch, mode, nullptr, 0, 0, up + j, n_scales, mode == 3 ? up2 : nullptr, 1.f,
+                  (float*)(base + L.coef),
                   (float*)(base + L.gpad), out, op, ob, coarse, Wc, Hc, st);
     if (s != SSIMX_OK) return s;
   }

@@ -9,7 +9,7 @@ struct FastArgs {
   PlaneArg x, y;
   Geom g;            // TW fixed at 64; TH = output rows per tile (multiple of 16)
   float C1, C2;
-  int mode;          // 0: Q = l*cs, 1: cs
+  int mode;          // 0: Q = l*cs, 1: cs, 3: l (forward) / g_l l + g_cs cs (coefficients)
   int vec_ok;        // 4-element vector loads allowed for interior footprint rows
   // forward epilogue
   float* map;
@@ -18,8 +18,10 @@ struct FastArgs {
   // coefficient epilogue
   const float* grad_map;
   int64_t gm_pitch, gm_bstride;
-  const float* gscale;
+  const float* gscale;   // per-frame upstream, gscale[frame * gscale_stride] * gmul (of cs in mode 3)
   int gscale_stride;
+  const float* gscale2;  // mode 3: per-frame upstream of l, gscale2[frame * gscale2_stride] * gmul
+  int gscale2_stride;
   float gmul;
   float tu, tv;
   float* coef;       // planes A = A_u - A_v, B_u, B_v, each [batch][Ho][cpitch]

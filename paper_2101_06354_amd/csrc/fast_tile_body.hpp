@@ -309,6 +309,7 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
   row_pass<K>(taps, U, V, S::HALO, HM, 0);
 
   const float gframe = (EPI == 1 && !a.grad_map) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
+  const float gl_frame = (EPI == 1 && a.mode == 3) ? a.gscale2[(int64_t)frame * a.gscale2_stride] * a.gmul : 0.f;
   float acc = 0.f;
   const int oy_end = __builtin_amdgcn_readfirstlane(min(a.g.Ho, oy0 + a.g.TH));
   Quad<T> qx[ChunkItems<K>::PER_THREAD], qy[ChunkItems<K>::PER_THREAD];
@@ -365,24 +366,30 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
           const float ib2 = __builtin_amdgcn_rcpf(t.B2);
           const float dcs_du = 0.5f * var_v * ib2 * ib2;
           const float dcs_dv = -0.5f * (t.A2 + t.B2) * ib2 * ib2;
-          float au = 0.f, av = 0.f, bu, bv;
-          if (a.mode == 0) {
-            const float ib1 = __builtin_amdgcn_rcpf(t.B1);
-            const float l = t.A1 * ib1, cs = t.A2 * ib2;
-            au = cs * mean_u * (mean_v * mean_v) * ib1 * ib1;
-            av = -cs * mean_v * (t.A1 + t.B1) * ib1 * ib1;
-            bu = l * dcs_du;
-            bv = l * dcs_dv;
-          } else {
+          float au = 0.f, av = 0.f, bu, bv, gg = g;
+          if (a.mode == 1) {
             bu = dcs_du;
             bv = dcs_dv;
+          } else {
+            // d(fl l + fc cs): Q = l cs takes fl = cs, fc = l; mode 3 the two upstreams
+            const float ib1 = __builtin_amdgcn_rcpf(t.B1);
+            float fl = t.A2 * ib2, fc = t.A1 * ib1;
+            if (a.mode == 3) {
+              fl = gl_frame;
+              fc = g;
+              gg = 1.f;
+            }
+            au = fl * mean_u * (mean_v * mean_v) * ib1 * ib1;
+            av = -fl * mean_v * (t.A1 + t.B1) * ib1 * ib1;
+            bu = fc * dcs_du;
+            bv = fc * dcs_dv;
           }
           // W^T is linear: the two A maps are combined before the transpose
           const int64_t o = ((int64_t)frame * a.g.Ho + oi) * a.cpitch + oj;
           const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
-          a.coef[o] = g * ((au - 2.f * bu * (mean_u - a.tu)) - (av - 2.f * bv * (mean_v - a.tv)));
-          a.coef[qs + o] = 2.f * g * bu;
-          a.coef[2 * qs + o] = 2.f * g * bv;
+          a.coef[o] = gg * ((au - 2.f * bu * (mean_u - a.tu)) - (av - 2.f * bv * (mean_v - a.tv)));
+          a.coef[qs + o] = 2.f * gg * bu;
+          a.coef[2 * qs + o] = 2.f * gg * bv;
         }
       }
     }

@@ -305,13 +305,14 @@ MsLayout ms_layout(const ssimx_params* p, int dtype, int W, int H, int batch, in
     }
   }
   L.vals_off = ws.take(sizeof(float) * (size_t)batch * n_scales);
+  L.lvals_off = ws.take(sizeof(float) * (size_t)batch);
   L.total = ws.used;
   return L;
 }
 
 ssimx_status check_ms(const ssimx_params* p, const float* weights, int n_scales, int flags, int W, int H) {
   if (!weights || n_scales < 1 || n_scales > MAX_SCALES) return SSIMX_EINVAL;
-  if (flags & ~(SSIMX_MS_RENORM | SSIMX_MS_CS_CLAMP | SSIMX_MS_SUM)) return SSIMX_EINVAL;
+  if (flags & ~(SSIMX_MS_RENORM | SSIMX_MS_CS_CLAMP | SSIMX_MS_SUM | SSIMX_MS_COARSE_SEPARATE)) return SSIMX_EINVAL;
   double sum = 0.0;
   for (int j = 0; j < n_scales; ++j) {
     if (!isfinite(weights[j])) return SSIMX_EINVAL;
@@ -480,14 +481,22 @@ ssimx_status ms_forward(const ssimx_params* p, const float* w, int n_scales, int
                                         (float*)(base + L.lvl_y_off[j + 1]), y, batch, st);
       if (err) return hip_status(err);
     }
-    const int mode = (j + 1 < n_scales) ? 1 : 0;
+    const bool sep = j + 1 == n_scales && (flags & SSIMX_MS_COARSE_SEPARATE);
+    const int mode = (j + 1 < n_scales || sep) ? 1 : 0;
     const int tile = pick_tile(p, dt, L.W[j], L.H[j], batch);
     ssimx_status s = fwd_pass(p, dt, x, y, L.W[j], L.H[j], batch, mode, nullptr, 0, 0, vals + j, n_scales,
                               (float*)(base + L.partial_off[j]), nullptr, tile, st);
     if (s != SSIMX_OK) return s;
+    if (sep) {  // coarsest term mean(l) * mean(cs): the mean of l as well
+      s = fwd_pass(p, dt, x, y, L.W[j], L.H[j], batch, 3, nullptr, 0, 0, (float*)(base + L.lvals_off), 1,
+                   (float*)(base + L.partial_off[j]), nullptr, tile, st);
+      if (s != SSIMX_OK) return s;
+    }
   }
   if (score_out) {
-    const int err = launch_ms_combine(vals, n_scales, batch, w, flags, score_out, cs_out, st);
+    const int err = launch_ms_combine(vals, n_scales, batch, w, flags, score_out, cs_out,
+                                      (flags & SSIMX_MS_COARSE_SEPARATE) ? (const float*)(base + L.lvals_off) : nullptr,
+                                      st);
     if (err) return hip_status(err);
   }
   return SSIMX_OK;

@@ -52,6 +52,7 @@ struct MsLayout {
   size_t partial_off[MAX_SCALES];
   size_t lvl_x_off[MAX_SCALES], lvl_y_off[MAX_SCALES];
   size_t vals_off;
+  size_t lvals_off;  // mean(l) at the coarsest scale (SSIMX_MS_COARSE_SEPARATE)
   size_t total;
 };
 MsLayout ms_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int n_scales);

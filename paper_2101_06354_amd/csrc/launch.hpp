@@ -25,7 +25,7 @@ int launch_downsample(int dtype, PlaneArg in, int W, int H, float* outx, float* 
 int launch_downsample_f(int dtype, PlaneArg x, PlaneArg y, int W, int H, int f, float* outx, float* outy, int batch,
                         hipStream_t st);
 int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w, int flags, float* score_out,
-                      float* cs_out, hipStream_t st);
+                      float* cs_out, const float* lvals, hipStream_t st);
 int launch_sat(int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, uint32_t* sat, hipStream_t st);
 int launch_sat_ssim(const uint32_t* sat, const Geom& g, int dtype, int batch, float C1, float C2, int mode,
                     float* map, int64_t map_pitch, int64_t map_bstride, float* partial, int32_t* sums, int tile_idx,

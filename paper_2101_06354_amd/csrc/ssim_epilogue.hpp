@@ -40,9 +40,10 @@ __device__ __forceinline__ SsimTerms ssim_terms_uv(float mean_u, float mean_v, f
   return t;
 }
 
-// mode 0: Q = l*cs ; mode 1: cs
+// mode 0: Q = l*cs ; mode 1: cs ; mode 3: l
 __device__ __forceinline__ float ssim_value(const SsimTerms& t, int mode) {
   if (mode == 1) return fmaf(-t.D2, __builtin_amdgcn_rcpf(t.B2), 1.f);
+  if (mode == 3) return fmaf(-t.D1, __builtin_amdgcn_rcpf(t.B1), 1.f);
   const float n = fmaf(t.D1, t.A2, t.D2 * t.B1);
   return fmaf(-n, __builtin_amdgcn_rcpf(t.B1 * t.B2), 1.f);
 }

@@ -395,7 +395,7 @@ struct Ms3Layout {
   int dt[MAX_SCALES];         // plane kind of each scale
   double cscale[MAX_SCALES];  // C1, C2 multiplier of each scale
   size_t lvl_x[MAX_SCALES], lvl_y[MAX_SCALES];
-  size_t partial, vals, total;
+  size_t partial, vals, lvals, total;
 };
 
 // For 8-bit clips the second scale is kept as exact uint16 2x2 sums (4x the
@@ -420,6 +420,7 @@ Ms3Layout ms3_layout(const ssimx_params* p, int kt, int dtype, int W, int H, int
   }
   L.partial = ws.take(sizeof(float) * np);
   L.vals = ws.take(sizeof(float) * (size_t)(frames - kt + 1) * M);
+  L.lvals = ws.take(sizeof(float) * (size_t)(frames - kt + 1));
   L.total = ws.used;
   return L;
 }
@@ -511,11 +512,18 @@ ssimx_status ssimx_msssim3d(const ssimx_params* p, int kt, const float* weights,
       }
       if (err) return hip_status(err);
     }
-    s = vol_pass(p, kt, dt, L.cscale[j], x, y, L.W[j], L.H[j], frames, j + 1 < n_scales ? 1 : 0, nullptr, 0, 0,
-                 vals + j, n_scales, (float*)(base + L.partial), st);
+    const bool sep = j + 1 == n_scales && (flags & SSIMX_MS_COARSE_SEPARATE);
+    s = vol_pass(p, kt, dt, L.cscale[j], x, y, L.W[j], L.H[j], frames, (j + 1 < n_scales || sep) ? 1 : 0, nullptr, 0,
+                 0, vals + j, n_scales, (float*)(base + L.partial), st);
     if (s != SSIMX_OK) return s;
+    if (sep) {  // coarsest term mean(l) * mean(cs): the mean of l as well
+      s = vol_pass(p, kt, dt, L.cscale[j], x, y, L.W[j], L.H[j], frames, 3, nullptr, 0, 0,
+                   (float*)(base + L.lvals), 1, (float*)(base + L.partial), st);
+      if (s != SSIMX_OK) return s;
+    }
   }
-  const int err = launch_ms_combine(vals, n_scales, frames - kt + 1, w, flags, score_out, cs_out, st);
+  const int err = launch_ms_combine(vals, n_scales, frames - kt + 1, w, flags, score_out, cs_out,
+                                    (flags & SSIMX_MS_COARSE_SEPARATE) ? (const float*)(base + L.lvals) : nullptr, st);
   return err ? hip_status(err) : SSIMX_OK;
 }
 

@@ -137,24 +137,25 @@ def _weights(weights, n_scales):
     return (ctypes.c_float * n_scales)(*[float(v) for v in weights[:n_scales]])
 
 
-def _ms_flags(renorm: bool, cs_clamp: bool, aggregation: str) -> int:
+def _ms_flags(renorm: bool, cs_clamp: bool, aggregation: str, coarse_separate: bool = False) -> int:
     if aggregation not in ("product", "sum"):
         raise ValueError(f"aggregation must be 'product' or 'sum', not {aggregation!r}")
     return ((L.MS_RENORM if renorm else 0) | (L.MS_CS_CLAMP if cs_clamp else 0)
-            | (L.MS_SUM if aggregation == "sum" else 0))
+            | (L.MS_SUM if aggregation == "sum" else 0) | (L.MS_COARSE_SEPARATE if coarse_separate else 0))
 
 
 def ms_ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, weights=MS_WEIGHTS,
             n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, return_cs: bool = False,
-            aggregation: str = "product", **kw):
+            aggregation: str = "product", coarse_separate: bool = False, **kw):
     """MS-SSIM per frame (float32 [B]); with return_cs also [B, n_scales]
     holding CS_1..CS_{M-1} and S_M.  aggregation="sum" takes the weighted
     average of the same terms with normalised weights instead of the
-    weighted product."""
+    weighted product; coarse_separate=True reads the coarsest term as
+    mean(l) * mean(cs) instead of mean(l * cs)."""
     cfg = _cfg(cfg, kw)
     xi, yi, b = _pair(x, y)
     p = cfg.to_c()
-    flags = _ms_flags(renorm, cs_clamp, aggregation)
+    flags = _ms_flags(renorm, cs_clamp, aggregation, coarse_separate)
     ws = _workspace(workspace_size(cfg, L.OP_MSSSIM, xi.dtype, xi.height, xi.width, b, n_scales), x.device)
     score = torch.empty(b, dtype=torch.float32, device=x.device)
     cs = torch.empty((b, n_scales), dtype=torch.float32, device=x.device) if return_cs else None
@@ -198,11 +199,11 @@ def ssim_map_backward(x: torch.Tensor, y: torch.Tensor, grad_map: torch.Tensor, 
 
 def ms_ssim_backward(x: torch.Tensor, y: torch.Tensor, grad_score: torch.Tensor, cfg: SSIMConfig | None = None,
                      weights=MS_WEIGHTS, n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False,
-                     aggregation: str = "product", **kw):
+                     aggregation: str = "product", coarse_separate: bool = False, **kw):
     cfg = _cfg(cfg, kw)
     xi, yi, b = _pair(x, y)
     p = cfg.to_c()
-    flags = _ms_flags(renorm, cs_clamp, aggregation)
+    flags = _ms_flags(renorm, cs_clamp, aggregation, coarse_separate)
     g = grad_score.to(device=x.device, dtype=torch.float32).reshape(b).contiguous()
     out = torch.empty(_as3(y).shape, dtype=torch.float32, device=x.device)
     ws = _workspace(workspace_size(cfg, L.OP_MSSSIM_BACKWARD, xi.dtype, xi.height, xi.width, b, n_scales),
@@ -361,7 +362,7 @@ def ssim3d(x: torch.Tensor, y: torch.Tensor, kt: int, cfg: SSIMConfig | None = N
 
 def ms_ssim3d(x: torch.Tensor, y: torch.Tensor, kt: int, cfg: SSIMConfig | None = None, weights=MS_WEIGHTS,
               n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, aggregation: str = "product",
-              return_cs: bool = False, **kw):
+              return_cs: bool = False, coarse_separate: bool = False, **kw):
     """MS-SSIM-3D of two clips (T, H, W): float32 [T-kt+1] (and, with
     return_cs, [T-kt+1, n_scales] holding CS_1..CS_{M-1} and S_M per map
     frame).  The window defaults to the 11 x 11 box."""
@@ -370,7 +371,7 @@ def ms_ssim3d(x: torch.Tensor, y: torch.Tensor, kt: int, cfg: SSIMConfig | None 
     cfg = _cfg(cfg, kw)
     xi, yi, t = _clip_pair(x, y)
     p = cfg.to_c()
-    flags = _ms_flags(renorm, cs_clamp, aggregation)
+    flags = _ms_flags(renorm, cs_clamp, aggregation, coarse_separate)
     n = ctypes.c_size_t()
     L.check(L.lib.ssimx_msssim3d_workspace_size(ctypes.byref(p), kt, n_scales, xi.dtype, xi.width, xi.height, t,
                                                 ctypes.byref(n)), "ssimx_msssim3d_workspace_size")

@@ -123,7 +123,7 @@ def test_msssim_scale_validation(L):
     assert L.lib.msssim(ctypes.byref(p), w, 5, 0, ctypes.byref(ok), ctypes.byref(ok), 1, s, None, None, 0,
                         None) == L.EWORKSPACE
     # unknown flag bits; normalised weights that sum to zero
-    assert L.lib.msssim(ctypes.byref(p), w, 5, 8, ctypes.byref(ok), ctypes.byref(ok), 1, s, None, None, 0,
+    assert L.lib.msssim(ctypes.byref(p), w, 5, 16, ctypes.byref(ok), ctypes.byref(ok), 1, s, None, None, 0,
                         None) == L.EINVAL
     wz = (ctypes.c_float * 2)(1.0, -1.0)
     for fl in (L.MS_RENORM, L.MS_SUM):
@@ -230,7 +230,7 @@ def test_ssim3d_validates_before_launch(L):
     assert L.lib.ssimx_msssim3d_workspace_size(ctypes.byref(box), 3, 3, L.U8, 64, 48, 8, ctypes.byref(n)) == L.OK
     assert L.lib.ssimx_msssim3d_workspace_size(ctypes.byref(box), 3, 4, L.U8, 64, 48, 8,
                                                ctypes.byref(n)) == L.ETOOSMALL
-    assert L.lib.ssimx_msssim3d(ctypes.byref(box), 3, w, 3, 8, ctypes.byref(clip), ctypes.byref(clip), 8, s, None,
+    assert L.lib.ssimx_msssim3d(ctypes.byref(box), 3, w, 3, 16, ctypes.byref(clip), ctypes.byref(clip), 8, s, None,
                                 None, 0, None) == L.EINVAL
     assert L.lib.ssimx_msssim3d(ctypes.byref(box), 3, w, 3, 0, ctypes.byref(clip), ctypes.byref(clip), 8, s, None,
                                 None, 0, None) == L.EWORKSPACE

@@ -193,3 +193,18 @@ def test_band_adjoint_window_sizes(P, dev, k, sigma, h, w):
     cfg = P.SSIMConfig(k=k, sigma=sigma)
     g = P.ssim_backward(to_dev(x, dev), to_dev(y, dev), torch.tensor([1.0], device=dev), cfg)
     _cmp(g.cpu().numpy(), O.ssim_pooled_backward(x, y, 1.0, oparams(cfg)), f"k{k}")
+
+
+@pytest.mark.parametrize("window,k,n_scales", [("gaussian", 11, 3), ("box", 8, 2), ("gaussian", 7, 1)])
+def test_msssim_coarse_separate_backward(P, dev, window, k, n_scales):
+    """Adjoint of the mean(l) * mean(cs) coarsest term through both coefficient
+    kernels (the stride-1 Gaussian band kernel and the generic one)."""
+    x, y = synth.config2(frames=2, h=160, w=200)
+    cfg = P.SSIMConfig(window=window, k=k, L=1023.0)
+    w = P.MS_WEIGHTS if n_scales > 1 else (1.0,)
+    g = P.ms_ssim_backward(to_dev(x, dev), to_dev(y, dev), torch.tensor([1.0, 0.5], device=dev), cfg,
+                           weights=w, n_scales=n_scales, renorm=True, coarse_separate=True).cpu().numpy()
+    for f, gs in enumerate((1.0, 0.5)):
+        gref = O.msssim_backward(x[f], y[f], gs, oparams(cfg), weights=w, n_scales=n_scales, renorm=True,
+                                 coarse_separate=True)
+        _cmp(g[f], gref, f"frame {f}")

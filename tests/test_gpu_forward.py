@@ -448,3 +448,24 @@ def test_strided_gaussian_dtypes_identity_and_tiles(P, dev, dtype):
     _, mxy = P.ssim(xt, yt, cfg, return_map=True)
     _, myx = P.ssim(yt, xt, cfg, return_map=True)
     assert torch.equal(mxy, myx)
+
+
+@pytest.mark.parametrize("window,k,algo,n_scales,aggregation", [
+    ("gaussian", 11, "auto", 3, "product"), ("gaussian", 11, "auto", 1, "product"),
+    ("gaussian", 11, "auto", 4, "sum"), ("box", 8, "separable", 1, "product"),
+    ("box", 8, "auto", 1, "product"), ("box", 8, "auto", 2, "product")])
+def test_msssim_coarse_separate(P, dev, window, k, algo, n_scales, aggregation):
+    """Coarsest term mean(l) * mean(cs): every forward kernel family's l mode."""
+    x, y = synth.config1(frames=2, h=200, w=260)
+    cfg = P.SSIMConfig(window=window, k=k, algo=algo)
+    w = P.MS_WEIGHTS if n_scales > 1 else (1.0,)
+    s, cs = P.ms_ssim(to_dev(x, dev), to_dev(y, dev), cfg, weights=w, n_scales=n_scales, renorm=True,
+                      aggregation=aggregation, coarse_separate=True, return_cs=True)
+    s, cs = s.cpu().numpy(), cs.cpu().numpy()
+    for f in range(2):
+        r = O.msssim(x[f], y[f], oparams(cfg), w, n_scales, True, aggregation=aggregation, coarse_separate=True)
+        assert abs(s[f] - r["score"]) <= SCORE_TOL
+        assert abs(cs[f, -1] - r["s_M"]) <= SCORE_TOL
+    xi = to_dev(x, dev)
+    one = P.ms_ssim(xi, xi, cfg, weights=w, n_scales=n_scales, renorm=True, coarse_separate=True).cpu().numpy()
+    assert np.all(np.abs(one - 1.0) <= 1e-6)

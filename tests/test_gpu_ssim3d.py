@@ -195,3 +195,12 @@ def test_msssim3d_bf16_clip(P, dev):
     s = P.ms_ssim3d(xt, yt, 3, cfg, n_scales=3, renorm=True).cpu().numpy()
     r = O.msssim3d(xa, ya, oparams(cfg), 3, P.MS_WEIGHTS, 3, renorm=True)
     np.testing.assert_allclose(s, r["score"], rtol=0, atol=SCORE_TOL)
+
+
+def test_msssim3d_coarse_separate(P, dev):
+    x, y = synth.video_clip(7, 96, 120, stream=13)
+    cfg = _box(P, 11)
+    s = P.ms_ssim3d(to_dev(x, dev), to_dev(y, dev), 3, cfg, n_scales=2, renorm=True,
+                    coarse_separate=True).cpu().numpy()
+    r = O.msssim3d(x, y, oparams(cfg), 3, P.MS_WEIGHTS, 2, renorm=True, coarse_separate=True)
+    np.testing.assert_allclose(s, r["score"], rtol=0, atol=SCORE_TOL)
