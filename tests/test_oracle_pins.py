@@ -423,3 +423,41 @@ def test_rgb_luma():
     np.testing.assert_allclose(O.rgb_to_y_bt601(rgb), 0.3, atol=1e-15)
     assert abs(sum(O.BT601) - 1.0) < 1e-15
     np.testing.assert_allclose(O.y_grad_to_rgb_bt601(np.ones((2, 2)))[:, 0, 0], O.BT601)
+
+
+@pytest.mark.parametrize("padding,stride,window,k", [("valid", 1, "gaussian", 7), ("zero", 2, "gaussian", 5),
+                                                   ("reflect", 3, "gaussian", 7), ("reflect", 1, "box", 4),
+                                                   ("zero", 1, "box", 3)])
+def test_adjoint_dot_product_over_the_whole_map(padding, stride, window, k):
+    """<J dy, g> = <dy, J^T g> for random directions dy and random upstream maps
+    g: J dy by FP64 central differences of the map, J^T g by the adjoint (the
+    transposed window, the border fold and the per-pixel combine together)."""
+    rng = np.random.default_rng(77)
+    x = synth.smooth_field(rng, 29, 33, 20, 230)
+    y = np.clip(x + rng.normal(0, 12, x.shape), 0, 255)
+    C1, C2 = O.constants(0.01, 0.03, 255.0)
+    p = O.SSIMParams(window=window, k=k, sigma=1.2, C1=C1, C2=C2, stride=stride, padding=padding)
+    q0 = O.ssim_map(x, y, p)["map"]
+    g = rng.normal(size=q0.shape)
+    dy = rng.normal(size=y.shape)
+    h = 1e-4
+    jdy = (O.ssim_map(x, y + h * dy, p)["map"] - O.ssim_map(x, y - h * dy, p)["map"]) / (2 * h)
+    lhs = float((jdy * g).sum())
+    rhs = float((dy * O.ssim_map_backward(x, y, g, p)).sum())
+    assert abs(lhs - rhs) <= 1e-7 * max(abs(lhs), 1e-12), (lhs, rhs)
+
+
+def test_msssim_directional_derivative():
+    rng = np.random.default_rng(78)
+    x = synth.smooth_field(rng, 80, 72, 20, 230)
+    y = np.clip(x + rng.normal(0, 10, x.shape), 0, 255)
+    p = O.SSIMParams(k=7, sigma=1.0)
+    dy = rng.normal(size=y.shape)
+    h = 1e-4
+    for agg, sep in (("product", False), ("sum", True)):
+        f = lambda yy: O.msssim(x, yy, p, n_scales=3, renorm=True, aggregation=agg,  # noqa: E731
+                                coarse_separate=sep)["score"]
+        lhs = (f(y + h * dy) - f(y - h * dy)) / (2 * h)
+        rhs = float((dy * O.msssim_backward(x, y, 1.0, p, n_scales=3, renorm=True, aggregation=agg,
+                                            coarse_separate=sep)).sum())
+        assert abs(lhs - rhs) <= 1e-7 * abs(lhs), (agg, lhs, rhs)
