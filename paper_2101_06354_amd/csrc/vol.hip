@@ -35,6 +35,7 @@ constexpr int kVolOW = 64;   // map columns per tile
 constexpr int kVolSeg = 16;  // map columns per horizontal task
 constexpr int kVolKMax = 16;
 constexpr int kVolKtMax = 64;
+constexpr int kVolWaves = kVolNT / 64;  // pooled partials per tile and map frame
 
 struct VolArgs {
   PlaneArg x, y;
@@ -50,7 +51,7 @@ struct VolArgs {
   int mode;          // 0: l*cs, 1: cs
   float* map;        // nullable: [n_out][Ho][map_pitch], frame stride map_fstride
   int64_t map_pitch, map_fstride;
-  float* partial;    // [n_out][tiles]
+  float* partial;    // [n_out][tiles][waves]
 };
 
 template <typename Acc, int OH, int KCAP>
@@ -101,14 +102,15 @@ __device__ __forceinline__ float vol_value(double sx, double sy, double sxx, dou
 }
 
 // KC > 0: the window size is the compile-time constant KC (loops unroll);
-// KC == 0: runtime k <= KCAP.
-template <typename T, typename Acc, int OH, int KC, int KCAP>
+// KC == 0: runtime k <= KCAP.  G map rows per column task (OH = multiple of G,
+// 64 * OH / G <= 256 tasks).
+template <typename T, typename Acc, int OH, int G, int KC, int KCAP>
 __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
+  static_assert(OH % G == 0 && kVolOW * (OH / G) <= kVolNT, "column tasks must fit the workgroup");
   using S = VolShape<Acc, OH, (KC > 0 ? KC : KCAP)>;
   using RawT = Raw<T, Acc>;
   __shared__ Acc tsum[S::T_WORDS];  // [5][IH][IWP] temporal sums of the footprint
   __shared__ Acc hsum[S::H_WORDS];  // [5][IH][HSP] k-wide row sums
-  __shared__ float red[kVolNT / 64];
 
   int tile, seg;
   xcd_tile(tile, seg);
@@ -219,26 +221,26 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
     const int t = f - f_first_out + t0;  // map frame
     float part = 0.f;
     const int j = tid % kVolOW, g = tid / kVolOW;
-    if (g < OH / 4) {
-      Acc acc[4][5];
+    if (g < OH / G) {
+      Acc acc[G][5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        const Acc* col = hsum + (m * IH + 4 * g) * S::HSP + j;
+        const Acc* col = hsum + (m * IH + G * g) * S::HSP + j;
         Acc s = (Acc)0;
 #pragma unroll
         for (int r = 0; r < (KC > 0 ? KC : KCAP); ++r)
           if (KC > 0 || r < k) s += col[r * S::HSP];
         acc[0][m] = s;
 #pragma unroll
-        for (int i = 1; i < 4; ++i) {
+        for (int i = 1; i < G; ++i) {
           s += col[(i + k - 1) * S::HSP] - col[(i - 1) * S::HSP];
           acc[i][m] = s;
         }
       }
       const int oj = col0 + j;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int oi = row0 + 4 * g + i;
+      for (int i = 0; i < G; ++i) {
+        const int oi = row0 + G * g + i;
         if (oi < a.Ho && oj < a.Wo) {
           const float v = vol_value((double)acc[i][0], (double)acc[i][1], (double)acc[i][2], (double)acc[i][3],
                                     (double)acc[i][4], a.N, a.invN2, a.C1, a.C2, a.mode);
@@ -247,27 +249,32 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
         }
       }
     }
-    const float tot = block_sum<kVolNT>(part, red);
-    if (tid == 0) a.partial[(int64_t)t * (a.tiles_x * a.tiles_y) + tile] = tot;
+    // one partial per wave (no barrier); the finalize adds them in a fixed order
+    const float tot = wave_sum(part);
+    if ((tid & 63) == 0)
+      a.partial[((int64_t)t * (a.tiles_x * a.tiles_y) + tile) * kVolWaves + (tid >> 6)] = tot;
   }
 }
 
-// Rows of map positions per tile for each accumulator type (LDS budget).
-template <typename Acc>
-constexpr int vol_oh() {
-  return std::is_same<Acc, uint32_t>::value ? 16 : 8;
-}
+// Rows of map positions per tile (LDS budget): 16 for integer sums, 8 for
+// float64 sums.  (15-row tiles for the 11 x 11 window, whose 500 row-sum
+// tasks fill exactly two rounds of the workgroup, measured no faster.)
+constexpr int kVolOHInt = 16, kVolOHF64 = 8;
+
+int vol_tile_rows(bool int_acc, int) { return int_acc ? kVolOHInt : kVolOHF64; }
 
 template <typename T, typename Acc>
 int launch_vol_t(const VolArgs& a, int nsegs, hipStream_t st) {
-  constexpr int OH = vol_oh<Acc>();
+  constexpr bool kInt = std::is_same<Acc, uint32_t>::value;
+  constexpr int OH = kInt ? kVolOHInt : kVolOHF64;
   const dim3 grid(a.tiles_x * a.tiles_y, nsegs);
-  if (a.k == 11)
-    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 11, 11>), grid, dim3(kVolNT), 0, st, a);
-  else if (a.k < 11)
-    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 0, 11>), grid, dim3(kVolNT), 0, st, a);
-  else
-    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 0, kVolKMax>), grid, dim3(kVolNT), 0, st, a);
+  if (a.k == 11) {
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 4, 11, 11>), grid, dim3(kVolNT), 0, st, a);
+  } else if (a.k < 11) {
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 4, 0, 11>), grid, dim3(kVolNT), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 4, 0, kVolKMax>), grid, dim3(kVolNT), 0, st, a);
+  }
   return (int)hipGetLastError();
 }
 
@@ -287,7 +294,7 @@ VolGeom vol_geom(int W, int H, int frames, int k, int kt, int dtype) {
   g.Wo = W - k + 1;
   g.Ho = H - k + 1;
   g.n_out = frames - kt + 1;
-  const int OH = vol_int_acc(dtype) ? vol_oh<uint32_t>() : vol_oh<double>();
+  const int OH = vol_tile_rows(vol_int_acc(dtype), k);
   g.tiles_x = (g.Wo + kVolOW - 1) / kVolOW;
   g.tiles_y = (g.Ho + OH - 1) / OH;
   // Split the frames into runs so that the grid holds about 4096 workgroups,
@@ -350,7 +357,8 @@ ssimx_status vol_pass(const ssimx_params* p, int kt, int dtype, double cscale, P
   }
   if (err) return hip_status(err);
   if (out) {
-    err = launch_finalize(partial, g.tiles_x * g.tiles_y, g.n_out, g.Wo * g.Ho, 1.f, out, out_stride, st);
+    err = launch_finalize(partial, g.tiles_x * g.tiles_y * kVolWaves, g.n_out, g.Wo * g.Ho, 1.f, out, out_stride,
+                          st);
     if (err) return hip_status(err);
   }
   return SSIMX_OK;
@@ -358,7 +366,7 @@ ssimx_status vol_pass(const ssimx_params* p, int kt, int dtype, double cscale, P
 
 size_t vol_partial_floats(int W, int H, int frames, int k, int kt, int dtype) {
   const VolGeom g = vol_geom(W, H, frames, k, kt, dtype);
-  return (size_t)g.n_out * g.tiles_x * g.tiles_y;
+  return (size_t)g.n_out * g.tiles_x * g.tiles_y * kVolWaves;
 }
 
 size_t vol_ws_bytes(int W, int H, int frames, int k, int kt, int dtype) {
