@@ -234,3 +234,27 @@ def test_ssim3d_validates_before_launch(L):
                                 None, 0, None) == L.EINVAL
     assert L.lib.ssimx_msssim3d(ctypes.byref(box), 3, w, 3, 0, ctypes.byref(clip), ctypes.byref(clip), 8, s, None,
                                 None, 0, None) == L.EWORKSPACE
+
+
+def test_package_fails_loudly_without_the_library(tmp_path):
+    """A copy of the package without libssimx.so must not import (no CPU path)."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_2101_06354_amd")
+    dst = tmp_path / "paper_2101_06354_amd"
+    shutil.copytree(src, dst, ignore=shutil.ignore_patterns("*.so", "_build", "csrc", "__pycache__"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2101_06354_amd"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "not built" in r.stderr
+
+
+def test_host_tensors_are_rejected_not_computed(L):
+    import torch
+    import paper_2101_06354_amd as P
+    x = torch.zeros((1, 32, 32), dtype=torch.uint8)
+    with pytest.raises(ValueError, match="device tensors"):
+        P.ssim(x, x)
+    with pytest.raises(ValueError):
+        P.ssim3d(torch.zeros((4, 32, 32), dtype=torch.uint8), torch.zeros((4, 32, 32), dtype=torch.uint8), 2)
