@@ -357,8 +357,10 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     if (err) return hip_status(err);
   }
   if (fast && valid) {
-    fa.QH = 128;
+    // 256-row tiles halve the share of the K - 1 prologue rows when the
+    // launch still holds >= 4096 workgroups; smaller launches keep 128 rows
     fa.qtiles_x = (lv.W + 63) / 64;
+    fa.QH = (int64_t)fa.qtiles_x * ((lv.H + 255) / 256) * batch >= 4096 ? 256 : 128;
     fa.qtiles_y = (lv.H + fa.QH - 1) / fa.QH;
     fa.out = out;
     fa.out_pitch = out_pitch;

@@ -3,11 +3,15 @@
 // Cb = 0.539 (B - Y), Cr = 0.635 (R - Y)), the pooled SSIM of each channel,
 // and (f(Y) + alpha f(Cb) + beta f(Cr)) / (1 + alpha + beta).
 //
-// The three channel planes of a frame are written as three consecutive
-// float32 frames, so one batched windowed pass over 3 B frames serves every
-// channel; a small kernel forms the weighted average.
+// 8-bit RGB on the stride-1 Gaussian band path: the band kernel reads the R,
+// G, B planes and forms each channel while staging its tile (staged frame
+// 3 b + c is channel c of frame b), so no channel planes are stored.
+// Otherwise the three channel planes of a frame are written as three
+// consecutive float32 frames and one batched windowed pass over 3 B frames
+// serves every channel.  A small kernel forms the weighted average.
 #include <math.h>
 
+#include "fast_tile.hpp"
 #include "launch.hpp"
 #include "host_common.hpp"
 #include "ssimx_internal.hpp"
@@ -112,6 +116,25 @@ ssimx_status ssimx_color_ssim(const ssimx_params* p, double alpha, double beta, 
   if (!ws || ws_bytes < L.total) return SSIMX_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   char* base = (char*)ws;
+  float* scores = (float*)(base + L.scores_off);
+  if (dtype == SSIMX_U8 && use_fast(p, SSIMX_F32)) {
+    const int tile = pick_tile(p, SSIMX_F32, w, h, 3 * batch);
+    const Geom g = fast_geom(p, w, h, tile);
+    FastArgs a{};
+    fill_fast_common(a, p, SSIMX_U8, PlaneArg{ref_rgb, pitch, batch_stride}, PlaneArg{dis_rgb, pitch, batch_stride},
+                     g);
+    a.vec_ok = a.vec_ok && channel_stride % 4 == 0;
+    a.cstride = channel_stride;
+    a.mode = 0;
+    a.partial = (float*)(base + L.fwd_off);
+    a.batch = 3 * batch;
+    int err = launch_fast_stats_rgb(a, batch, st);
+    if (!err) err = launch_finalize(a.partial, g.tiles_x * g.tiles_y, 3 * batch, g.Wo * g.Ho, 1.f, scores, 1, st);
+    if (err) return hip_status(err);
+    hipLaunchKernelGGL(color_combine_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, scores, batch, (float)alpha,
+                       (float)beta, score_out, channel_scores);
+    return hip_status((int)hipGetLastError());
+  }
   float* px = (float*)(base + L.planes_off);
   float* py = px + 3 * (size_t)batch * w * h;
   for (int side = 0; side < 2; ++side) {
@@ -126,7 +149,6 @@ ssimx_status ssimx_color_ssim(const ssimx_params* p, double alpha, double beta, 
   }
   int err = (int)hipGetLastError();
   if (err) return hip_status(err);
-  float* scores = (float*)(base + L.scores_off);
   PlaneArg x{px, w, (int64_t)w * h}, y{py, w, (int64_t)w * h};
   const int tile = pick_tile(p, SSIMX_F32, w, h, 3 * batch);
   s = fwd_pass(p, SSIMX_F32, x, y, w, h, 3 * batch, 0, nullptr, 0, 0, scores, 1, (float*)(base + L.fwd_off), nullptr,

@@ -58,6 +58,18 @@ static int launch_stats_k(int dtype, const FastArgs& a, dim3 grid, hipStream_t s
   return (int)hipGetLastError();
 }
 
+int launch_fast_stats_rgb(const FastArgs& a, int batch, hipStream_t st) {
+  dim3 grid(a.g.tiles_x * a.g.tiles_y, 3 * batch);
+  switch (a.g.k) {
+    case 7: hipLaunchKernelGGL((fast_stats_kernel<7, Rgb8, 0>), grid, dim3(kNT), 0, st, a); break;
+    case 9: hipLaunchKernelGGL((fast_stats_kernel<9, Rgb8, 0>), grid, dim3(kNT), 0, st, a); break;
+    case 11: hipLaunchKernelGGL((fast_stats_kernel<11, Rgb8, 0>), grid, dim3(kNT), 0, st, a); break;
+    case 13: hipLaunchKernelGGL((fast_stats_kernel<13, Rgb8, 0>), grid, dim3(kNT), 0, st, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
 int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStream_t st) {
   dim3 grid(a.g.tiles_x * a.g.tiles_y, batch);
 #define SSIMX_K(KK)                                                                          \

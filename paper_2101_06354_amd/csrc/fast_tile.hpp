@@ -5,12 +5,19 @@
 
 namespace ssimx {
 
+// 8-bit planar RGB source of the colour path: staged frame 3 b + c of a launch
+// is channel c (0 Y, 1 Cb, 2 Cr, BT.709 as printed) of RGB frame b.
+struct Rgb8 {
+  uint8_t v;
+};
+
 struct FastArgs {
   PlaneArg x, y;
   Geom g;            // TW fixed at 64; TH = output rows per tile (multiple of 16)
   float C1, C2;
   int mode;          // 0: Q = l*cs, 1: cs, 3: l (forward) / g_l l + g_cs cs (coefficients)
   int vec_ok;        // 4-element vector loads allowed for interior footprint rows
+  int64_t cstride;   // Rgb8 sources: elements between the R, G and B planes
   // forward epilogue
   float* map;
   int64_t map_pitch, map_bstride;
@@ -39,6 +46,9 @@ struct FastArgs {
 bool fast_supported(int k, int stride);
 int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStream_t st);
 int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st);
+// Colour path: pooled partials of the three YCbCr channels of `batch` 8-bit
+// RGB frames, staged frames 3 b + c (EPI 0, mode 0).
+int launch_fast_stats_rgb(const FastArgs& a, int batch, hipStream_t st);
 int fast_chunks(int tile_idx);   // 16-row chunks per tile of the fast kernels
 
 }  // namespace ssimx

@@ -29,6 +29,8 @@
 //                                 transpose of a coarser-scale gradient.
 #pragma once
 
+#include <type_traits>
+
 #include "fast_tile.hpp"
 #include "ssim_epilogue.hpp"
 #include "ssimx_internal.hpp"
@@ -89,22 +91,6 @@ __device__ __forceinline__ void load4(const T* P, int64_t pitch, const Geom& g, 
     o[i] = padded_source(py, px + i, g.H, g.W, g.pad, g.before, g.Hp, g.Wp, sy, sx)
                ? to_f32<T>(P[(int64_t)sy * pitch + sx])
                : 0.f;
-  }
-}
-
-// Stage `nrows` footprint rows starting at padded row py0 into U, V (u = x+y,
-// v = x-y).
-template <int K, typename T>
-__device__ __forceinline__ void stage_rows(const FastArgs& a, const T* X, const T* Y, int py0, int px0, int nrows,
-                                           float* U, float* V) {
-  using S = Shape<K>;
-  for (int it = threadIdx.x; it < nrows * S::NQ; it += kNT) {
-    const int r = it / S::NQ, q = it - r * S::NQ;
-    float xv[4], yv[4];
-    load4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, xv);
-    load4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, yv);
-    *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
-    *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
   }
 }
 
@@ -176,6 +162,78 @@ __device__ __forceinline__ void unpack4(const Quad<T>& q, float* o) {
   }
 }
 
+// ---- 8-bit planar RGB sources (colour path)
+template <>
+struct Quad<Rgb8> {
+  static constexpr int NW = 3;  // the R, G, B words of 4 pixels
+  uint32_t w[3];
+};
+
+// Channel c of BT.709 YCbCr as printed (0 Y, 1 Cb, 2 Cr), in the operation
+// order of the stand-alone transform kernel.
+__device__ __forceinline__ float ycbcr709(float R, float G, float B, int c) {
+  const float Y = fmaf(0.213f, R, fmaf(0.715f, G, 0.072f * B));
+  return c == 0 ? Y : (c == 1 ? 0.539f * (B - Y) : 0.635f * (R - Y));
+}
+
+__device__ __forceinline__ void fetch4_rgb(const uint8_t* P, int64_t pitch, int64_t cs, const Geom& g, int vec_ok,
+                                           int py, int px, Quad<Rgb8>& q) {
+  if (vec_ok && g.pad == SSIMX_PAD_VALID && py < g.H && px + 3 < g.W) {
+    const uint8_t* s = P + (int64_t)py * pitch + px;
+    q.w[0] = *(const uint32_t*)s;
+    q.w[1] = *(const uint32_t*)(s + cs);
+    q.w[2] = *(const uint32_t*)(s + 2 * cs);
+    return;
+  }
+  q.w[0] = q.w[1] = q.w[2] = 0u;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int sy, sx;
+    if (padded_source(py, px + i, g.H, g.W, g.pad, g.before, g.Hp, g.Wp, sy, sx)) {
+      const uint8_t* s = P + (int64_t)sy * pitch + sx;
+      q.w[0] |= (uint32_t)s[0] << (8 * i);
+      q.w[1] |= (uint32_t)s[cs] << (8 * i);
+      q.w[2] |= (uint32_t)s[2 * cs] << (8 * i);
+    }
+  }
+}
+
+__device__ __forceinline__ void unpack4_rgb(const Quad<Rgb8>& q, int c, float* o) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    o[i] = ycbcr709((float)((q.w[0] >> (8 * i)) & 0xffu), (float)((q.w[1] >> (8 * i)) & 0xffu),
+                    (float)((q.w[2] >> (8 * i)) & 0xffu), c);
+}
+
+template <typename T>
+constexpr bool is_rgb() {
+  return std::is_same<T, Rgb8>::value;
+}
+
+// Stage `nrows` footprint rows starting at padded row py0 into U, V (u = x+y,
+// v = x-y).
+template <int K, typename T>
+__device__ __forceinline__ void stage_rows(const FastArgs& a, const T* X, const T* Y, int py0, int px0, int nrows,
+                                           float* U, float* V, int ch) {
+  using S = Shape<K>;
+  for (int it = threadIdx.x; it < nrows * S::NQ; it += kNT) {
+    const int r = it / S::NQ, q = it - r * S::NQ;
+    float xv[4], yv[4];
+    if constexpr (is_rgb<T>()) {
+      Quad<Rgb8> qa, qb;
+      fetch4_rgb((const uint8_t*)X, a.x.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qa);
+      fetch4_rgb((const uint8_t*)Y, a.y.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qb);
+      unpack4_rgb(qa, ch, xv);
+      unpack4_rgb(qb, ch, yv);
+    } else {
+      load4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, xv);
+      load4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, yv);
+    }
+    *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
+    *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
+  }
+}
+
 // Chunk staging split in two halves: fetch_chunk issues the global loads of
 // kCH footprint rows into registers, store_chunk converts them to u, v and
 // writes LDS.
@@ -194,14 +252,19 @@ __device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const
     const int it = threadIdx.x + i * kNT;
     if (it < ChunkItems<K>::N) {
       const int r = it / S::NQ, q = it - r * S::NQ;
-      fetch4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qx[i]);
-      fetch4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qy[i]);
+      if constexpr (is_rgb<T>()) {
+        fetch4_rgb((const uint8_t*)X, a.x.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qx[i]);
+        fetch4_rgb((const uint8_t*)Y, a.y.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qy[i]);
+      } else {
+        fetch4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qx[i]);
+        fetch4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qy[i]);
+      }
     }
   }
 }
 
 template <int K, typename T>
-__device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy, float* U, float* V) {
+__device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy, float* U, float* V, int ch) {
   using S = Shape<K>;
 #pragma unroll
   for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
@@ -209,8 +272,13 @@ __device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy
     if (it < ChunkItems<K>::N) {
       const int r = it / S::NQ, q = it - r * S::NQ;
       float xv[4], yv[4];
-      unpack4<T>(qx[i], xv);
-      unpack4<T>(qy[i], yv);
+      if constexpr (is_rgb<T>()) {
+        unpack4_rgb(qx[i], ch, xv);
+        unpack4_rgb(qy[i], ch, yv);
+      } else {
+        unpack4<T>(qx[i], xv);
+        unpack4<T>(qy[i], yv);
+      }
       *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
       *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
     }
@@ -297,14 +365,17 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
   const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
   // block-uniform tile origin and chunk-loop bound (scalar loop control)
   const int ox0 = __builtin_amdgcn_readfirstlane(txi * kTW), oy0 = __builtin_amdgcn_readfirstlane(tyi * a.g.TH);
-  const T* X = (const T*)a.x.data + (int64_t)frame * a.x.bstride;
-  const T* Y = (const T*)a.y.data + (int64_t)frame * a.y.bstride;
+  // RGB sources: staged frame 3 b + c is channel c of RGB frame b
+  const int src = is_rgb<T>() ? frame / 3 : frame;
+  const int ch = is_rgb<T>() ? frame - 3 * src : 0;
+  const T* X = (const T*)a.x.data + (int64_t)src * a.x.bstride;
+  const T* Y = (const T*)a.y.data + (int64_t)src * a.y.bstride;
   float taps[K];
 #pragma unroll
   for (int t = 0; t < K; ++t) taps[t] = a.taps[t];
 
   // prologue: the first K-1 footprint rows
-  stage_rows<K, T>(a, X, Y, oy0, ox0, S::HALO, U, V);
+  stage_rows<K, T>(a, X, Y, oy0, ox0, S::HALO, U, V, ch);
   __syncthreads();
   row_pass<K>(taps, U, V, S::HALO, HM, 0);
 
@@ -316,7 +387,7 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
   fetch_chunk<K, T>(a, X, Y, oy0 + S::HALO, ox0, qx, qy);
   for (int cy = oy0; cy < oy_end; cy += kCH) {
     __syncthreads();  // U, V free; band rows [0, HALO) ready
-    store_chunk<K, T>(qx, qy, U, V);
+    store_chunk<K, T>(qx, qy, U, V, ch);
     // the next chunk's pixels are loaded while this chunk's row and column
     // passes run (the registers were just staged)
     if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);

@@ -57,3 +57,34 @@ def test_color_ssim_float_rgb_and_grey(P, dev):
     gd = np.repeat(d4[:, :1], 3, axis=1)
     _, ch = P.color_ssim(to_dev(g, dev), to_dev(gd, dev), cfg, return_channels=True)
     assert float((ch[:, 1:] - 1.0).abs().max()) <= SCORE_TOL
+
+
+@pytest.mark.parametrize("padding", ["valid", "reflect"])
+def test_color_ssim_u8_fused_matches_two_step_bitwise(P, dev, padding):
+    """8-bit RGB on the Gaussian band path forms the channels while staging;
+    the same values as float32 RGB go through stored channel planes.  Both
+    stage identical floats, so the scores agree bit for bit."""
+    x, y = _rgb_u8(5, 3, 120, 200)
+    cfg = P.SSIMConfig(padding=padding)
+    s8, c8 = P.color_ssim(to_dev(x, dev), to_dev(y, dev), cfg, return_channels=True)
+    sf, cf = P.color_ssim(to_dev(x.astype(np.float32), dev), to_dev(y.astype(np.float32), dev), cfg,
+                          return_channels=True)
+    assert torch.equal(c8, cf) and torch.equal(s8, sf)
+    for f in range(3):
+        r = O.color_ssim(x[f], y[f], oparams(cfg))
+        np.testing.assert_allclose(c8[f].cpu().numpy(), r["channels"], rtol=0, atol=SCORE_TOL)
+
+
+def test_color_ssim_u8_unaligned_pitch(P, dev):
+    """Rows that are not 4-byte aligned take the element-wise loads."""
+    x, y = _rgb_u8(6, 2, 90, 157)
+    bx = torch.zeros((2, 3, 90, 163), dtype=torch.uint8, device=dev)
+    by = torch.zeros_like(bx)
+    bx[..., 1:158] = to_dev(x, dev)
+    by[..., 1:158] = to_dev(y, dev)
+    cfg = P.SSIMConfig()
+    s, ch = P.color_ssim(bx[..., 1:158], by[..., 1:158], cfg, return_channels=True)
+    for f in range(2):
+        r = O.color_ssim(x[f], y[f], oparams(cfg))
+        np.testing.assert_allclose(ch[f].cpu().numpy(), r["channels"], rtol=0, atol=SCORE_TOL)
+        assert abs(float(s[f]) - r["score"]) <= SCORE_TOL
