@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
   int tile, frame;
   xcd_tile(tile, frame);
   const float acc = fast_stats_tile<K, T, EPI>(a, frame, tile, smem);
-  if constexpr (EPI == 0) {
+  if constexpr (EPI != 1) {
     const float tot = block_sum<kNT>(acc, red);
     if (threadIdx.x == 0) a.partial[(int64_t)frame * gridDim.x + tile] = tot;
   }
@@ -74,7 +74,8 @@ int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStrea
   dim3 grid(a.g.tiles_x * a.g.tiles_y, batch);
 #define SSIMX_K(KK)                                                                          \
   case KK:                                                                                   \
-    return epi == 0 ? launch_stats_k<KK, 0>(dtype, a, grid, st) : launch_stats_k<KK, 1>(dtype, a, grid, st);
+    return epi == 0 ? launch_stats_k<KK, 0>(dtype, a, grid, st)                              \
+                    : epi == 1 ? launch_stats_k<KK, 1>(dtype, a, grid, st) : launch_stats_k<KK, 2>(dtype, a, grid, st);
   switch (a.g.k) {
     SSIMX_K(7)
     SSIMX_K(9)

@@ -22,6 +22,11 @@ struct FastArgs {
   float* map;
   int64_t map_pitch, map_bstride;
   float* partial;
+  // forward, optional (valid borders): the 2x2-average down-sampled x, y of
+  // the next MS-SSIM scale, float32 [batch][H/2][W/2]; every tile writes the
+  // blocks of the input rows and columns it owns
+  float* ds_x;
+  float* ds_y;
   // coefficient epilogue
   const float* grad_map;
   int64_t gm_pitch, gm_bstride;
@@ -44,6 +49,7 @@ struct FastArgs {
 };
 
 bool fast_supported(int k, int stride);
+// epi 0: forward, 1: adjoint coefficients, 2: forward + 2x2 means (a.ds_x, a.ds_y)
 int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStream_t st);
 int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st);
 // Colour path: pooled partials of the three YCbCr channels of `batch` 8-bit

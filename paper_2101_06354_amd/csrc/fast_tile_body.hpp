@@ -285,6 +285,34 @@ __device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy
   }
 }
 
+// 2x2 means of the staged rows rbase .. rbase + nrows - 1 (LDS rows 0 ..) that
+// the tile owns: input rows [own_r0, own_r1) and columns [ox0, own_c1).  With
+// u = x + y and v = x - y staged, the x mean is the sum of u + v over the
+// block / 8 and the y mean the sum of u - v / 8: exact, and equal to the
+// stand-alone down-sampling, for integer-valued planes and their pyramid
+// levels.  Every boundary is even, so no block straddles two tiles or chunks.
+template <int K>
+__device__ __forceinline__ void emit_down(const FastArgs& a, const float* U, const float* V, int rbase, int nrows,
+                                          int ox0, int own_r0, int own_r1, int own_c1, int frame) {
+  using S = Shape<K>;
+  const int W2 = a.g.W / 2, H2 = a.g.H / 2;
+  const int r_lo = max(rbase, own_r0), r_hi = min(min(rbase + nrows, own_r1), 2 * H2);
+  const int c_hi = min(own_c1, 2 * W2);
+  if (r_hi <= r_lo || c_hi <= ox0) return;  // uniform over the block
+  const int npr = (r_hi - r_lo) / 2, npc = (c_hi - ox0) / 2;
+  for (int it = threadIdx.x; it < npr * npc; it += kNT) {
+    const int pr = it / npc, pc = it - pr * npc;
+    const int ri = r_lo - rbase + 2 * pr, ci = 2 * pc;
+    const float2 u0 = *(const float2*)&U[ri * S::IWP + ci], u1 = *(const float2*)&U[(ri + 1) * S::IWP + ci];
+    const float2 v0 = *(const float2*)&V[ri * S::IWP + ci], v1 = *(const float2*)&V[(ri + 1) * S::IWP + ci];
+    const float sx = ((u0.x + v0.x) + (u0.y + v0.y)) + ((u1.x + v1.x) + (u1.y + v1.y));
+    const float sy = ((u0.x - v0.x) + (u0.y - v0.y)) + ((u1.x - v1.x) + (u1.y - v1.y));
+    const int64_t o = ((int64_t)frame * H2 + (r_lo / 2 + pr)) * W2 + (ox0 / 2 + pc);
+    a.ds_x[o] = 0.125f * sx;
+    a.ds_y[o] = 0.125f * sy;
+  }
+}
+
 // Row pass over `nrows` staged rows into band rows [band0, band0 + nrows).
 template <int K>
 __device__ __forceinline__ void row_pass(const float* taps, const float* U, const float* V, int nrows, float* HM,
@@ -352,8 +380,10 @@ __host__ __device__ constexpr int fast_smem_floats() {
   return 2 * kCH * Shape<K>::IWP + 4 * Shape<K>::PL;
 }
 
-// One map tile: returns this thread's share of the tile's pooled sum (EPI 0)
-// or 0 (EPI 1).  `smem` holds fast_smem_floats<K>() floats.
+// One map tile: returns this thread's share of the tile's pooled sum (EPI 0:
+// forward; EPI 2: forward that also writes the 2x2 means of its input to
+// a.ds_x, a.ds_y) or 0 (EPI 1: adjoint coefficients).  `smem` holds
+// fast_smem_floats<K>() floats.
 template <int K, typename T, int EPI>
 __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, int tile, float* smem) {
   using S = Shape<K>;
@@ -374,9 +404,15 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
 #pragma unroll
   for (int t = 0; t < K; ++t) taps[t] = a.taps[t];
 
+  // input rows and columns whose 2x2 means this tile writes (down-sampling)
+  constexpr bool down = EPI == 2;  // forward plus the next scale's 2x2 means
+  const int own_r1 = tyi == a.g.tiles_y - 1 ? a.g.H : oy0 + a.g.TH;
+  const int own_c1 = txi == a.g.tiles_x - 1 ? a.g.W : ox0 + kTW;
+
   // prologue: the first K-1 footprint rows
   stage_rows<K, T>(a, X, Y, oy0, ox0, S::HALO, U, V, ch);
   __syncthreads();
+  if constexpr (down) emit_down<K>(a, U, V, oy0, S::HALO, ox0, oy0, own_r1, own_c1, frame);
   row_pass<K>(taps, U, V, S::HALO, HM, 0);
 
   const float gframe = (EPI == 1 && !a.grad_map) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
@@ -389,9 +425,15 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
     __syncthreads();  // U, V free; band rows [0, HALO) ready
     store_chunk<K, T>(qx, qy, U, V, ch);
     // the next chunk's pixels are loaded while this chunk's row and column
-    // passes run (the registers were just staged)
-    if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
+    // passes run (the registers were just staged; with down-sampling, after
+    // the 2x2 means are written, which keeps those registers free for it)
+    if constexpr (!down)
+      if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
     __syncthreads();
+    if constexpr (down) {
+      emit_down<K>(a, U, V, cy + S::HALO, kCH, ox0, oy0, own_r1, own_c1, frame);
+      if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
+    }
     row_pass<K>(taps, U, V, kCH, HM, S::HALO);
     __syncthreads();
     // column pass: item = (4 output rows, 1 column)
@@ -426,7 +468,7 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
         const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
         const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
         const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
-        if constexpr (EPI == 0) {
+        if constexpr (EPI != 1) {
           const float val = ssim_value(t, a.mode);
           if (a.map) a.map[(int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + oj] = val;
           acc += val;

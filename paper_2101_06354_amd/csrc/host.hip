@@ -342,10 +342,11 @@ void ms_weights(const float* weights, int n_scales, int flags, float* w) {
 // of the pooled term written to out[frame * out_stride].
 ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, int mode,
                       float* map, int64_t map_pitch, int64_t map_bstride, float* out, int64_t out_stride,
-                      float* partial, uint32_t* sat, int tile_idx, hipStream_t st) {
+                      float* partial, uint32_t* sat, int tile_idx, hipStream_t st, float* ds_x, float* ds_y) {
   const Path path = choose_path(p, dtype);
   const float C1 = (float)p->C1, C2 = (float)p->C2;
   int err = 0, tiles = 0;
+  bool ds_done = false;
   Geom g = make_geom_path(p, dtype, W, H, tile_idx);
   if (use_fast(p, dtype)) {
     FastArgs a{};
@@ -357,7 +358,12 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
     a.map_bstride = map_bstride;
     a.partial = partial;
     a.batch = batch;
-    err = launch_fast_stats(dtype, 0, a, batch, st);
+    if (ds_x && p->padding == SSIMX_PAD_VALID && W >= 2 && H >= 2) {
+      a.ds_x = ds_x;
+      a.ds_y = ds_y;
+      ds_done = true;
+    }
+    err = launch_fast_stats(dtype, ds_done ? 2 : 0, a, batch, st);
     tiles = g.tiles_x * g.tiles_y;
   } else if (use_strided(p, dtype)) {
     FastArgs a{};
@@ -430,6 +436,10 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
     err = launch_finalize(partial, tiles, batch, g.Wo * g.Ho, 1.f, out, out_stride, st);
     if (err) return hip_status(err);
   }
+  if (ds_x && !ds_done) {
+    err = launch_downsample(dtype, x, W, H, ds_x, ds_y, y, batch, st);
+    if (err) return hip_status(err);
+  }
   return SSIMX_OK;
 }
 
@@ -476,16 +486,14 @@ ssimx_status ms_forward(const ssimx_params* p, const float* w, int n_scales, int
       y = PlaneArg{base + L.lvl_y_off[j], L.W[j], (int64_t)L.W[j] * L.H[j]};
       dt = SSIMX_F32;
     }
-    if (j + 1 < n_scales) {
-      const int err = launch_downsample(dt, x, L.W[j], L.H[j], (float*)(base + L.lvl_x_off[j + 1]),
-                                        (float*)(base + L.lvl_y_off[j + 1]), y, batch, st);
-      if (err) return hip_status(err);
-    }
     const bool sep = j + 1 == n_scales && (flags & SSIMX_MS_COARSE_SEPARATE);
     const int mode = (j + 1 < n_scales || sep) ? 1 : 0;
     const int tile = pick_tile(p, dt, L.W[j], L.H[j], batch);
+    // the next scale's planes are written by this scale's windowed pass
+    float* nx = j + 1 < n_scales ? (float*)(base + L.lvl_x_off[j + 1]) : nullptr;
+    float* ny = j + 1 < n_scales ? (float*)(base + L.lvl_y_off[j + 1]) : nullptr;
     ssimx_status s = fwd_pass(p, dt, x, y, L.W[j], L.H[j], batch, mode, nullptr, 0, 0, vals + j, n_scales,
-                              (float*)(base + L.partial_off[j]), nullptr, tile, st);
+                              (float*)(base + L.partial_off[j]), nullptr, tile, st, nx, ny);
     if (s != SSIMX_OK) return s;
     if (sep) {  // coarsest term mean(l) * mean(cs): the mean of l as well
       s = fwd_pass(p, dt, x, y, L.W[j], L.H[j], batch, 3, nullptr, 0, 0, (float*)(base + L.lvals_off), 1,
