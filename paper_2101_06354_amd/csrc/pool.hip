@@ -68,6 +68,24 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // kind: 0 sum Q | 1 sum Q, Q^2 | 2 sum |Q - mu|^p | 3 sum (1-Q)^p | 4 sum (1-Q)^p Q, (1-Q)^p
 // | 5 sum of Q below the per-frame threshold, and their count | 6 sum log Q | 7 sum 1/Q over
 // the non-zero values, and the number of zeros
+// Calls f(v) on every value of the frame rows blockIdx.x, blockIdx.x +
+// gridDim.x, ...; thread t takes columns t, t + NT, ... of a row in that order,
+// with eight loads in flight before their values are used.
+template <class F>
+__device__ __forceinline__ void for_each_value(const MapArg& a, const float* m, F& f) {
+  for (int r = blockIdx.x; r < a.h; r += gridDim.x) {
+    const float* row = m + (int64_t)r * a.pitch;
+    for (int c0 = threadIdx.x; c0 < a.w; c0 += 8 * kPoolNT) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = c0 + j * kPoolNT < a.w ? row[c0 + j * kPoolNT] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (c0 + j * kPoolNT < a.w) f(v[j]);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kPoolNT) void pool_sums_kernel(MapArg a, int kind, double p, int ip, const double* mu,
                                                             const uint32_t* thr_key, double* partial) {
   __shared__ double red[2][kPoolNT / 64];
@@ -104,18 +122,7 @@ __global__ __launch_bounds__(kPoolNT) void pool_sums_kernel(MapArg a, int kind, 
         break;
     }
   };
-  for (int r = blockIdx.x; r < a.h; r += gridDim.x) {
-    const float* row = m + (int64_t)r * a.pitch;
-    int c = threadIdx.x;
-    for (; c + 3 * kPoolNT < a.w; c += 4 * kPoolNT) {  // four loads in flight
-      const float v0 = row[c], v1 = row[c + kPoolNT], v2 = row[c + 2 * kPoolNT], v3 = row[c + 3 * kPoolNT];
-      acc(v0);
-      acc(v1);
-      acc(v2);
-      acc(v3);
-    }
-    for (; c < a.w; c += kPoolNT) acc(row[c]);
-  }
+  for_each_value(a, m, acc);
   s0 = wave_sum_d(s0);
   s1 = wave_sum_d(s1);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -250,16 +257,18 @@ __device__ __forceinline__ void flush_run(uint32_t* h, int idx, uint32_t cnt) {
 
 __global__ __launch_bounds__(kPoolNT) void sel_hist_kernel(SelArgs s, int shift) {
   __shared__ uint32_t h[kMaxTargets * 256];
-  __shared__ uint32_t uq[kMaxTargets];
-  __shared__ int nu_s;
   const int frame = blockIdx.y;
   const uint32_t* st = s.state + (int64_t)frame * kStateWords;
   for (int i = threadIdx.x; i < kMaxTargets * 256; i += kPoolNT) h[i] = 0u;
-  if (threadIdx.x < kMaxTargets) uq[threadIdx.x] = st[kUniq + threadIdx.x];
-  if (threadIdx.x == 0) nu_s = (int)st[kNUniq];
-  __syncthreads();
-  const int nu = nu_s;
   const uint32_t himask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
+  // The distinct prefixes are the same for the whole block: held in registers
+  // and matched by a fixed compare-select. Unused slots hold a word whose low
+  // (shift + 8) bits are set, which no masked key equals.
+  const int nu = (int)st[kNUniq];
+  uint32_t pm[kMaxTargets];
+#pragma unroll
+  for (int u = 0; u < kMaxTargets; ++u) pm[u] = u < nu ? (st[kUniq + u] & himask) : 0xffffffffu;
+  __syncthreads();
   const float* m = s.a.map + (int64_t)frame * s.a.bstride;
   // Neighbouring map values are strongly correlated, so runs of equal bins in
   // a thread's keys are merged before they reach the (contended) LDS bins.
@@ -267,12 +276,11 @@ __global__ __launch_bounds__(kPoolNT) void sel_hist_kernel(SelArgs s, int shift)
   uint32_t cnt = 0u;
   auto add = [&](float v) {
     const uint32_t k = ordered_key(v);
-    int idx = -1;
-    for (int u = 0; u < nu; ++u)
-      if (((k ^ uq[u]) & himask) == 0u) {
-        idx = u * 256 + (int)((k >> shift) & 255u);
-        break;
-      }
+    const uint32_t kp = k & himask;
+    int base = -1;
+#pragma unroll
+    for (int u = 0; u < kMaxTargets; ++u) base = kp == pm[u] ? u * 256 : base;
+    const int idx = base < 0 ? -1 : base + (int)((k >> shift) & 255u);
     if (idx != cur) {
       flush_run(h, cur, cnt);
       cur = idx;
@@ -280,19 +288,7 @@ __global__ __launch_bounds__(kPoolNT) void sel_hist_kernel(SelArgs s, int shift)
     }
     ++cnt;
   };
-  for (int r = blockIdx.x; r < s.a.h; r += gridDim.x) {
-    const float* row = m + (int64_t)r * s.a.pitch;
-    int c = threadIdx.x;
-    // four loads in flight, then their keys in order
-    for (; c + 3 * kPoolNT < s.a.w; c += 4 * kPoolNT) {
-      const float v0 = row[c], v1 = row[c + kPoolNT], v2 = row[c + 2 * kPoolNT], v3 = row[c + 3 * kPoolNT];
-      add(v0);
-      add(v1);
-      add(v2);
-      add(v3);
-    }
-    for (; c < s.a.w; c += kPoolNT) add(row[c]);
-  }
+  for_each_value(s.a, m, add);
   flush_run(h, cur, cnt);
   __syncthreads();
   uint32_t* g = s.hist + (int64_t)frame * kMaxTargets * 256;
