@@ -356,7 +356,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     err = (int)hipGetLastError();
     if (err) return hip_status(err);
   }
-  if (fast && valid) {
+  if (fast && valid && cpitch < kFastMaxPitch) {  // coefficient offsets: 24-bit multiplies of cpitch
     // 256-row tiles halve the share of the K - 1 prologue rows when the
     // launch still holds >= 4096 workgroups; smaller launches keep 128 rows
     fa.qtiles_x = (lv.W + 63) / 64;

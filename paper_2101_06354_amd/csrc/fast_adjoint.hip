@@ -31,8 +31,6 @@ struct AShape {
   static constexpr int CH = 16;                           // pixel rows per chunk
   static constexpr int BAND = CH + HALO;
   static constexpr int PL = BAND * kTWP;
-  static constexpr int ITEMS = CH * NQ;
-  static constexpr int PER_THREAD = (ITEMS + kNT - 1) / kNT;
   static_assert(CH >= HALO, "band copy needs CH >= K - 1");
   static_assert(IWP >= LP + kTW + K - 1, "footprint row too short");
 };
@@ -41,34 +39,51 @@ struct CQuad {
   float4 v[kNM];  // four consecutive map positions of each plane
 };
 
+// Item i of a thread in a chunk of coefficient rows: row r and quad q of the
+// footprint.  Item 0 is row t / 16, quad t % 16; item 1 covers the NQ - 16
+// quads past them, four lanes per row in the first wave.
+template <int K>
+__device__ __forceinline__ bool coef_item(int i, int& r, int& q) {
+  if (i == 0) {
+    r = threadIdx.x >> 4;
+    q = threadIdx.x & 15;
+    return true;
+  }
+  r = (threadIdx.x >> 2) & 15;
+  q = 16 + (threadIdx.x & 3);
+  return threadIdx.x < 64 && (threadIdx.x & 3) < AShape<K>::NQ - 16;
+}
+
 // Map rows r0 .. r0+nrows-1, footprint columns from c0 (a multiple of 4),
-// into registers.
+// into registers.  The rows' base is block-uniform; an interior quad adds a
+// 32-bit offset to it (the host runs this kernel only for coefficient row
+// pitches below 2^24 floats).
 template <int K>
 __device__ __forceinline__ void fetch_coef(const FastArgs& a, int frame, int r0, int c0, int nrows, CQuad* q) {
   using S = AShape<K>;
+  static_assert(S::CH == 16 && kNT == 256 && S::NQ >= 16 && S::NQ - 16 <= 4, "item layout");
   const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
   const float* base = a.coef + (int64_t)frame * a.g.Ho * a.cpitch;
+  const char* rb = (const char*)(base + (int64_t)r0 * a.cpitch);  // may point before the plane; read only in range
 #pragma unroll
-  for (int i = 0; i < S::PER_THREAD; ++i) {
-    const int it = threadIdx.x + i * kNT;
-    if (it < nrows * S::NQ) {
-      const int r = it / S::NQ, qq = it - r * S::NQ;
-      const int pr = r0 + r, pc = c0 + 4 * qq;
-      if (pr >= 0 && pr < a.g.Ho && pc >= 0 && pc + 3 < a.g.Wo) {
-        const float* src = base + (int64_t)pr * a.cpitch + pc;
+  for (int i = 0; i < 2; ++i) {
+    int r, qq;
+    if (!coef_item<K>(i, r, qq) || r >= nrows) continue;
+    const int pr = r0 + r, pc = c0 + 4 * qq;
+    if (pr >= 0 && pr < a.g.Ho && pc >= 0 && pc + 3 < a.g.Wo) {
+      const uint32_t off = 4u * (__umul24((uint32_t)r, (uint32_t)a.cpitch) + (uint32_t)pc);
 #pragma unroll
-        for (int m = 0; m < kNM; ++m) q[i].v[m] = *(const float4*)(src + m * qs);
-      } else {
+      for (int m = 0; m < kNM; ++m) q[i].v[m] = *(const float4*)(rb + 4 * m * qs + off);
+    } else {
 #pragma unroll
-        for (int m = 0; m < kNM; ++m) {
-          float e[4];
+      for (int m = 0; m < kNM; ++m) {
+        float e[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const bool in = pr >= 0 && pr < a.g.Ho && pc + k >= 0 && pc + k < a.g.Wo;
-            e[k] = in ? base[m * qs + (int64_t)pr * a.cpitch + pc + k] : 0.f;
-          }
-          q[i].v[m] = make_float4(e[0], e[1], e[2], e[3]);
+        for (int k = 0; k < 4; ++k) {
+          const bool in = pr >= 0 && pr < a.g.Ho && pc + k >= 0 && pc + k < a.g.Wo;
+          e[k] = in ? base[m * qs + (int64_t)pr * a.cpitch + pc + k] : 0.f;
         }
+        q[i].v[m] = make_float4(e[0], e[1], e[2], e[3]);
       }
     }
   }
@@ -77,14 +92,18 @@ __device__ __forceinline__ void fetch_coef(const FastArgs& a, int frame, int r0,
 // Pixel quads of the chunk's rows (the 64 output columns of the tile), one
 // quad per thread and plane, held in registers until the chunk is staged
 // (valid borders: pixels outside the plane read as zero and are not used).
+// Vector loads add a 32-bit offset to the block-uniform row base of the
+// chunk (vec_ok implies row pitches below 2^24 elements).
 template <typename T>
-__device__ __forceinline__ void fetch_quad_valid(const T* P, int64_t pitch, int W, int H, int vec_ok, int py, int px,
-                                                 fast::Quad<T>& q) {
+__device__ __forceinline__ void fetch_quad_valid(const T* P, int64_t pitch, int W, int H, int vec_ok, int py0, int r,
+                                                 int px, fast::Quad<T>& q) {
 #pragma unroll
   for (int i = 0; i < fast::Quad<T>::NW; ++i) q.w[i] = 0u;
+  const int py = py0 + r;
   if (py >= H) return;
-  const T* s = P + (int64_t)py * pitch + px;
   if (vec_ok && px + 3 < W) {
+    const char* s = (const char*)(P + (int64_t)py0 * pitch) +
+                    (__umul24((uint32_t)r, (uint32_t)pitch) + (uint32_t)px) * (uint32_t)sizeof(T);
     if constexpr (sizeof(T) == 1) {
       q.w[0] = *(const uint32_t*)s;
     } else if constexpr (sizeof(T) == 2) {
@@ -100,6 +119,7 @@ __device__ __forceinline__ void fetch_quad_valid(const T* P, int64_t pitch, int 
     }
     return;
   }
+  const T* s = P + (int64_t)py * pitch + px;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     if (px + e >= W) break;
@@ -114,8 +134,8 @@ template <typename T>
 __device__ __forceinline__ void fetch_xy(const FastArgs& a, const T* X, const T* Y, int py0, int px0,
                                          fast::Quad<T>& qx, fast::Quad<T>& qy) {
   const int r = threadIdx.x >> 4, q = threadIdx.x & 15;  // 16 rows x 16 quads
-  fetch_quad_valid<T>(X, a.x.pitch, a.g.W, a.g.H, a.vec_ok, py0 + r, px0 + 4 * q, qx);
-  fetch_quad_valid<T>(Y, a.y.pitch, a.g.W, a.g.H, a.vec_ok, py0 + r, px0 + 4 * q, qy);
+  fetch_quad_valid<T>(X, a.x.pitch, a.g.W, a.g.H, a.vec_ok, py0, r, px0 + 4 * q, qx);
+  fetch_quad_valid<T>(Y, a.y.pitch, a.g.W, a.g.H, a.vec_ok, py0, r, px0 + 4 * q, qy);
 }
 
 // Registers -> the LDS planes C[m][r][col].
@@ -124,14 +144,12 @@ __device__ __forceinline__ void store_coef(const CQuad* q, int nrows, float* C) 
   using S = AShape<K>;
   constexpr int PLC = S::CH * S::IWP;
 #pragma unroll
-  for (int i = 0; i < S::PER_THREAD; ++i) {
-    const int it = threadIdx.x + i * kNT;
-    if (it < nrows * S::NQ) {
-      const int r = it / S::NQ, qq = it - r * S::NQ;
-      float* d = C + r * S::IWP + 4 * qq;
+  for (int i = 0; i < 2; ++i) {
+    int r, qq;
+    if (!coef_item<K>(i, r, qq) || r >= nrows) continue;
+    float* d = C + r * S::IWP + 4 * qq;
 #pragma unroll
-      for (int m = 0; m < kNM; ++m) *(float4*)&d[m * PLC] = q[i].v[m];
-    }
+    for (int m = 0; m < kNM; ++m) *(float4*)&d[m * PLC] = q[i].v[m];
   }
 }
 
@@ -195,7 +213,7 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   const T* Y = (const T*)a.y.data + (int64_t)frame * a.y.bstride;
 
   // pixel row y reads map rows y-K+1 .. y; prologue = the first K-1 of them
-  CQuad q[S::PER_THREAD];
+  CQuad q[2];
   fetch_coef<K>(a, frame, qy0 - S::HALO, c0, S::HALO, q);
   store_coef<K>(q, S::HALO, C);
   __syncthreads();
@@ -221,8 +239,11 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
     __syncthreads();
     coef_row_pass<K>(taps, C, S::CH, HM, S::HALO);
     __syncthreads();
-    for (int it = threadIdx.x; it < (S::CH / 4) * kTW; it += kNT) {
-      const int gr = it / kTW, c = it - gr * kTW;
+    // item = (4 pixel rows, 1 column), one per thread; wave w takes rows
+    // cy + 4 w .. cy + 4 w + 3, so every output row base is wave-uniform
+    static_assert((S::CH / 4) * kTW == kNT, "one column-pass item per thread, one row group per wave");
+    {
+      const int gr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
       const int px = qx0 + c;
       float G[kNM][4];
 #pragma unroll
@@ -243,13 +264,12 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
           }
         }
       }
-      if (px >= a.g.W) continue;
       const T* xs = (const T*)XY[0];
       const T* ys = (const T*)XY[1];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int py = cy + 4 * gr + j;
-        if (py >= qy_end) continue;
+        const int py = cy + 4 * gr + j;  // wave-uniform
+        if (py >= qy_end || px >= a.g.W) continue;
         // staged row 4 gr + j, column c (quads are stored row-major, 16 per row)
         const float xv = to_f32<T>(xs[(4 * gr + j) * kTW + c]);
         const float yv = to_f32<T>(ys[(4 * gr + j) * kTW + c]);
@@ -257,9 +277,13 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
         float gy = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]) - ((xv - yv) - a.tv) * G[2][j];
         if (a.coarse) {
           const int cyy = py >> 1, cxx = px >> 1;
-          if (cyy < a.Hc && cxx < a.Wc) gy += 0.25f * a.coarse[((int64_t)frame * a.Hc + cyy) * a.Wc + cxx];
+          if (cyy < a.Hc && cxx < a.Wc) {
+            const char* crow = (const char*)(a.coarse + ((int64_t)frame * a.Hc + cyy) * a.Wc);
+            gy += 0.25f * *(const float*)(crow + 4u * (uint32_t)cxx);
+          }
         }
-        a.out[(int64_t)frame * a.out_bstride + (int64_t)py * a.out_pitch + px] = gy;
+        char* orow = (char*)(a.out + (int64_t)frame * a.out_bstride + (int64_t)py * a.out_pitch);
+        *(float*)(orow + 4u * (uint32_t)px) = gy;
       }
     }
     __syncthreads();

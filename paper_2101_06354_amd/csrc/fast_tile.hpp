@@ -11,12 +11,16 @@ struct Rgb8 {
   uint8_t v;
 };
 
+// Row pitches (elements) below which interior quads are loaded as vectors at
+// 32-bit offsets from a chunk's row base (24-bit multiplies of the pitch).
+constexpr int64_t kFastMaxPitch = int64_t(1) << 24;
+
 struct FastArgs {
   PlaneArg x, y;
   Geom g;            // TW fixed at 64; TH = output rows per tile (multiple of 16)
   float C1, C2;
   int mode;          // 0: Q = l*cs, 1: cs, 3: l (forward) / g_l l + g_cs cs (coefficients)
-  int vec_ok;        // 4-element vector loads allowed for interior footprint rows
+  int vec_ok;        // 4-element vector loads allowed for interior footprint rows (aligned, pitch < kFastMaxPitch)
   int64_t cstride;   // Rgb8 sources: elements between the R, G and B planes
   // forward epilogue
   float* map;

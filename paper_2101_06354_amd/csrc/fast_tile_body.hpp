@@ -236,29 +236,82 @@ __device__ __forceinline__ void stage_rows(const FastArgs& a, const T* X, const 
 
 // Chunk staging split in two halves: fetch_chunk issues the global loads of
 // kCH footprint rows into registers, store_chunk converts them to u, v and
-// writes LDS.
+// writes LDS.  A thread's items are fixed for the whole tile: item 0 is row
+// t / 16, quad t % 16 (the 16 quads of the tile's 64 columns, 16 lanes per
+// row); item 1 covers the NQ - 16 quads past them, four lanes per row in the
+// first wave.  Only the row base of a chunk changes; it is block-uniform, so
+// a vector load adds a 32-bit in-chunk offset to a scalar base (the host
+// allows vector loads only for row pitches below 2^24 elements, so 16 rows of
+// any element type stay below 2^32 bytes).
 template <int K>
 struct ChunkItems {
-  static constexpr int N = kCH * Shape<K>::NQ;
-  static constexpr int PER_THREAD = (N + kNT - 1) / kNT;
+  static constexpr int NQ = Shape<K>::NQ;
+  static constexpr int PER_THREAD = 2;
+  static_assert(kCH == 16 && kNT == 256 && NQ >= 16 && NQ - 16 <= 4, "item layout");
 };
+
+template <int K>
+__device__ __forceinline__ bool chunk_item(int i, int& r, int& q) {
+  if (i == 0) {
+    r = threadIdx.x >> 4;
+    q = threadIdx.x & 15;
+    return true;
+  }
+  r = (threadIdx.x >> 2) & 15;
+  q = 16 + (threadIdx.x & 3);
+  return threadIdx.x < 64 && (threadIdx.x & 3) < ChunkItems<K>::NQ - 16;
+}
 
 template <int K, typename T>
 __device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const T* Y, int py0, int px0, Quad<T>* qx,
                                             Quad<T>* qy) {
-  using S = Shape<K>;
+  const bool vec = a.vec_ok && a.g.pad == SSIMX_PAD_VALID;
+  // block-uniform row bases of the chunk
+  const char* xr = (const char*)(X + (int64_t)py0 * a.x.pitch);
+  const char* yr = (const char*)(Y + (int64_t)py0 * a.y.pitch);
+  constexpr uint32_t ES = is_rgb<T>() ? 1u : (uint32_t)sizeof(T);
 #pragma unroll
   for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
-    const int it = threadIdx.x + i * kNT;
-    if (it < ChunkItems<K>::N) {
-      const int r = it / S::NQ, q = it - r * S::NQ;
+    int r, q;
+    if (!chunk_item<K>(i, r, q)) continue;
+    const int px = px0 + 4 * q;
+    if (vec && py0 + r < a.g.H && px + 3 < a.g.W) {
+      const uint32_t xo = (__umul24((uint32_t)r, (uint32_t)a.x.pitch) + (uint32_t)px) * ES;
+      const uint32_t yo = (__umul24((uint32_t)r, (uint32_t)a.y.pitch) + (uint32_t)px) * ES;
       if constexpr (is_rgb<T>()) {
-        fetch4_rgb((const uint8_t*)X, a.x.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qx[i]);
-        fetch4_rgb((const uint8_t*)Y, a.y.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qy[i]);
+        const int64_t cs = a.cstride;
+        qx[i].w[0] = *(const uint32_t*)(xr + xo);
+        qx[i].w[1] = *(const uint32_t*)(xr + cs + xo);
+        qx[i].w[2] = *(const uint32_t*)(xr + 2 * cs + xo);
+        qy[i].w[0] = *(const uint32_t*)(yr + yo);
+        qy[i].w[1] = *(const uint32_t*)(yr + cs + yo);
+        qy[i].w[2] = *(const uint32_t*)(yr + 2 * cs + yo);
+      } else if constexpr (sizeof(T) == 1) {
+        qx[i].w[0] = *(const uint32_t*)(xr + xo);
+        qy[i].w[0] = *(const uint32_t*)(yr + yo);
+      } else if constexpr (sizeof(T) == 2) {
+        const uint2 vx = *(const uint2*)(xr + xo), vy = *(const uint2*)(yr + yo);
+        qx[i].w[0] = vx.x;
+        qx[i].w[1] = vx.y;
+        qy[i].w[0] = vy.x;
+        qy[i].w[1] = vy.y;
       } else {
-        fetch4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qx[i]);
-        fetch4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qy[i]);
+        const uint4 vx = *(const uint4*)(xr + xo), vy = *(const uint4*)(yr + yo);
+        qx[i].w[0] = vx.x;
+        qx[i].w[1] = vx.y;
+        qx[i].w[2] = vx.z;
+        qx[i].w[3] = vx.w;
+        qy[i].w[0] = vy.x;
+        qy[i].w[1] = vy.y;
+        qy[i].w[2] = vy.z;
+        qy[i].w[3] = vy.w;
       }
+    } else if constexpr (is_rgb<T>()) {
+      fetch4_rgb((const uint8_t*)X, a.x.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px, qx[i]);
+      fetch4_rgb((const uint8_t*)Y, a.y.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px, qy[i]);
+    } else {
+      fetch4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px, qx[i]);
+      fetch4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px, qy[i]);
     }
   }
 }
@@ -268,20 +321,18 @@ __device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy
   using S = Shape<K>;
 #pragma unroll
   for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
-    const int it = threadIdx.x + i * kNT;
-    if (it < ChunkItems<K>::N) {
-      const int r = it / S::NQ, q = it - r * S::NQ;
-      float xv[4], yv[4];
-      if constexpr (is_rgb<T>()) {
-        unpack4_rgb(qx[i], ch, xv);
-        unpack4_rgb(qy[i], ch, yv);
-      } else {
-        unpack4<T>(qx[i], xv);
-        unpack4<T>(qy[i], yv);
-      }
-      *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
-      *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
+    int r, q;
+    if (!chunk_item<K>(i, r, q)) continue;
+    float xv[4], yv[4];
+    if constexpr (is_rgb<T>()) {
+      unpack4_rgb(qx[i], ch, xv);
+      unpack4_rgb(qy[i], ch, yv);
+    } else {
+      unpack4<T>(qx[i], xv);
+      unpack4<T>(qy[i], yv);
     }
+    *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
+    *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
   }
 }
 
@@ -436,10 +487,15 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
     }
     row_pass<K>(taps, U, V, kCH, HM, S::HALO);
     __syncthreads();
-    // column pass: item = (4 output rows, 1 column)
-    for (int it = threadIdx.x; it < (kCH / 4) * kTW; it += kNT) {
-      const int gr = it / kTW, c = it - gr * kTW;
+    // column pass: item = (4 output rows, 1 column); the block's 256 items
+    // are one per thread, wave w taking output rows cy + 4 w .. cy + 4 w + 3,
+    // so the row base of every store is wave-uniform and a store only adds
+    // the lane's column
+    static_assert((kCH / 4) * kTW == kNT && kTW == 64, "one column-pass item per thread, one row group per wave");
+    {
+      const int gr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
       const int oj = ox0 + c;
+      const uint32_t cb = 4u * (uint32_t)oj;  // byte offset of the lane's column in a float row
       const float* hu_ = HM + 4 * gr * kTWP + c;
       const float Tu = hu_[S::SHIFT * kTWP], Tv = hu_[PL + S::SHIFT * kTWP];
       float Mu[4] = {0.f, 0.f, 0.f, 0.f}, Mv[4] = {0.f, 0.f, 0.f, 0.f};
@@ -463,18 +519,24 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int oi = cy + 4 * gr + j;
+        const int oi = cy + 4 * gr + j;  // wave-uniform
         if (oi >= oy_end || oj >= a.g.Wo) continue;
         const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
         const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
         const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
         if constexpr (EPI != 1) {
           const float val = ssim_value(t, a.mode);
-          if (a.map) a.map[(int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + oj] = val;
+          if (a.map) {
+            char* row = (char*)(a.map + (int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch);
+            *(float*)(row + cb) = val;
+          }
           acc += val;
         } else {
-          const float g = a.grad_map ? a.grad_map[(int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch + oj]
-                                     : gframe;
+          float g = gframe;
+          if (a.grad_map) {
+            const char* row = (const char*)(a.grad_map + (int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch);
+            g = *(const float*)(row + cb);
+          }
           // reciprocal estimates (about 1 ulp) suffice for the adjoint
           const float ib2 = __builtin_amdgcn_rcpf(t.B2);
           const float dcs_du = 0.5f * var_v * ib2 * ib2;
@@ -498,11 +560,11 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
             bv = fc * dcs_dv;
           }
           // W^T is linear: the two A maps are combined before the transpose
-          const int64_t o = ((int64_t)frame * a.g.Ho + oi) * a.cpitch + oj;
           const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
-          a.coef[o] = gg * ((au - 2.f * bu * (mean_u - a.tu)) - (av - 2.f * bv * (mean_v - a.tv)));
-          a.coef[qs + o] = 2.f * gg * bu;
-          a.coef[2 * qs + o] = 2.f * gg * bv;
+          char* row = (char*)(a.coef + ((int64_t)frame * a.g.Ho + oi) * a.cpitch);
+          *(float*)(row + cb) = gg * ((au - 2.f * bu * (mean_u - a.tu)) - (av - 2.f * bv * (mean_v - a.tv)));
+          *(float*)(row + 4 * qs + cb) = 2.f * gg * bu;
+          *(float*)(row + 8 * qs + cb) = 2.f * gg * bv;
         }
       }
     }

@@ -187,8 +187,11 @@ void fill_fast_common(FastArgs& a, const ssimx_params* p, int dtype, PlaneArg x,
   a.g = g;
   a.C1 = (float)p->C1;
   a.C2 = (float)p->C2;
+  // vector loads of interior quads form their in-chunk offsets with 24-bit
+  // multiplies of the row pitch; wider pitches take the element-wise loads
   a.vec_ok = aligned_vec(x.data, x.pitch, x.bstride, dtype_size(dtype)) &&
-             aligned_vec(y.data, y.pitch, y.bstride, dtype_size(dtype));
+             aligned_vec(y.data, y.pitch, y.bstride, dtype_size(dtype)) && x.pitch < kFastMaxPitch &&
+             y.pitch < kFastMaxPitch;
   gaussian_taps_f32(p->window, p->k, p->sigma, a.taps);
 }
 

@@ -208,3 +208,25 @@ def test_msssim_coarse_separate_backward(P, dev, window, k, n_scales):
         gref = O.msssim_backward(x[f], y[f], gs, oparams(cfg), weights=w, n_scales=n_scales, renorm=True,
                                  coarse_separate=True)
         _cmp(g[f], gref, f"frame {f}")
+
+
+def test_backward_row_pitch_beyond_vector_offsets(P, dev):
+    """Inputs whose rows lie 2^24 + 64 elements apart take the element-wise
+    loads in both backward kernels: the gradient equals the one of the same
+    frames stored densely."""
+    x, y = synth.config1(frames=1, h=40, w=150)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    cfg = P.SSIMConfig()
+    up = torch.tensor([1.0], device=dev)
+    g = P.ssim_backward(xt, yt, up, cfg)
+    pitch = (1 << 24) + 64
+    bx = torch.zeros((40 * pitch,), dtype=torch.uint8, device=dev)
+    by = torch.zeros_like(bx)
+    vx = bx.as_strided((1, 40, 150), (40 * pitch, pitch, 1))
+    vy = by.as_strided((1, 40, 150), (40 * pitch, pitch, 1))
+    vx.copy_(xt)
+    vy.copy_(yt)
+    g2 = P.ssim_backward(vx, vy, up, cfg)
+    assert torch.equal(g2, g)
+    _cmp(g2[0].cpu().numpy(), O.ssim_pooled_backward(x[0], y[0], 1.0, oparams(cfg)), "wide pitch")
+    del bx, by, vx, vy

@@ -264,6 +264,28 @@ def test_tile_configs_agree_and_unaligned_planes(P, dev):
         assert np.abs(maps[0][f].cpu().numpy() - ref).max() <= MAP_TOL
 
 
+def test_row_pitch_beyond_vector_offsets(P, dev):
+    """Rows 2^24 + 64 elements apart (beyond the 32-bit in-chunk offsets of
+    the vector loads) take the element-wise loads: the map equals the one of
+    the same frames stored densely, and the oracle's."""
+    x, y = synth.config1(frames=1, h=24, w=150)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    cfg = P.SSIMConfig()
+    s, m = P.ssim(xt, yt, cfg, return_map=True)
+    pitch = (1 << 24) + 64
+    bx = torch.zeros((24 * pitch,), dtype=torch.uint8, device=dev)
+    by = torch.zeros_like(bx)
+    vx = bx.as_strided((1, 24, 150), (24 * pitch, pitch, 1))
+    vy = by.as_strided((1, 24, 150), (24 * pitch, pitch, 1))
+    vx.copy_(xt)
+    vy.copy_(yt)
+    s2, m2 = P.ssim(vx, vy, cfg, return_map=True)
+    assert torch.equal(m2, m) and torch.equal(s2, s)
+    ref = O.ssim_map(x[0], y[0], oparams(cfg))["map"]
+    assert np.abs(m2[0].cpu().numpy() - ref).max() <= MAP_TOL
+    del bx, by, vx, vy
+
+
 @pytest.mark.parametrize("dtype", ["u16", "f32", "bf16"])
 def test_band_kernel_other_dtypes(P, dev, dtype):
     if dtype == "u16":
