@@ -70,9 +70,10 @@ struct VolShape {
 template <typename T, typename Acc>
 using Raw = typename std::conditional<std::is_same<Acc, uint32_t>::value, uint32_t, float>::type;
 
+// Element `off` of a frame whose base is `fb` (block-uniform).
 template <typename T, typename Acc>
-__device__ __forceinline__ Raw<T, Acc> vol_load(const PlaneArg& a, int f, int r, int c) {
-  const T* p = (const T*)a.data + (int64_t)f * a.bstride + (int64_t)r * a.pitch + c;
+__device__ __forceinline__ Raw<T, Acc> vol_load(const T* fb, int64_t off) {
+  const T* p = fb + off;
   if constexpr (std::is_same<Acc, uint32_t>::value)
     return (uint32_t)*p;
   else
@@ -82,6 +83,17 @@ __device__ __forceinline__ Raw<T, Acc> vol_load(const PlaneArg& a, int f, int r,
 template <typename Acc, typename R>
 __device__ __forceinline__ Acc widen(R v) {
   return (Acc)v;
+}
+
+// Product of two samples in the accumulation type.  Integer sums take
+// samples below 2^24 whose products stay below 2^32 (8-bit values and sums of
+// four of them), so the full-rate 24-bit multiply is exact.
+template <typename Acc>
+__device__ __forceinline__ Acc sprod(Acc a, Acc b) {
+  if constexpr (std::is_same<Acc, uint32_t>::value)
+    return __umul24(a, b);
+  else
+    return a * b;
 }
 
 // SSIM terms from the five box sums (as float64 values, exact for 8-bit clips).
@@ -125,15 +137,20 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
   const int npx = IW * IH;
   const int tid = threadIdx.x;
 
-  // footprint pixels owned by this thread: p = tid + i * NT
+  // footprint pixels owned by this thread: p = tid + i * NT, and their
+  // element offsets within a frame (fixed for the tile: a frame's loads only
+  // change the block-uniform frame base)
   int pr[S::PPT], pc[S::PPT];
   bool pin[S::PPT];
+  int64_t xoff[S::PPT], yoff[S::PPT];
 #pragma unroll
   for (int i = 0; i < S::PPT; ++i) {
     const int p = tid + i * kVolNT;
     pr[i] = p / IW;
     pc[i] = p - pr[i] * IW;
     pin[i] = p < npx && row0 + pr[i] < a.H && col0 + pc[i] < a.W;
+    xoff[i] = (int64_t)(row0 + pr[i]) * a.x.pitch + col0 + pc[i];
+    yoff[i] = (int64_t)(row0 + pr[i]) * a.y.pitch + col0 + pc[i];
   }
 
   Acc st[S::PPT][5];
@@ -144,13 +161,15 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
 
   RawT nx[S::PPT], ny[S::PPT], ox[S::PPT], oy[S::PPT];
   auto fetch = [&](int f, RawT* vx, RawT* vy) {
+    const T* fx = (const T*)a.x.data + (int64_t)f * a.x.bstride;
+    const T* fy = (const T*)a.y.data + (int64_t)f * a.y.bstride;
 #pragma unroll
     for (int i = 0; i < S::PPT; ++i) {
       vx[i] = (RawT)0;
       vy[i] = (RawT)0;
       if (pin[i]) {
-        vx[i] = vol_load<T, Acc>(a.x, f, row0 + pr[i], col0 + pc[i]);
-        vy[i] = vol_load<T, Acc>(a.y, f, row0 + pr[i], col0 + pc[i]);
+        vx[i] = vol_load<T, Acc>(fx, xoff[i]);
+        vy[i] = vol_load<T, Acc>(fy, yoff[i]);
       }
     }
   };
@@ -165,16 +184,16 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
       const Acc xn = widen<Acc>(nx[i]), yn = widen<Acc>(ny[i]);
       st[i][0] += xn;
       st[i][1] += yn;
-      st[i][2] += xn * xn;
-      st[i][3] += yn * yn;
-      st[i][4] += xn * yn;
+      st[i][2] += sprod(xn, xn);
+      st[i][3] += sprod(yn, yn);
+      st[i][4] += sprod(xn, yn);
       if (drop) {
         const Acc xo = widen<Acc>(ox[i]), yo = widen<Acc>(oy[i]);
         st[i][0] -= xo;
         st[i][1] -= yo;
-        st[i][2] -= xo * xo;
-        st[i][3] -= yo * yo;
-        st[i][4] -= xo * yo;
+        st[i][2] -= sprod(xo, xo);
+        st[i][3] -= sprod(yo, yo);
+        st[i][4] -= sprod(xo, yo);
       }
     }
     // prefetch the next entering and leaving frames
@@ -220,7 +239,7 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
     // k-tall running sums down the columns and the epilogue: task = (column, 4 rows)
     const int t = f - f_first_out + t0;  // map frame
     float part = 0.f;
-    const int j = tid % kVolOW, g = tid / kVolOW;
+    const int j = tid % kVolOW, g = __builtin_amdgcn_readfirstlane(tid / kVolOW);  // g: wave-uniform
     if (g < OH / G) {
       Acc acc[G][5];
 #pragma unroll
@@ -244,7 +263,10 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
         if (oi < a.Ho && oj < a.Wo) {
           const float v = vol_value((double)acc[i][0], (double)acc[i][1], (double)acc[i][2], (double)acc[i][3],
                                     (double)acc[i][4], a.N, a.invN2, a.C1, a.C2, a.mode);
-          if (a.map) a.map[(int64_t)t * a.map_fstride + (int64_t)oi * a.map_pitch + oj] = v;
+          if (a.map) {
+            char* row = (char*)(a.map + (int64_t)t * a.map_fstride + (int64_t)oi * a.map_pitch);  // wave-uniform
+            *(float*)(row + 4u * (uint32_t)oj) = v;
+          }
           part += v;
         }
       }
