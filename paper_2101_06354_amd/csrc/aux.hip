@@ -95,8 +95,31 @@ int launch_downsample(int dtype, PlaneArg in, int W, int H, float* outx, float* 
 
 // f x f block means (pre-scaling by an integer factor; remainders dropped),
 // float32 [batch][H/f][W/f].  The block sum is exact for integer planes and is
-// divided once (correctly rounded mean).
-template <typename T>
+// divided once (correctly rounded mean).  One thread per output, its block
+// summed row by row.  Factors 2..9 (the pre-scaling factors of frames up to
+// 2304 rows) are compile-time constants, so all f * f loads of a block are in
+// flight together; other factors take the runtime loop, in the same order.
+template <typename T, int F>
+__device__ __forceinline__ float block_sum(const T* P, int64_t pitch, int f) {
+  float s = 0.f;
+  if constexpr (F > 0) {
+    float v[F][F];
+#pragma unroll
+    for (int i = 0; i < F; ++i)
+#pragma unroll
+      for (int j = 0; j < F; ++j) v[i][j] = to_f32<T>(P[(int64_t)i * pitch + j]);
+#pragma unroll
+    for (int i = 0; i < F; ++i)
+#pragma unroll
+      for (int j = 0; j < F; ++j) s += v[i][j];
+  } else {
+    for (int i = 0; i < f; ++i)
+      for (int j = 0; j < f; ++j) s += to_f32<T>(P[(int64_t)i * pitch + j]);
+  }
+  return s;
+}
+
+template <typename T, int F>
 __global__ __launch_bounds__(BLOCK) void downsample_f_kernel(PlaneArg xa, PlaneArg ya, int Wf, int Hf, int f,
                                                              float* ox, float* oy) {
   const int idx = blockIdx.x * BLOCK + threadIdx.x;
@@ -105,38 +128,47 @@ __global__ __launch_bounds__(BLOCK) void downsample_f_kernel(PlaneArg xa, PlaneA
   const int r = idx / Wf, c = idx - r * Wf;
   const int64_t o = (int64_t)frame * Wf * Hf + idx;
   const float ff = (float)(f * f);
-  for (int which = 0; which < 2; ++which) {
-    const PlaneArg& pa = which ? ya : xa;
-    const T* P = (const T*)pa.data + (int64_t)frame * pa.bstride + (int64_t)(f * r) * pa.pitch + f * c;
-    float s = 0.f;
-    for (int i = 0; i < f; ++i)
-      for (int j = 0; j < f; ++j) s += to_f32<T>(P[(int64_t)i * pa.pitch + j]);
-    (which ? oy : ox)[o] = s / ff;
+  const T* PX = (const T*)xa.data + (int64_t)frame * xa.bstride + (int64_t)(f * r) * xa.pitch + (int64_t)f * c;
+  const T* PY = (const T*)ya.data + (int64_t)frame * ya.bstride + (int64_t)(f * r) * ya.pitch + (int64_t)f * c;
+  ox[o] = block_sum<T, F>(PX, xa.pitch, f) / ff;
+  oy[o] = block_sum<T, F>(PY, ya.pitch, f) / ff;
+}
+
+template <typename T>
+int launch_downsample_f_t(PlaneArg x, PlaneArg y, int Wf, int Hf, int f, float* outx, float* outy, int batch,
+                          hipStream_t st) {
+  const dim3 grid((Wf * Hf + BLOCK - 1) / BLOCK, batch);
+#define SSIMX_DSF(FF)                                                                                              \
+  case FF:                                                                                                         \
+    hipLaunchKernelGGL((downsample_f_kernel<T, FF>), grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);       \
+    break;
+  switch (f) {
+    SSIMX_DSF(2)
+    SSIMX_DSF(3)
+    SSIMX_DSF(4)
+    SSIMX_DSF(5)
+    SSIMX_DSF(6)
+    SSIMX_DSF(7)
+    SSIMX_DSF(8)
+    SSIMX_DSF(9)
+    default:
+      hipLaunchKernelGGL((downsample_f_kernel<T, 0>), grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
   }
+#undef SSIMX_DSF
+  return (int)hipGetLastError();
 }
 
 int launch_downsample_f(int dtype, PlaneArg x, PlaneArg y, int W, int H, int f, float* outx, float* outy, int batch,
                         hipStream_t st) {
   const int Wf = W / f, Hf = H / f;
   if (f < 1 || Wf < 1 || Hf < 1) return (int)hipErrorInvalidValue;
-  dim3 grid((Wf * Hf + BLOCK - 1) / BLOCK, batch);
   switch (dtype) {
-    case SSIMX_U8:
-      hipLaunchKernelGGL(downsample_f_kernel<uint8_t>, grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
-      break;
-    case SSIMX_U16:
-      hipLaunchKernelGGL(downsample_f_kernel<uint16_t>, grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
-      break;
-    case SSIMX_F32:
-      hipLaunchKernelGGL(downsample_f_kernel<float>, grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
-      break;
-    case SSIMX_BF16:
-      hipLaunchKernelGGL(downsample_f_kernel<bf16_t>, grid, dim3(BLOCK), 0, st, x, y, Wf, Hf, f, outx, outy);
-      break;
-    default:
-      return (int)hipErrorInvalidValue;
+    case SSIMX_U8: return launch_downsample_f_t<uint8_t>(x, y, Wf, Hf, f, outx, outy, batch, st);
+    case SSIMX_U16: return launch_downsample_f_t<uint16_t>(x, y, Wf, Hf, f, outx, outy, batch, st);
+    case SSIMX_F32: return launch_downsample_f_t<float>(x, y, Wf, Hf, f, outx, outy, batch, st);
+    case SSIMX_BF16: return launch_downsample_f_t<bf16_t>(x, y, Wf, Hf, f, outx, outy, batch, st);
+    default: return (int)hipErrorInvalidValue;
   }
-  return (int)hipGetLastError();
 }
 
 struct MsWeights {

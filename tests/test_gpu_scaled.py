@@ -55,3 +55,15 @@ def test_scaled_pooled_u16_and_float_planes(P, dev):
     cfg = P.SSIMConfig(L=1.0)
     got = float(P.scaled_pooled_ssim(to_dev(r[0, 1], dev), to_dev(d[0, 1], dev), cfg, factor=3, pool="mean")[0])
     assert abs(got - O.scaled_pooled_ssim(r[0, 1], d[0, 1], oparams(cfg), 3, "mean")) <= SCORE_TOL
+
+
+@pytest.mark.parametrize("factor", [64, 65])
+def test_scaled_pooled_large_factors(P, dev, factor):
+    """The largest factor taken through the LDS column sums and the first one
+    above it (one thread per block mean): 12 x 12 means of a 780 x 790 frame."""
+    x, y = synth.config1(frames=2, h=780, w=790)
+    cfg = P.SSIMConfig(window="box", k=8, stride=1)
+    got = P.scaled_pooled_ssim(to_dev(x, dev), to_dev(y, dev), cfg, factor=factor, pool="mean").cpu().numpy()
+    for f in range(2):
+        want = O.scaled_pooled_ssim(x[f], y[f], oparams(cfg), factor, "mean", 0.0)
+        assert abs(got[f] - want) <= SCORE_TOL * max(1.0, abs(want)), (f, got[f], want)
