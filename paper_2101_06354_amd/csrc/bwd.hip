@@ -305,7 +305,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
   int err = 0;
   FastArgs fa{};
   if (fast) {
-    fill_fast_common(fa, &pf, lv.dtype, lv.x, lv.y, fast_geom(&pf, lv.W, lv.H, 0));
+    fill_fast_common(fa, &pf, lv.dtype, lv.x, lv.y, fast_geom(&pf, lv.W, lv.H, 0, batch));
     fa.mode = mode;
     fa.grad_map = grad_map;
     fa.gm_pitch = gm_pitch;
@@ -358,9 +358,11 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
   }
   if (fast && valid && cpitch < kFastMaxPitch) {  // coefficient offsets: 24-bit multiplies of cpitch
     // 256-row tiles halve the share of the K - 1 prologue rows when the
-    // launch still holds >= 4096 workgroups; smaller launches keep 128 rows
+    // launch still holds >= 4096 workgroups; smaller launches take 128 rows,
+    // halved down to 32 while they would hold fewer than 1024 workgroups
     fa.qtiles_x = (lv.W + 63) / 64;
     fa.QH = (int64_t)fa.qtiles_x * ((lv.H + 255) / 256) * batch >= 4096 ? 256 : 128;
+    while (fa.QH > 32 && (int64_t)fa.qtiles_x * ((lv.H + fa.QH - 1) / fa.QH) * batch < 1024) fa.QH /= 2;
     fa.qtiles_y = (lv.H + fa.QH - 1) / fa.QH;
     fa.out = out;
     fa.out_pitch = out_pitch;

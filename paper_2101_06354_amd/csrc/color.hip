@@ -119,7 +119,7 @@ ssimx_status ssimx_color_ssim(const ssimx_params* p, double alpha, double beta, 
   float* scores = (float*)(base + L.scores_off);
   if (dtype == SSIMX_U8 && use_fast(p, SSIMX_F32)) {
     const int tile = pick_tile(p, SSIMX_F32, w, h, 3 * batch);
-    const Geom g = fast_geom(p, w, h, tile);
+    const Geom g = fast_geom(p, w, h, tile, 3 * batch);
     FastArgs a{};
     fill_fast_common(a, p, SSIMX_U8, PlaneArg{ref_rgb, pitch, batch_stride}, PlaneArg{dis_rgb, pitch, batch_stride},
                      g);

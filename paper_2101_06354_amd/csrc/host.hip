@@ -117,10 +117,32 @@ bool aligned_vec(const void* p, int64_t pitch, int64_t bstride, int esize) {
 
 int dtype_size(int dtype) { return dtype == SSIMX_U8 ? 1 : dtype == SSIMX_F32 ? 4 : 2; }
 
-Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx) {
-  Geom g = geom_with(p, W, H, 64, 16 * fast_chunks(tile_idx));
+// Rows per tile of the default tile index for a launch of `batch` frames:
+// halved, down to `min_rows` (a height of the tile tables, which the partial
+// buffers are sized for), while the launch would hold fewer than kFillBlocks
+// workgroups, so that single frames and small batches spread over all CUs.
+// For the box band and strided kernels, launches under kFillMinWork map
+// positions gain nothing from shorter tiles (measured on per-pair launches of
+// ladder frames) and keep their rows; a tuned tile index always keeps them.
+constexpr int64_t kFillBlocks = 1024;       // 4 workgroups per CU
+constexpr int64_t kFillMinWork = 1 << 20;  // map positions
+
+static int fill_rows(int rows, int min_rows, int64_t tiles_x, int Ho, int batch, int tile_idx, int unit,
+                     int64_t positions) {
+  if (tile_idx != 0 || batch < 1 || positions * batch < kFillMinWork) return rows;
+  while (rows / 2 >= min_rows && (rows / 2) % unit == 0 &&
+         tiles_x * ((Ho + rows - 1) / rows) * (int64_t)batch < kFillBlocks)
+    rows /= 2;
+  return rows;
+}
+
+Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch) {
+  int Wo, Ho;
+  map_dims(p, W, H, Wo, Ho);
+  const int th = fill_rows(16 * fast_chunks(tile_idx), 32, (Wo + 63) / 64, Ho, batch, tile_idx, 16, kFillMinWork);
+  Geom g = geom_with(p, W, H, 64, th);
   g.TW = 64;
-  g.TH = 16 * fast_chunks(tile_idx);
+  g.TH = th;
   g.tiles_x = (g.Wo + 63) / 64;
   g.tiles_y = (g.Ho + g.TH - 1) / g.TH;
   return g;
@@ -129,9 +151,10 @@ Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx) {
 // Input rows per tile of the 8-bit box band kernel, for the same index.
 static const int kBandRows[] = {128, 256, 64, 512, 32, 1024};
 
-Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx) {
+Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch) {
   Geom g = geom_with(p, W, H, 256, 1);
-  const int rows = kBandRows[(tile_idx >= 0 && tile_idx < num_tile_cfgs()) ? tile_idx : 0];
+  int rows = kBandRows[(tile_idx >= 0 && tile_idx < num_tile_cfgs()) ? tile_idx : 0];
+  rows = fill_rows(rows, 32, (g.Wo + 255) / 256, g.Ho * p->stride, batch, tile_idx, p->stride, (int64_t)g.Wo * g.Ho);
   g.TW = 256;
   g.TH = std::max(1, rows / p->stride);
   g.tiles_x = (g.Wo + 255) / 256;
@@ -143,11 +166,13 @@ Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx) {
 // (rounded to whole chunks).
 static const int kStridedRows[] = {32, 64, 16, 128, 8, 256};
 
-Geom strided_geom(const ssimx_params* p, int W, int H, int tile_idx) {
+Geom strided_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch) {
   Geom g = geom_with(p, W, H, strided::kTWo, 1);
   const int cho = p->stride == 2 ? strided::Shape<7, 2>::CHo : p->stride == 3 ? strided::Shape<7, 3>::CHo
                                                                               : strided::Shape<7, 4>::CHo;
-  const int rows = kStridedRows[(tile_idx >= 0 && tile_idx < num_tile_cfgs()) ? tile_idx : 0];
+  int rows = kStridedRows[(tile_idx >= 0 && tile_idx < num_tile_cfgs()) ? tile_idx : 0];
+  rows = fill_rows(rows, 16, (g.Wo + strided::kTWo - 1) / strided::kTWo, g.Ho, batch, tile_idx, 1,
+                   (int64_t)g.Wo * g.Ho);
   g.TW = strided::kTWo;
   g.TH = std::max(1, rows / cho) * cho;
   g.tiles_x = (g.Wo + strided::kTWo - 1) / strided::kTWo;
@@ -353,7 +378,7 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
   Geom g = make_geom_path(p, dtype, W, H, tile_idx);
   if (use_fast(p, dtype)) {
     FastArgs a{};
-    g = fast_geom(p, W, H, tile_idx);
+    g = fast_geom(p, W, H, tile_idx, batch);
     fill_fast_common(a, p, dtype, x, y, g);
     a.mode = mode;
     a.map = map;
@@ -370,7 +395,7 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
     tiles = g.tiles_x * g.tiles_y;
   } else if (use_strided(p, dtype)) {
     FastArgs a{};
-    g = strided_geom(p, W, H, tile_idx);
+    g = strided_geom(p, W, H, tile_idx, batch);
     fill_fast_common(a, p, dtype, x, y, g);
     a.mode = mode;
     a.map = map;
@@ -398,7 +423,7 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
   } else if (path == Path::kBox && mode != 2 && band_eligible(p, dtype) &&
              aligned_vec(x.data, x.pitch, x.bstride, 1) && aligned_vec(y.data, y.pitch, y.bstride, 1)) {
     BandArgs a{};
-    g = band_geom(p, W, H, tile_idx);
+    g = band_geom(p, W, H, tile_idx, batch);
     a.x = x;
     a.y = y;
     a.g = g;

@@ -32,9 +32,9 @@ size_t fwd_ws_bytes(const ssimx_params* p, int dtype, int W, int H, int batch);
 
 struct FastArgs;
 int dtype_size(int dtype);
-Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx);
-Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx);
-Geom strided_geom(const ssimx_params* p, int W, int H, int tile_idx);
+Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch = 0);  // batch > 0: fill small launches
+Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch = 0);
+Geom strided_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch = 0);
 bool use_strided(const ssimx_params* p, int dtype);
 bool band_eligible(const ssimx_params* p, int dtype);
 bool aligned_vec(const void* p, int64_t pitch, int64_t bstride, int esize);
