@@ -121,3 +121,20 @@ def test_config2_full_batch_msssim(P, dev):
     for f in (1, 7, 16, B - 2):
         s1 = P.ms_ssim(xt[f:f + 1], yt[f:f + 1], cfg)
         assert abs(float(s1[0]) - float(s[f])) <= 2e-7
+
+
+@pytest.mark.parametrize("window,k,stride", [("gaussian", 11, 1), ("box", 8, 1), ("gaussian", 11, 4), ("box", 8, 4)])
+def test_single_frame_shorter_tiles(P, dev, c1, window, k, stride):
+    """One 1080p frame alone is cut into shorter tiles than inside the batch
+    (so that it spreads over all CUs): its map equals the batched frame's map
+    bit for bit, and the oracle's map, and its score matches."""
+    x, y, xt, yt = c1
+    cfg = P.SSIMConfig(window=window, k=k, stride=stride)
+    sb, mb = P.ssim(xt[:4], yt[:4], cfg, return_map=True)
+    s1, m1 = P.ssim(xt[2:3], yt[2:3], cfg, return_map=True)
+    torch.cuda.synchronize()
+    assert torch.equal(m1[0], mb[2])
+    assert abs(float(s1[0]) - float(sb[2])) <= 2e-7
+    ref = O.ssim_map(x[2], y[2], oparams(cfg))["map"]
+    assert np.abs(m1[0].cpu().numpy() - ref).max() <= MAP_TOL
+    assert abs(float(s1[0]) - O.mean_pool(ref)) <= SCORE_TOL
