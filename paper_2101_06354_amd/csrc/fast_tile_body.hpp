@@ -537,34 +537,35 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
             const char* row = (const char*)(a.grad_map + (int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch);
             g = *(const float*)(row + cb);
           }
-          // reciprocal estimates (about 1 ulp) suffice for the adjoint
-          const float ib2 = __builtin_amdgcn_rcpf(t.B2);
-          const float dcs_du = 0.5f * var_v * ib2 * ib2;
-          const float dcs_dv = -0.5f * (t.A2 + t.B2) * ib2 * ib2;
-          float au = 0.f, av = 0.f, bu, bv, gg = g;
+          // reciprocal estimates (about 1 ulp) suffice for the adjoint.
+          // d(f_l l + f_c cs) with upstream g: Q = l cs takes f_l = cs,
+          // f_c = l (both times g); cs alone f_l = 0, f_c = g; mode 3 the
+          // two upstreams.  With k_l = f_l / B1^2 and k_c = f_c / B2^2:
+          //   B_u = k_c var_v,  B_v = -k_c (A2 + B2),
+          //   A   = k_l m_v (m_u m_v + A1 + B1) - B_u (m_u - t_u) + B_v (m_v - t_v)
+          // (the three planes are A = A_u - A_v, B_u, B_v of the transpose).
+          const float ib1 = __builtin_amdgcn_rcpf(t.B1), ib2 = __builtin_amdgcn_rcpf(t.B2);
+          float fl, fc;
           if (a.mode == 1) {
-            bu = dcs_du;
-            bv = dcs_dv;
+            fl = 0.f;
+            fc = g;
+          } else if (a.mode == 3) {
+            fl = gl_frame;
+            fc = g;
           } else {
-            // d(fl l + fc cs): Q = l cs takes fl = cs, fc = l; mode 3 the two upstreams
-            const float ib1 = __builtin_amdgcn_rcpf(t.B1);
-            float fl = t.A2 * ib2, fc = t.A1 * ib1;
-            if (a.mode == 3) {
-              fl = gl_frame;
-              fc = g;
-              gg = 1.f;
-            }
-            au = fl * mean_u * (mean_v * mean_v) * ib1 * ib1;
-            av = -fl * mean_v * (t.A1 + t.B1) * ib1 * ib1;
-            bu = fc * dcs_du;
-            bv = fc * dcs_dv;
+            fl = g * (t.A2 * ib2);
+            fc = g * (t.A1 * ib1);
           }
+          const float kl = fl * (ib1 * ib1), kc = fc * (ib2 * ib2);
+          const float bu = kc * var_v, bv = -kc * (t.A2 + t.B2);
+          const float ca = fmaf(kl * mean_v, fmaf(mean_u, mean_v, t.A1 + t.B1),
+                                fmaf(-bu, mean_u - a.tu, bv * (mean_v - a.tv)));
           // W^T is linear: the two A maps are combined before the transpose
           const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
           char* row = (char*)(a.coef + ((int64_t)frame * a.g.Ho + oi) * a.cpitch);
-          *(float*)(row + cb) = gg * ((au - 2.f * bu * (mean_u - a.tu)) - (av - 2.f * bv * (mean_v - a.tv)));
-          *(float*)(row + 4 * qs + cb) = 2.f * gg * bu;
-          *(float*)(row + 8 * qs + cb) = 2.f * gg * bv;
+          *(float*)(row + cb) = ca;
+          *(float*)(row + 4 * qs + cb) = bu;
+          *(float*)(row + 8 * qs + cb) = bv;
         }
       }
     }
