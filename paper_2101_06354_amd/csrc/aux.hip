@@ -23,7 +23,7 @@ __global__ __launch_bounds__(BLOCK) void finalize_kernel(const float* partial, i
   ls[threadIdx.x] = c;
   __syncthreads();
   for (int w = BLOCK / 2; w >= 1; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       float e, t;
       two_sum(hs[threadIdx.x], hs[threadIdx.x + w], t, e);
       hs[threadIdx.x] = t;
