@@ -445,6 +445,11 @@ def _variants_c2(P, dev, stream, rec):
     ms = _time(lambda: P.ms_ssim_backward(x2[:8], y2[:8], torch.ones(8, device=dev), c2), reps=3,
                stream=stream)
     rec("c2_msssim_4k_u16_bwd_8frames", ms, x2[:8].numel(), "adjoint of MS-SSIM on 8 of the frames")
+    sc, cs = P.ms_ssim(x2[:8], y2[:8], c2, return_cs=True)
+    ms = _time(lambda: P.ms_ssim_backward(x2[:8], y2[:8], torch.ones(8, device=dev), c2, fwd=(sc, cs)), reps=3,
+               stream=stream)
+    rec("c2_msssim_4k_u16_bwd_8frames_given_fwd", ms, x2[:8].numel(),
+        "the same adjoint given the forward's score and per-scale values (msssim_backward_values)")
     del x2, y2
 
 

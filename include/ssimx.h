@@ -179,6 +179,20 @@ ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_
                              float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* The same adjoint for a caller that has already run msssim on these inputs
+ * with these weights, n_scales and flags (a training loss): fwd_score float32
+ * [batch] and fwd_cs float32 [batch][n_scales] are that call's score_out and
+ * cs_out (device, read only).  The per-scale windowed passes of the forward
+ * are not repeated; only the 2x2 pyramid is rebuilt, so the gradient is the
+ * one msssim_backward gives.  Null fwd_score or fwd_cs: SSIMX_EINVAL.
+ * SSIMX_MS_COARSE_SEPARATE returns SSIMX_ENOTSUP (its split coarsest term is
+ * not in cs_out).  Workspace: the msssim_backward size. */
+ssimx_status msssim_backward_values(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                    const ssimx_image* ref, const ssimx_image* dis, int batch,
+                                    const float* fwd_score, const float* fwd_cs, const float* grad_score,
+                                    float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
+                                    void* ws, size_t ws_bytes, void* stream);
+
 /* Exact integer window sums of a rectangular k x k window (Performance-
  * Efficiency subsection): sums_out int32 [5][batch][map_h][map_w] holding
  * S1x, S1y, S2x, S2y, S12 in that order (x = ref, y = dis), valid windows at

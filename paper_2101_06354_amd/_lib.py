@@ -79,6 +79,8 @@ _SIGS = {
                                      c_void_p]),
     "msssim_backward": (c_int, [_P, _F, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_int64, c_int64,
                                 c_void_p, c_size_t, c_void_p]),
+    "msssim_backward_values": (c_int, [_P, _F, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, c_int64, c_int64, c_void_p, c_size_t, c_void_p]),
     "ssimx_box_sums": (c_int, [c_int, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ssimx_integral_images": (c_int, [_I, _I, c_int, c_void_p, c_void_p]),
     "ssimx_rgb_to_luma": (c_int, [c_void_p, c_int, c_int, c_int, c_int64, c_int64, c_int64, c_int, c_void_p,

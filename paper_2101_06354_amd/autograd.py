@@ -26,20 +26,28 @@ class SSIMFunction(torch.autograd.Function):
 class MSSSIMFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, y, cfg, weights, n_scales, renorm, cs_clamp, aggregation, coarse_separate):
-        ctx.save_for_backward(x, y)
         ctx.args = (cfg, tuple(weights), n_scales, renorm, cs_clamp, aggregation, coarse_separate)
-        return ops.ms_ssim(x, y, cfg, weights=weights, n_scales=n_scales, renorm=renorm, cs_clamp=cs_clamp,
-                           aggregation=aggregation, coarse_separate=coarse_separate)
+        if coarse_separate:  # the split coarsest term is not in cs: the backward recomputes
+            ctx.save_for_backward(x, y)
+            return ops.ms_ssim(x, y, cfg, weights=weights, n_scales=n_scales, renorm=renorm, cs_clamp=cs_clamp,
+                               aggregation=aggregation, coarse_separate=coarse_separate)
+        score, cs = ops.ms_ssim(x, y, cfg, weights=weights, n_scales=n_scales, renorm=renorm, cs_clamp=cs_clamp,
+                                aggregation=aggregation, return_cs=True)
+        # the forward's values let the backward skip its windowed passes
+        ctx.save_for_backward(x, y, score, cs)
+        return score
 
     @staticmethod
     def backward(ctx, g):
-        x, y = ctx.saved_tensors
+        saved = ctx.saved_tensors
+        x, y = saved[0], saved[1]
+        fwd = (saved[2], saved[3]) if len(saved) == 4 else None
         cfg, weights, n_scales, renorm, cs_clamp, aggregation, coarse_separate = ctx.args
         gy = None
         if ctx.needs_input_grad[1]:
             gy = ops.ms_ssim_backward(x, y, g, cfg, weights=weights, n_scales=n_scales, renorm=renorm,
-                                      cs_clamp=cs_clamp, aggregation=aggregation,
-                                      coarse_separate=coarse_separate).to(y.dtype)
+                                      cs_clamp=cs_clamp, aggregation=aggregation, coarse_separate=coarse_separate,
+                                      fwd=fwd).to(y.dtype)
         return None, gy, None, None, None, None, None, None, None
 
 

@@ -497,47 +497,48 @@ static ssimx_status ssim_bwd_entry(const ssimx_params* p, const ssimx_image* ref
                    (float*)(base + L.coef), (float*)(base + L.gpad), grad, gp, gb, nullptr, 0, 0, st);
 }
 
-}  // namespace ssimx
-
-using namespace ssimx;
-
-extern "C" {
-
-ssimx_status ssim_map_backward(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
-                               const float* grad_map, int64_t map_pitch, int64_t map_batch_stride, float* grad_dis,
-                               int64_t grad_pitch, int64_t grad_batch_stride, void* ws, size_t ws_bytes,
-                               void* stream) {
-  if (!grad_map) return SSIMX_EINVAL;
-  return ssim_bwd_entry(p, ref, dis, batch, grad_map, map_pitch, map_batch_stride, nullptr, grad_dis, grad_pitch,
-                        grad_batch_stride, ws, ws_bytes, (hipStream_t)stream);
-}
-
-ssimx_status ssim_pooled_backward(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
-                                  const float* grad_score, float* grad_dis, int64_t grad_pitch,
-                                  int64_t grad_batch_stride, void* ws, size_t ws_bytes, void* stream) {
-  if (!grad_score) return SSIMX_EINVAL;
-  return ssim_bwd_entry(p, ref, dis, batch, nullptr, 0, 0, grad_score, grad_dis, grad_pitch, grad_batch_stride, ws,
-                        ws_bytes, (hipStream_t)stream);
-}
-
-ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_scales, int flags,
-                             const ssimx_image* ref, const ssimx_image* dis, int batch, const float* grad_score,
-                             float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride, void* ws,
-                             size_t ws_bytes, void* stream) {
+// MS-SSIM adjoint.  With fwd_score / fwd_cs (the score_out and cs_out of a
+// forward call on the same inputs and flags) the forward's windowed passes are
+// not repeated: only the 2x2 pyramid is rebuilt, and the per-scale values feed
+// the upstream factors directly.
+static ssimx_status ms_bwd_impl(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                const ssimx_image* ref, const ssimx_image* dis, int batch, const float* fwd_score,
+                                const float* fwd_cs, const float* grad_score, float* grad_dis, int64_t grad_pitch,
+                                int64_t grad_batch_stride, void* ws, size_t ws_bytes, hipStream_t st) {
   ssimx_status s = check_bwd(p, ref, dis, batch, grad_dis, grad_pitch, grad_batch_stride);
   if (s != SSIMX_OK) return s;
   if (!grad_score) return SSIMX_EINVAL;
   if ((s = check_ms(p, weights, n_scales, flags, ref->width, ref->height)) != SSIMX_OK) return s;
+  // the split coarsest term (mean l, mean cs) is not in a forward's cs_out
+  if (fwd_cs && (flags & SSIMX_MS_COARSE_SEPARATE)) return SSIMX_ENOTSUP;
   if ((s = check_path(p, ref->dtype)) != SSIMX_OK) return s;
   if ((s = check_path(p, SSIMX_F32)) != SSIMX_OK) return s;
   const MsBwdLayout L = ms_bwd_layout(p, ref->dtype, ref->width, ref->height, batch, n_scales);
   if (!ws || ws_bytes < L.total) return SSIMX_EWORKSPACE;
-  hipStream_t st = (hipStream_t)stream;
   char* base = (char*)ws;
   float w[MAX_SCALES];
   ms_weights(weights, n_scales, flags, w);
-  s = ms_forward(p, w, n_scales, flags, ref, dis, batch, (float*)(base + L.msval), nullptr, ws, L.fwd, st);
-  if (s != SSIMX_OK) return s;
+  const float* vals = fwd_cs;
+  const float* msv = fwd_score;
+  if (fwd_cs) {
+    for (int j = 1; j < n_scales; ++j) {
+      const PlaneArg x = j == 1 ? PlaneArg{ref->data, ref->pitch, ref->batch_stride}
+                                : PlaneArg{base + L.fwd.lvl_x_off[j - 1], L.fwd.W[j - 1],
+                                           (int64_t)L.fwd.W[j - 1] * L.fwd.H[j - 1]};
+      const PlaneArg y = j == 1 ? PlaneArg{dis->data, dis->pitch, dis->batch_stride}
+                                : PlaneArg{base + L.fwd.lvl_y_off[j - 1], L.fwd.W[j - 1],
+                                           (int64_t)L.fwd.W[j - 1] * L.fwd.H[j - 1]};
+      const int err = launch_downsample(j == 1 ? ref->dtype : SSIMX_F32, x, L.fwd.W[j - 1], L.fwd.H[j - 1],
+                                        (float*)(base + L.fwd.lvl_x_off[j]), (float*)(base + L.fwd.lvl_y_off[j]), y,
+                                        batch, st);
+      if (err) return hip_status(err);
+    }
+  } else {
+    s = ms_forward(p, w, n_scales, flags, ref, dis, batch, (float*)(base + L.msval), nullptr, ws, L.fwd, st);
+    if (s != SSIMX_OK) return s;
+    vals = (const float*)(base + L.fwd.vals_off);
+    msv = (const float*)(base + L.msval);
+  }
   UpArgs u{};
   for (int j = 0; j < n_scales; ++j) {
     int Wo, Ho;
@@ -548,8 +549,7 @@ ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_
   float* up = (float*)(base + L.up);
   float* up2 = (float*)(base + L.up2);
   const bool sep = (flags & SSIMX_MS_COARSE_SEPARATE) != 0;
-  hipLaunchKernelGGL(ms_upstream_kernel, dim3((batch + 63) / 64), dim3(64), 0, st,
-                     (const float*)(base + L.fwd.vals_off), (const float*)(base + L.msval), grad_score, u, n_scales,
+  hipLaunchKernelGGL(ms_upstream_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, vals, msv, grad_score, u, n_scales,
                      (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, batch,
                      sep ? (const float*)(base + L.fwd.lvals_off) : nullptr, up, up2);
   int err = (int)hipGetLastError();
@@ -581,6 +581,46 @@ ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_
     if (s != SSIMX_OK) return s;
   }
   return SSIMX_OK;
+}
+
+}  // namespace ssimx
+
+using namespace ssimx;
+
+extern "C" {
+
+ssimx_status ssim_map_backward(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                               const float* grad_map, int64_t map_pitch, int64_t map_batch_stride, float* grad_dis,
+                               int64_t grad_pitch, int64_t grad_batch_stride, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (!grad_map) return SSIMX_EINVAL;
+  return ssim_bwd_entry(p, ref, dis, batch, grad_map, map_pitch, map_batch_stride, nullptr, grad_dis, grad_pitch,
+                        grad_batch_stride, ws, ws_bytes, (hipStream_t)stream);
+}
+
+ssimx_status ssim_pooled_backward(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                                  const float* grad_score, float* grad_dis, int64_t grad_pitch,
+                                  int64_t grad_batch_stride, void* ws, size_t ws_bytes, void* stream) {
+  if (!grad_score) return SSIMX_EINVAL;
+  return ssim_bwd_entry(p, ref, dis, batch, nullptr, 0, 0, grad_score, grad_dis, grad_pitch, grad_batch_stride, ws,
+                        ws_bytes, (hipStream_t)stream);
+}
+
+ssimx_status msssim_backward(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                             const ssimx_image* ref, const ssimx_image* dis, int batch, const float* grad_score,
+                             float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride, void* ws,
+                             size_t ws_bytes, void* stream) {
+  return ms_bwd_impl(p, weights, n_scales, flags, ref, dis, batch, nullptr, nullptr, grad_score, grad_dis,
+                     grad_pitch, grad_batch_stride, ws, ws_bytes, (hipStream_t)stream);
+}
+
+ssimx_status msssim_backward_values(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                    const ssimx_image* ref, const ssimx_image* dis, int batch, const float* fwd_score,
+                                    const float* fwd_cs, const float* grad_score, float* grad_dis, int64_t grad_pitch,
+                                    int64_t grad_batch_stride, void* ws, size_t ws_bytes, void* stream) {
+  if (!fwd_score || !fwd_cs) return SSIMX_EINVAL;
+  return ms_bwd_impl(p, weights, n_scales, flags, ref, dis, batch, fwd_score, fwd_cs, grad_score, grad_dis,
+                     grad_pitch, grad_batch_stride, ws, ws_bytes, (hipStream_t)stream);
 }
 
 ssimx_status ssimx_workspace_size(const ssimx_params* p, int op, int dtype, int width, int height, int batch,

@@ -199,7 +199,10 @@ def ssim_map_backward(x: torch.Tensor, y: torch.Tensor, grad_map: torch.Tensor, 
 
 def ms_ssim_backward(x: torch.Tensor, y: torch.Tensor, grad_score: torch.Tensor, cfg: SSIMConfig | None = None,
                      weights=MS_WEIGHTS, n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False,
-                     aggregation: str = "product", coarse_separate: bool = False, **kw):
+                     aggregation: str = "product", coarse_separate: bool = False, fwd=None, **kw):
+    """dL/dy of MS-SSIM.  fwd = (score, cs), the outputs of ms_ssim(..., return_cs=True)
+    on the same inputs and options, skips the forward's windowed passes
+    (msssim_backward_values); without it they are recomputed."""
     cfg = _cfg(cfg, kw)
     xi, yi, b = _pair(x, y)
     p = cfg.to_c()
@@ -208,10 +211,20 @@ def ms_ssim_backward(x: torch.Tensor, y: torch.Tensor, grad_score: torch.Tensor,
     out = torch.empty(_as3(y).shape, dtype=torch.float32, device=x.device)
     ws = _workspace(workspace_size(cfg, L.OP_MSSSIM_BACKWARD, xi.dtype, xi.height, xi.width, b, n_scales),
                     x.device)
-    st = L.lib.msssim_backward(ctypes.byref(p), _weights(weights, n_scales), n_scales, flags, ctypes.byref(xi),
-                               ctypes.byref(yi), b, g.data_ptr(), out.data_ptr(), out.stride(1), out.stride(0),
-                               ws.data_ptr(), ws.numel(), _stream(x))
-    L.check(st, "msssim_backward")
+    if fwd is None:
+        st = L.lib.msssim_backward(ctypes.byref(p), _weights(weights, n_scales), n_scales, flags, ctypes.byref(xi),
+                                   ctypes.byref(yi), b, g.data_ptr(), out.data_ptr(), out.stride(1), out.stride(0),
+                                   ws.data_ptr(), ws.numel(), _stream(x))
+        L.check(st, "msssim_backward")
+    else:
+        score, cs = fwd
+        score = score.to(device=x.device, dtype=torch.float32).reshape(b).contiguous()
+        cs = cs.to(device=x.device, dtype=torch.float32).reshape(b, n_scales).contiguous()
+        st = L.lib.msssim_backward_values(ctypes.byref(p), _weights(weights, n_scales), n_scales, flags,
+                                          ctypes.byref(xi), ctypes.byref(yi), b, score.data_ptr(), cs.data_ptr(),
+                                          g.data_ptr(), out.data_ptr(), out.stride(1), out.stride(0), ws.data_ptr(),
+                                          ws.numel(), _stream(x))
+        L.check(st, "msssim_backward_values")
     return out.reshape(y.shape)
 
 

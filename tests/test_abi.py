@@ -135,6 +135,25 @@ def test_msssim_scale_validation(L):
                         None, None, 0, None) == L.EWORKSPACE
 
 
+def test_msssim_backward_values_validation(L):
+    """The forward-values adjoint: both forward outputs are required, the split
+    coarsest term is refused (it is not in cs_out), otherwise the checks of
+    msssim_backward apply (here: no workspace)."""
+    p = _params(L)
+    ok = L.Image(12345, L.U8, 256, 256, 256, 65536)
+    w = (ctypes.c_float * 5)(0.0448, 0.2856, 0.3001, 0.2363, 0.1333)
+    d = ctypes.c_void_p(1)
+    f = L.lib.msssim_backward_values
+    args = (ctypes.byref(p), w, 5)
+    img = (ctypes.byref(ok), ctypes.byref(ok), 1)
+    assert f(*args, 0, *img, None, d, d, d, 256, 65536, None, 0, None) == L.EINVAL
+    assert f(*args, 0, *img, d, None, d, d, 256, 65536, None, 0, None) == L.EINVAL
+    assert f(*args, L.MS_COARSE_SEPARATE, *img, d, d, d, d, 256, 65536, None, 0, None) == L.ENOTSUP
+    assert f(*args, 0, *img, d, d, None, d, 256, 65536, None, 0, None) == L.EINVAL
+    assert f(*args, 0, *img, d, d, d, d, 256, 65536, None, 0, None) == L.EWORKSPACE
+    assert f(*args, 16, *img, d, d, d, d, 256, 65536, None, 0, None) == L.EINVAL
+
+
 def test_workspace_size_and_tile_api(L):
     p = _params(L)
     n = ctypes.c_size_t()

@@ -230,3 +230,55 @@ def test_backward_row_pitch_beyond_vector_offsets(P, dev):
     assert torch.equal(g2, g)
     _cmp(g2[0].cpu().numpy(), O.ssim_pooled_backward(x[0], y[0], 1.0, oparams(cfg)), "wide pitch")
     del bx, by, vx, vy
+
+
+@pytest.mark.parametrize("kind,n_scales,padding,aggregation",
+                         [("u16", 5, "valid", "product"), ("u16", 3, "reflect", "product"),
+                          ("u8", 4, "valid", "sum"), ("f32", 3, "valid", "product")])
+def test_msssim_backward_from_forward_values(P, dev, kind, n_scales, padding, aggregation):
+    """msssim_backward_values with the forward's score and per-scale values
+    gives msssim_backward's gradient: bit for bit on integer planes (the same
+    exact pyramid), to rounding on float planes, and the oracle's."""
+    if kind == "f32":
+        r, d = synth.config4(batch=2, h=200, w=260)
+        x, y = r[:, 0], d[:, 0]
+        cfg = P.SSIMConfig(L=1.0, padding=padding)
+    elif kind == "u16":
+        x, y = synth.config2(frames=2, h=200, w=260)
+        cfg = P.SSIMConfig(L=1023.0, padding=padding)
+    else:
+        x, y = synth.config1(frames=2, h=200, w=260)
+        cfg = P.SSIMConfig(padding=padding)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    gs = torch.tensor([1.0, -0.5], device=dev)
+    kw = dict(n_scales=n_scales, renorm=n_scales < 5, aggregation=aggregation)
+    score, cs = P.ms_ssim(xt, yt, cfg, return_cs=True, **kw)
+    g0 = P.ms_ssim_backward(xt, yt, gs, cfg, **kw)
+    g1 = P.ms_ssim_backward(xt, yt, gs, cfg, fwd=(score, cs), **kw)
+    if kind == "f32":
+        # the rebuilt 2x2 pyramid and the forward's (means formed from the
+        # staged sums x + y, x - y) differ by rounding on float planes
+        rel = float(torch.linalg.vector_norm(g1 - g0) / torch.linalg.vector_norm(g0))
+        assert rel <= 1e-5, rel
+    else:
+        assert torch.equal(g1, g0)
+    g1 = g1.cpu().numpy()
+    for f, v in enumerate((1.0, -0.5)):
+        gref = O.msssim_backward(x[f], y[f], v, oparams(cfg), n_scales=n_scales, renorm=n_scales < 5,
+                                 aggregation=aggregation)
+        _cmp(g1[f], gref, f"frame {f}")
+    with pytest.raises(Exception):
+        P.ms_ssim_backward(xt, yt, gs, cfg, fwd=(score, cs), coarse_separate=True, **kw)
+
+
+def test_msssim_autograd_uses_forward_values(P, dev):
+    """The differentiable MS-SSIM keeps its forward's values for the backward;
+    the gradient equals the recomputing adjoint's bit for bit (8-bit planes)."""
+    x, y = synth.config1(frames=2, h=200, w=260)
+    xt, yt = to_dev(x, dev), to_dev(y, dev).float().requires_grad_(True)
+    cfg = P.SSIMConfig()
+    s = P.autograd.ms_ssim(xt.float(), yt, cfg, n_scales=3, renorm=True)
+    (s * torch.tensor([1.0, 2.0], device=dev)).sum().backward()
+    g = P.ms_ssim_backward(xt.float(), yt.detach(), torch.tensor([1.0, 2.0], device=dev), cfg, n_scales=3,
+                           renorm=True)
+    assert torch.equal(yt.grad, g)
