@@ -114,7 +114,8 @@ __global__ __launch_bounds__(kSNT) void sat_group_kernel(SatArgs a) {
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
       // 8/16-bit samples: full-rate 24-bit products, exact below 2^32
-      const uint32_t e[5] = {xv[i], yv[i], __umul24(xv[i], xv[i]), __umul24(yv[i], yv[i]), __umul24(xv[i], yv[i])};
+      const uint32_t e[5] = {xv[i], yv[i], (uint32_t)__umul24(xv[i], xv[i]), (uint32_t)__umul24(yv[i], yv[i]),
+                             (uint32_t)__umul24(xv[i], yv[i])};
 #pragma unroll
       for (int q = 0; q < 5; ++q) p[q][i] = i ? p[q][i - 1] + e[q] : e[q];
     }
