@@ -491,3 +491,30 @@ def test_msssim_coarse_separate(P, dev, window, k, algo, n_scales, aggregation):
     xi = to_dev(x, dev)
     one = P.ms_ssim(xi, xi, cfg, weights=w, n_scales=n_scales, renorm=True, coarse_separate=True).cpu().numpy()
     assert np.all(np.abs(one - 1.0) <= 1e-6)
+
+
+@pytest.mark.parametrize("window,k,stride", [("gaussian", 11, 1), ("gaussian", 11, 4), ("box", 8, 1),
+                                             ("gaussian", 5, 1), ("gaussian", 7, 2)])
+def test_nan_and_inf_inputs_propagate(P, dev, window, k, stride):
+    """A NaN or Inf input pixel makes exactly the map positions whose windows
+    cover it non-finite (shared centring values must not leak it to other
+    windows), and the pooled score NaN; MS-SSIM's score is NaN too."""
+    r, d = synth.config4(batch=1, h=70, w=90)
+    cfg = P.SSIMConfig(L=1.0, window=window, k=k, stride=stride, sigma=1.5 if k == 11 else 1.0)
+    for bad, (pr, pc), which in ((np.nan, (33, 41), 0), (np.inf, (9, 70), 1), (-np.inf, (60, 5), 0)):
+        x, y = r[0, 0].copy(), d[0, 0].copy()
+        (x if which == 0 else y)[pr, pc] = bad
+        s, m = P.ssim(to_dev(x, dev), to_dev(y, dev), cfg, return_map=True)
+        m = m[0].cpu().numpy()
+        ho, wo = m.shape
+        ii = np.arange(ho)[:, None] * stride
+        jj = np.arange(wo)[None, :] * stride
+        cover = (ii <= pr) & (pr < ii + k) & (jj <= pc) & (pc < jj + k)
+        assert cover.any()
+        assert not np.isfinite(m[cover]).any(), (bad, np.isfinite(m[cover]).sum())
+        assert np.isfinite(m[~cover]).all(), (bad, (~np.isfinite(m[~cover])).sum())
+        assert np.isnan(float(s[0]))
+    x = r[0, 0].copy()
+    x[40, 40] = np.nan
+    ms = P.ms_ssim(to_dev(x, dev), to_dev(d[0, 0], dev), P.SSIMConfig(L=1.0), n_scales=2, renorm=True)
+    assert np.isnan(float(ms[0]))
