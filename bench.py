@@ -395,6 +395,14 @@ def variants(P, x, y, xt, yt, dev, stream, only=()):
         ms_f = _time(lambda: [P.ssim(xt[f], yt[f], cfg, return_map=True) for f in range(B)], reps=3, stream=stream)
         rec("c1_batched_launch", ms_b, px1, "64 frames in one launch")
         rec("c1_per_frame_launches", ms_f, px1, "64 single-frame launches")
+    # one GPU's share of an 8-way frame split: forward + pooled backward on 8 frames
+    if want("c1_shard_8_frames_fwd_bwd"):
+        import torch
+
+        ones = torch.ones(8, device=dev)
+        ms = _time(lambda: (P.ssim(xt[:8], yt[:8], cfg, return_map=True), P.ssim_backward(xt[:8], yt[:8], ones, cfg)),
+                   stream=stream)
+        rec("c1_shard_8_frames_fwd_bwd", ms, px1 // 8, "8 of the frames (one GPU's share of 8), forward + backward")
     # spatial pooling of the 64 x 1080p Gaussian map; Enhanced SSIM; colour SSIM
     if want("c1_pool_cov", "c1_pool_five_number"):
         _, qm = P.ssim(xt, yt, cfg, return_map=True)
