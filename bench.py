@@ -23,15 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
-FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FP32 flop/clk (packed FMA)
-# Without packed FP32 (not used by this build) one wave64 VALU instruction
-# occupies a 16-lane SIMD for 4 cycles: 256 CU x 4 SIMD x 16 lanes x 2 flop
-# x 2.4 GHz for FMA.
-FP32_VALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-SIMDS, CLOCK_HZ, CYCLES_PER_WAVE_INST = 1024, 2.4e9, 4
-# Textbook separable 5-moment Gaussian SSIM, per output map pixel: 5 maps x 11
-# taps x 2 passes x 2 flop + 3 products + ~17 flop of luminance/cs/Q terms.
-ALG_FLOP_PER_OUT_PX = 5 * 11 * 2 * 2 + 3 + 17
+# Algorithmic HBM bytes per input pixel of the headline step (u8 x and y):
+# forward reads x, y (2 B) and writes the float32 map (4 B per map position)
+# and one score per frame; the pooled backward reads x, y (2 B) and writes the
+# float32 gradient (4 B), plus one upstream value per frame.
+FWD_READ_B_PER_PX, MAP_B_PER_POS, BWD_B_PER_PX = 2, 4, 2 + 4
 
 
 def parse():
@@ -64,33 +60,31 @@ def copy_calibration(nbytes: int) -> None:
     print(json.dumps({"copy_bytes": n * 4}))
 
 
-# Sources of the dominant kernel (the stride-1 Gaussian band kernel): a PMC
-# traffic figure is used only while these files are unchanged.
-DOMINANT_KERNEL_SOURCES = ("fast_tile.hip", "fast_tile_body.hpp", "fast_tile.hpp", "ssim_epilogue.hpp",
-                           "ssimx_internal.hpp")
-
-
 def kernel_source_hash() -> str:
+    """Hash of every kernel and host source of the library: a committed PMC
+    figure is used only while the sources it was taken on are unchanged."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2101_06354_amd", "csrc")
-    for f in DOMINANT_KERNEL_SOURCES:
-        h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_counters(kernel: str) -> dict:
-    """Per-launch figures from the committed rocprofv3 PMC summary (HBM bytes
-    from FETCH_SIZE / WRITE_SIZE, VALU wave instructions), if they were taken
-    on the current kernel sources; else {}."""
+def measured_counters() -> dict:
+    """Per-step figures of the headline step from the committed rocprofv3 PMC
+    summary (HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
+    reading, VALU activity), if they were taken on the current sources; else
+    {}."""
     path = os.path.join(ROOT, "profiles", "pmc_counters.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return {}
-    e = d.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash():
         return {}
-    return e
+    return d
 
 
 _CPU_FRAMES = None  # (x, y) for the forked oracle workers
@@ -288,16 +282,19 @@ def main():
     fwd_avg = float(np.mean(fwd_ms))
     out_px = B * ho * wo
 
-    alg_bytes = px * 2 + out_px * 4 + B * 4          # read x, y; write map and scores
-    alg_flop = out_px * ALG_FLOP_PER_OUT_PX
-    achieved_tflops = alg_flop / (fwd_avg * 1e-3) / 1e12
-    achieved_gbs = alg_bytes / (fwd_avg * 1e-3) / 1e9
-    pmc = measured_counters("fast_stats_kernel<11,u8,0>")
-    traffic = pmc.get("bytes_per_launch")
-    valu = pmc.get("valu_insts_per_launch")
-    # fraction of the VALU issue rate the forward uses (4 cycles per wave64
-    # instruction on each of the 1024 SIMDs), from the measured duration
-    issue_frac = (valu * CYCLES_PER_WAVE_INST / (SIMDS * CLOCK_HZ * fwd_avg * 1e-3)) if valu else None
+    fwd_bytes = px * FWD_READ_B_PER_PX + out_px * MAP_B_PER_POS + B * 4   # x, y in; map and scores out
+    bwd_bytes = px * BWD_B_PER_PX + B * 4 if with_bwd else 0               # x, y in; gradient out
+    step_bytes = fwd_bytes + bwd_bytes
+    bwd_avg = float(np.mean(bwd_ms)) if with_bwd else None
+    pmc = measured_counters()
+
+    def hbm(nbytes, ms):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs, "ms": ms,
+                "alg_bytes": nbytes, "alg_bytes_per_input_px": nbytes / px}
+
+    step = hbm(step_bytes, step_ms)
+    kernels = pmc.get("kernels", {})
     res = {
         "metric": "SSIM Mpixel/s fwd & fwd+bwd (1080p luma, Gaussian 11x11); % HBM roofline",
         "value": value,
@@ -317,19 +314,23 @@ def main():
         "fwd_mpixel_s": px / (fwd_avg * 1e-3) / 1e6,
         "fwd_ms": fwd_avg,
         "fwd_bwd_mpixel_s": value if with_bwd else None,
-        "bwd_ms": float(np.mean(bwd_ms)) if with_bwd else None,
-        "roofline": {"bound": "alu", "kernel": "fast_stats_kernel<11,u8,0> (+finalize)", "achieved": achieved_tflops,
-                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP32_VALU_PEAK_TFLOPS,
-                     "traffic": traffic,
-                     "peak_nonpacked": FP32_VALU_NONPACKED_TFLOPS,
-                     "frac_nonpacked": achieved_tflops / FP32_VALU_NONPACKED_TFLOPS,
-                     "valu_issue_frac": issue_frac,
-                     "alg_flop_per_launch": alg_flop},
+        "bwd_ms": bwd_avg,
+        # The headline step (forward + pooled backward) against the HBM roof:
+        # algorithmic bytes over the step time.  `traffic` is the HBM bytes the
+        # step's kernels moved per step (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+        # scaled by a plain copy's reading), null when the committed counters
+        # predate the current sources.  The kernels are bound by VALU issue,
+        # not by HBM: `kernels` gives each one's counter-derived VALU activity.
+        "roofline": {"bound": "hbm", "scope": "forward + pooled backward step" if with_bwd else "forward",
+                     "achieved": step["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step["frac"],
+                     "traffic": pmc.get("bytes_per_step") if with_bwd else pmc.get("fwd_bytes_per_step"),
+                     "alg_bytes_per_step": step_bytes, "alg_bytes_per_input_px": step_bytes / px,
+                     "measured_copy_gbs": copy_gbs, "frac_of_copy": step["frac_of_copy"],
+                     "forward": hbm(fwd_bytes, fwd_avg),
+                     "backward": hbm(bwd_bytes, bwd_avg) if with_bwd else None,
+                     "kernels": kernels or None,
+                     "counters": pmc.get("summary")},
         "timing": timing,
-        "hbm_roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "measured_copy_gbs": copy_gbs, "frac_of_copy": achieved_gbs / copy_gbs,
-                         "frac": achieved_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
     }
     if not a.no_variants:
         res["variants"] = variants(P, x, y, xt, yt, dev, stream, [o for o in a.only.split(",") if o])

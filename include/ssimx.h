@@ -32,7 +32,11 @@
  *     `batch_stride` = elements between frames.  Planes of one call all have
  *     the same width and height.
  *   - Argument errors are detected on the host before any launch and return
- *     a negative ssimx_status; nothing is launched then.  A failed launch
+ *     a negative ssimx_status; nothing is launched then.  Launch limits are
+ *     argument errors too: a call takes 1..65535 frames (`batch`, `frames`;
+ *     1..21845 RGB frames for ssimx_color_ssim, whose three channels are
+ *     launched as frames), and a plane holds at most 2^31 - 2^16 pixels;
+ *     beyond either, SSIMX_EINVAL.  A failed launch
  *     returns SSIMX_EHIP and ssimx_last_hip_error() gives the hipError_t.
  *     Faults inside kernels surface at the caller's next synchronisation.
  *   - NaN/Inf in inputs propagate to outputs.
@@ -72,7 +76,11 @@ typedef enum { SSIMX_WIN_GAUSSIAN = 0, SSIMX_WIN_BOX = 1 } ssimx_window;
 /* Rectangular windows on integer planes: AUTO/SEPARABLE = tile-local exact
  * integer window sums; INTEGRAL_IMAGE = the paper's five summed-area tables
  * (uint32, wrap-around) and the four-corner formula.  Both give the same
- * integer sums.  Ignored for Gaussian windows. */
+ * integer sums where INTEGRAL_IMAGE is accepted: 8-bit planes (k <= 64 keeps
+ * every window sum below 2^32).  For 16-bit planes a window sum of squares
+ * reaches 2^32 from k = 2 (k^2 * 65535^2), which uint32 tables cannot hold,
+ * so INTEGRAL_IMAGE with uint16 and k > 1 returns SSIMX_ENOTSUP (AUTO gives
+ * the exact sums).  Ignored for Gaussian windows. */
 typedef enum { SSIMX_ALGO_AUTO = 0, SSIMX_ALGO_SEPARABLE = 1, SSIMX_ALGO_INTEGRAL_IMAGE = 2 } ssimx_algo;
 
 /* VALID: windows fully inside the plane.  ZERO / REFLECT: the plane is
@@ -154,6 +162,20 @@ ssimx_status ssim_pooled(const ssimx_params* p, const ssimx_image* ref, const ss
 ssimx_status msssim(const ssimx_params* p, const float* weights, int n_scales, int flags,
                     const ssimx_image* ref, const ssimx_image* dis, int batch,
                     float* score_out, float* cs_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Host only.  Where msssim leaves its pyramid.  After an msssim call with the
+ * same params, dtype, sizes, batch and n_scales returns, its workspace holds
+ * the 2x2-average levels of scales j = 1 .. n_scales-1 (level j has
+ * floor(H / 2^j) x floor(W / 2^j) pixels: MS-SSIM implementation list of the
+ * "Versions of SSIM" section) of both planes as float32
+ * [batch][heights[j]][widths[j]], dense, at byte offsets x_offsets[j] (ref)
+ * and y_offsets[j] (dis) from the workspace base; for j = 0 (the caller's own
+ * planes) the offsets are -1.  On integer planes every level is the exact
+ * block mean (a multiple of 4^-j).  The four output arrays are HOST arrays of
+ * n_scales entries; any may be NULL. */
+ssimx_status ssimx_msssim_pyramid_layout(const ssimx_params* p, int dtype, int width, int height, int batch,
+                                         int n_scales, int64_t* x_offsets, int64_t* y_offsets, int* widths,
+                                         int* heights);
 
 /* Adjoint of ssim_map with respect to dis:
  *   grad_dis(q) = sum_p grad_map(p) dQ(p)/d dis(q).
@@ -389,7 +411,17 @@ ssimx_status ssimx_plan_info(const ssimx_plan* plan, int* n_items, int* n_blocks
  * read by every later call and plan.  Mutex-guarded. */
 ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int height, int batch, void* stream,
                             int* best_tile_out);
-/* Load / save the cache as JSON (path: host string). */
+/* Load / save the cache as JSON (path: host string):
+ *   {"version": SSIMX_VERSION, "entries": {"<key>": <tile index>, ...}}
+ * Load is strict and all-or-nothing: a missing file, a file of 1 MiB or more,
+ * another version, a tile index outside 0..ssimx_num_tile_configs()-1, a
+ * duplicate key, a key with a quote, backslash or non-printable byte or over
+ * 191 bytes, or anything else malformed returns SSIMX_EINVAL and leaves the
+ * cache unchanged; otherwise the entries are merged into the cache.
+ * Environment: SSIMX_TUNE_CACHE=<path> loads that file once, before the
+ * process's first tile choice, autotune or save call (a missing or malformed
+ * file loads nothing), and ssimx_autotune
+ * writes the whole cache back to it. */
 ssimx_status ssimx_tune_cache_load(const char* path);
 ssimx_status ssimx_tune_cache_save(const char* path);
 /* Force a tile configuration index for later calls (-1 = automatic). */

@@ -57,7 +57,7 @@ class SSIMXError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2101_06354_amd.build_lib`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2101_06354_amd/build_lib.py`")
     return ctypes.CDLL(LIB_PATH)
 
 
@@ -73,6 +73,8 @@ _SIGS = {
     "ssim_map": (c_int, [_P, _I, _I, c_int, c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ssim_pooled": (c_int, [_P, _I, _I, c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
     "msssim": (c_int, [_P, _F, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ssimx_msssim_pyramid_layout": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, POINTER(c_int64),
+                                            POINTER(c_int64), POINTER(c_int), POINTER(c_int)]),
     "ssim_map_backward": (c_int, [_P, _I, _I, c_int, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_int64,
                                   c_void_p, c_size_t, c_void_p]),
     "ssim_pooled_backward": (c_int, [_P, _I, _I, c_int, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_size_t,

@@ -1,7 +1,9 @@
-"""torch.autograd wrappers: SSIM and MS-SSIM as differentiable functions of the
-distorted plane (the reference plane gets no gradient), and the BT.601 luma
-front end.  Forward and backward both run in libssimx; the backward
-recomputes the window moments instead of saving them."""
+"""torch.autograd wrappers: SSIM and MS-SSIM as differentiable functions of
+both planes, and the BT.601 luma front end.  Forward and backward both run in
+libssimx; the backward recomputes the window moments instead of saving them.
+SSIM and MS-SSIM are symmetric in their two planes (every term of the
+Background-section definitions is), so the gradient with respect to the
+reference plane is the library's adjoint with the two planes swapped."""
 from __future__ import annotations
 
 import torch
@@ -19,8 +21,9 @@ class SSIMFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         x, y = ctx.saved_tensors
-        gy = ops.ssim_backward(x, y, g, ctx.cfg) if ctx.needs_input_grad[1] else None
-        return None, (gy.to(y.dtype) if gy is not None else None), None
+        gx = ops.ssim_backward(y, x, g, ctx.cfg).to(x.dtype) if ctx.needs_input_grad[0] else None
+        gy = ops.ssim_backward(x, y, g, ctx.cfg).to(y.dtype) if ctx.needs_input_grad[1] else None
+        return gx, gy, None
 
 
 class MSSSIMFunction(torch.autograd.Function):
@@ -43,12 +46,14 @@ class MSSSIMFunction(torch.autograd.Function):
         x, y = saved[0], saved[1]
         fwd = (saved[2], saved[3]) if len(saved) == 4 else None
         cfg, weights, n_scales, renorm, cs_clamp, aggregation, coarse_separate = ctx.args
-        gy = None
+        kw = dict(weights=weights, n_scales=n_scales, renorm=renorm, cs_clamp=cs_clamp, aggregation=aggregation,
+                  coarse_separate=coarse_separate, fwd=fwd)
+        gx = gy = None
+        if ctx.needs_input_grad[0]:  # the forward's values are symmetric too
+            gx = ops.ms_ssim_backward(y, x, g, cfg, **kw).to(x.dtype)
         if ctx.needs_input_grad[1]:
-            gy = ops.ms_ssim_backward(x, y, g, cfg, weights=weights, n_scales=n_scales, renorm=renorm,
-                                      cs_clamp=cs_clamp, aggregation=aggregation, coarse_separate=coarse_separate,
-                                      fwd=fwd).to(y.dtype)
-        return None, gy, None, None, None, None, None, None, None
+            gy = ops.ms_ssim_backward(x, y, g, cfg, **kw).to(y.dtype)
+        return gx, gy, None, None, None, None, None, None, None
 
 
 class LumaFunction(torch.autograd.Function):
@@ -84,8 +89,8 @@ def luma(rgb):
 def ms_ssim_loss_rgb(ref_rgb, dis_rgb, cfg: ops.SSIMConfig | None = None, n_scales: int = 3, renorm: bool = True,
                      **kw):
     """1 - MS-SSIM on BT.601 luma, averaged over the batch (the training loss
-    of the differentiable workload); gradients flow to dis_rgb."""
+    of the differentiable workload); gradients flow to both planes."""
     cfg = ops._cfg(cfg, kw)
-    yr = ops.rgb_to_luma(ref_rgb)
+    yr = luma(ref_rgb)
     yd = luma(dis_rgb)
     return (1.0 - ms_ssim(yr, yd, cfg, n_scales=n_scales, renorm=renorm)).mean()

@@ -1,6 +1,7 @@
 """Build libssimx.so (HIP C++ for gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2101_06354_amd.build_lib [--jobs N]
+Usage: python paper_2101_06354_amd/build_lib.py [--jobs N]  (by path: importing the package
+would first load the library being rebuilt)
 """
 from __future__ import annotations
 

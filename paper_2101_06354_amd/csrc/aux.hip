@@ -246,7 +246,9 @@ extern "C" {
 ssimx_status ssimx_rgb_to_luma(const void* rgb, int dtype, int width, int height, int64_t pitch,
                                int64_t channel_stride, int64_t batch_stride, int batch, float* y_out,
                                void* stream) {
-  if (!rgb || !y_out || width < 1 || height < 1 || batch < 1 || pitch < width) return SSIMX_EINVAL;
+  if (!rgb || !y_out || width < 1 || height < 1 || batch < 1 || batch > kMaxGridY || pitch < width)
+    return SSIMX_EINVAL;
+  if ((int64_t)width * height > kMaxPlaneElems) return SSIMX_EINVAL;
   if (channel_stride < pitch * (int64_t)height || (batch > 1 && batch_stride < 3 * channel_stride))
     return SSIMX_EINVAL;
   dim3 grid((width * height + BLOCK - 1) / BLOCK, batch);
@@ -264,7 +266,9 @@ ssimx_status ssimx_rgb_to_luma(const void* rgb, int dtype, int width, int height
 
 ssimx_status ssimx_luma_grad_to_rgb(const float* grad_y, int width, int height, int batch, float* grad_rgb,
                                     int64_t pitch, int64_t channel_stride, int64_t batch_stride, void* stream) {
-  if (!grad_y || !grad_rgb || width < 1 || height < 1 || batch < 1 || pitch < width) return SSIMX_EINVAL;
+  if (!grad_y || !grad_rgb || width < 1 || height < 1 || batch < 1 || batch > kMaxGridY || pitch < width)
+    return SSIMX_EINVAL;
+  if ((int64_t)width * height > kMaxPlaneElems) return SSIMX_EINVAL;
   if (channel_stride < pitch * (int64_t)height || (batch > 1 && batch_stride < 3 * channel_stride))
     return SSIMX_EINVAL;
   dim3 grid((width * height + BLOCK - 1) / BLOCK, batch);

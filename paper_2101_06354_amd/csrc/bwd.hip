@@ -627,7 +627,8 @@ ssimx_status ssimx_workspace_size(const ssimx_params* p, int op, int dtype, int 
                                   int n_scales, size_t* bytes) {
   ssimx_status s = check_params(p);
   if (s != SSIMX_OK) return s;
-  if (!bytes || width < 1 || height < 1 || batch < 1) return SSIMX_EINVAL;
+  if (!bytes || width < 1 || height < 1 || batch < 1 || batch > kMaxGridY) return SSIMX_EINVAL;
+  if ((int64_t)width * height > kMaxPlaneElems) return SSIMX_EINVAL;
   if (dtype < SSIMX_U8 || dtype > SSIMX_BF16) return SSIMX_EDTYPE;
   const bool ms = op == SSIMX_OP_MSSSIM || op == SSIMX_OP_MSSSIM_BACKWARD;
   if (ms && (n_scales < 1 || n_scales > MAX_SCALES)) return SSIMX_EINVAL;

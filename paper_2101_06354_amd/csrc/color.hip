@@ -91,7 +91,7 @@ extern "C" {
 ssimx_status ssimx_color_workspace_size(const ssimx_params* p, int w, int h, int batch, size_t* bytes) {
   ssimx_status s;
   if ((s = check_params(p)) != SSIMX_OK) return s;
-  if (!bytes || batch < 1) return SSIMX_EINVAL;
+  if (!bytes || batch < 1 || 3 * (int64_t)batch > kMaxGridY) return SSIMX_EINVAL;
   int Wo, Ho;
   map_dims(p, w, h, Wo, Ho);
   if (w < 1 || h < 1 || Wo < 1 || Ho < 1) return SSIMX_ETOOSMALL;
@@ -105,8 +105,9 @@ ssimx_status ssimx_color_ssim(const ssimx_params* p, double alpha, double beta, 
                               size_t ws_bytes, void* stream) {
   ssimx_status s;
   if ((s = check_color(p, alpha, beta, dtype)) != SSIMX_OK) return s;
-  if (!ref_rgb || !dis_rgb || !score_out || batch < 1) return SSIMX_EINVAL;
+  if (!ref_rgb || !dis_rgb || !score_out || batch < 1 || 3 * (int64_t)batch > kMaxGridY) return SSIMX_EINVAL;
   if (w < 1 || h < 1) return SSIMX_ETOOSMALL;
+  if ((int64_t)w * h > kMaxPlaneElems) return SSIMX_EINVAL;
   if (pitch < w || channel_stride < pitch * (int64_t)h || (batch > 1 && batch_stride < 3 * channel_stride))
     return SSIMX_EINVAL;
   int Wo, Ho;

@@ -45,11 +45,12 @@ ssimx_status check_params(const ssimx_params* p) {
 }
 
 ssimx_status check_images(const ssimx_image* a, const ssimx_image* b, int batch) {
-  if (!a || !b || batch < 1) return SSIMX_EINVAL;
+  if (!a || !b || batch < 1 || batch > kMaxGridY) return SSIMX_EINVAL;
   for (const ssimx_image* im : {a, b}) {
     if (!im->data) return SSIMX_EINVAL;
     if (im->dtype < SSIMX_U8 || im->dtype > SSIMX_BF16) return SSIMX_EDTYPE;
     if (im->width < 1 || im->height < 1) return SSIMX_ETOOSMALL;
+    if ((int64_t)im->width * im->height > kMaxPlaneElems) return SSIMX_EINVAL;
     if (im->pitch < im->width) return SSIMX_EINVAL;
     if (batch > 1 && im->batch_stride < im->pitch * (int64_t)im->height) return SSIMX_EINVAL;
   }
@@ -71,6 +72,9 @@ ssimx_status check_path(const ssimx_params* p, int dtype) {
   if (path == Path::kSep && p->k > KMAX_GAUSS) return SSIMX_ENOTSUP;  // float box wider than the tap table
   if (path == Path::kSat && p->padding != SSIMX_PAD_VALID) return SSIMX_ENOTSUP;
   if (p->algo == SSIMX_ALGO_INTEGRAL_IMAGE && p->window == SSIMX_WIN_BOX && !is_integer(dtype)) return SSIMX_EDTYPE;
+  // uint32 tables hold a window sum only below 2^32: k^2 * 65535^2 reaches it
+  // from k = 2, so 16-bit planes take the exact tile sums instead
+  if (path == Path::kSat && dtype == SSIMX_U16 && p->k > 1) return SSIMX_ENOTSUP;
   return SSIMX_OK;
 }
 
@@ -585,6 +589,25 @@ ssimx_status msssim(const ssimx_params* p, const float* weights, int n_scales, i
   float w[MAX_SCALES];
   ms_weights(weights, n_scales, flags, w);
   return ms_forward(p, w, n_scales, flags, ref, dis, batch, score_out, cs_out, ws, L, (hipStream_t)stream);
+}
+
+ssimx_status ssimx_msssim_pyramid_layout(const ssimx_params* p, int dtype, int width, int height, int batch,
+                                         int n_scales, int64_t* x_offsets, int64_t* y_offsets, int* widths,
+                                         int* heights) {
+  ssimx_status s;
+  if ((s = check_params(p)) != SSIMX_OK) return s;
+  if (width < 1 || height < 1 || batch < 1 || batch > kMaxGridY || n_scales < 1 || n_scales > MAX_SCALES)
+    return SSIMX_EINVAL;
+  if ((int64_t)width * height > kMaxPlaneElems) return SSIMX_EINVAL;
+  if (dtype < SSIMX_U8 || dtype > SSIMX_BF16) return SSIMX_EDTYPE;
+  const MsLayout L = ms_layout(p, dtype, width, height, batch, n_scales);
+  for (int j = 0; j < n_scales; ++j) {
+    if (x_offsets) x_offsets[j] = j == 0 ? -1 : (int64_t)L.lvl_x_off[j];
+    if (y_offsets) y_offsets[j] = j == 0 ? -1 : (int64_t)L.lvl_y_off[j];
+    if (widths) widths[j] = L.W[j];
+    if (heights) heights[j] = L.H[j];
+  }
+  return SSIMX_OK;
 }
 
 ssimx_status ssimx_box_sums(int k, int stride, int algo, const ssimx_image* ref, const ssimx_image* dis, int batch,

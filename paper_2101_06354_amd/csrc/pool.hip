@@ -573,7 +573,7 @@ extern "C" {
 ssimx_status ssimx_pool_workspace_size(const ssimx_pool* pool, int w, int h, int batch, size_t* bytes) {
   ssimx_status s;
   if ((s = check_pool(pool)) != SSIMX_OK) return s;
-  if (!bytes || batch < 1) return SSIMX_EINVAL;
+  if (!bytes || batch < 1 || batch > kMaxGridY) return SSIMX_EINVAL;
   if (w < 1 || h < 1) return SSIMX_ETOOSMALL;
   *bytes = pool_ws_bytes(pool, w, h, batch);
   return SSIMX_OK;
@@ -583,7 +583,7 @@ ssimx_status ssimx_pool_map(const ssimx_pool* pool, const float* map, int w, int
                             long long batch_stride, int batch, float* out, void* ws, size_t ws_bytes, void* stream) {
   ssimx_status s;
   if ((s = check_pool(pool)) != SSIMX_OK) return s;
-  if (!map || !out || batch < 1) return SSIMX_EINVAL;
+  if (!map || !out || batch < 1 || batch > kMaxGridY) return SSIMX_EINVAL;
   if (w < 1 || h < 1) return SSIMX_ETOOSMALL;
   if (pitch < w || (batch > 1 && batch_stride < pitch * (long long)h)) return SSIMX_EINVAL;
   if ((long long)w * h >= (1ll << 31)) return SSIMX_ENOTSUP;

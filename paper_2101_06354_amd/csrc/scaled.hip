@@ -62,7 +62,7 @@ ssimx_status ssimx_scaled_pooled_workspace_size(const ssimx_params* p, int facto
                                                 int w, int h, int batch, size_t* bytes) {
   ssimx_status s;
   if ((s = check_scaled(p, factor, pool, dtype)) != SSIMX_OK) return s;
-  if (!bytes || batch < 1) return SSIMX_EINVAL;
+  if (!bytes || batch < 1 || batch > kMaxGridY) return SSIMX_EINVAL;
   ScaledLayout L{};
   if ((s = scaled_layout(p, factor, pool, dtype, w, h, batch, L)) != SSIMX_OK) return s;
   *bytes = L.total;

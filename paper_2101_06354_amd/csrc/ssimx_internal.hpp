@@ -13,6 +13,11 @@ constexpr int KMAX_GAUSS = 41;  // largest Gaussian window (odd)
 constexpr int KMAX_BOX = 64;    // largest rectangular window
 constexpr int BLOCK = 256;      // threads per block of the tiled kernels
 constexpr int MAX_SCALES = 8;
+// Launch limits checked on the host before any launch: frames go on grid.y
+// (65535 at most; the colour path puts 3 channel frames per RGB frame
+// there), and per-plane element grids are formed in 32-bit ints.
+constexpr int kMaxGridY = 65535;
+constexpr int64_t kMaxPlaneElems = (1ll << 31) - (1ll << 16);
 
 struct bf16_t {
   uint16_t bits;

@@ -5,6 +5,7 @@
 // cache is filled by ssimx_autotune (timed with HIP events on the caller's
 // stream) or loaded from a JSON file, and read by every later call.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -36,7 +37,108 @@ static std::string tune_key(const ssimx_params* p, int dtype, int W, int H, int 
   return buf;
 }
 
+// ---- cache file: the JSON object the save call writes,
+//   {"version": <int>, "entries": {"<key>": <tile index>, ...}}
+// read by a strict recursive-descent parser: whitespace anywhere between
+// tokens, keys are plain strings (printable ASCII, no quote or backslash,
+// at most 191 bytes), values decimal integers naming a tile configuration,
+// "version" must equal SSIMX_VERSION, nothing may follow the object.  A file
+// that breaks any rule loads nothing.
+constexpr size_t kCacheMaxBytes = 1 << 20;
+
+namespace {
+
+struct CacheParser {
+  const std::string& t;
+  size_t i = 0;
+  void ws() {
+    while (i < t.size() && (t[i] == ' ' || t[i] == '\t' || t[i] == '\n' || t[i] == '\r')) ++i;
+  }
+  bool lit(char c) {
+    ws();
+    if (i < t.size() && t[i] == c) {
+      ++i;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string& out) {
+    if (!lit('"')) return false;
+    out.clear();
+    while (i < t.size() && t[i] != '"') {
+      const unsigned char c = (unsigned char)t[i];
+      if (c < 0x20 || c > 0x7e || c == '\\' || out.size() >= 191) return false;
+      out.push_back((char)c);
+      ++i;
+    }
+    if (i >= t.size()) return false;
+    ++i;  // closing quote
+    return true;
+  }
+  bool integer(long& v) {
+    ws();
+    const size_t b = i;
+    if (i < t.size() && t[i] == '-') ++i;
+    const size_t d = i;
+    while (i < t.size() && t[i] >= '0' && t[i] <= '9' && i - d < 9) ++i;
+    if (i == d || (i < t.size() && t[i] >= '0' && t[i] <= '9')) return false;  // no digits, or too many
+    v = strtol(t.c_str() + b, nullptr, 10);
+    return true;
+  }
+};
+
+}  // namespace
+
+static bool parse_cache(const std::string& text, std::map<std::string, int>& out) {
+  CacheParser P{text};
+  if (!P.lit('{')) return false;
+  bool have_version = false, have_entries = false;
+  std::string key;
+  do {
+    if (!P.str(key) || !P.lit(':')) return false;
+    if (key == "version") {
+      long v;
+      if (have_version || !P.integer(v) || v != SSIMX_VERSION) return false;
+      have_version = true;
+    } else if (key == "entries") {
+      if (have_entries || !P.lit('{')) return false;
+      have_entries = true;
+      if (!P.lit('}')) {
+        do {
+          long v;
+          if (!P.str(key) || !P.lit(':') || !P.integer(v)) return false;
+          if (v < 0 || v >= num_tile_cfgs() || out.count(key)) return false;
+          out[key] = (int)v;
+        } while (P.lit(','));
+        if (!P.lit('}')) return false;
+      }
+    } else {
+      return false;
+    }
+  } while (P.lit(','));
+  if (!P.lit('}') || !have_version || !have_entries) return false;
+  P.ws();
+  return P.i == text.size();
+}
+
+// SSIMX_TUNE_CACHE names a cache file: it is loaded once, before the first
+// tile choice or autotune call of the process (a missing or malformed file
+// loads nothing), and every autotune call writes the whole cache back to it.
+static std::once_flag g_env_once;
+
+static const char* env_cache_path() {
+  const char* e = getenv("SSIMX_TUNE_CACHE");
+  return (e && *e) ? e : nullptr;
+}
+
+static void load_env_cache() {
+  std::call_once(g_env_once, [] {
+    if (const char* path = env_cache_path()) (void)ssimx_tune_cache_load(path);
+  });
+}
+
 int pick_tile(const ssimx_params* p, int dtype, int W, int H, int batch) {
+  load_env_cache();
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (g_tile_override >= 0) return g_tile_override;
   auto it = g_tune_cache.find(tune_key(p, dtype, W, H, batch));
@@ -60,9 +162,12 @@ ssimx_status ssimx_set_tile_override(int tile) {
 
 ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int height, int batch, void* stream,
                             int* best_tile_out) {
+  load_env_cache();
   ssimx_status s = check_params(p);
   if (s != SSIMX_OK) return s;
-  if (width < 1 || height < 1 || batch < 1 || dtype < SSIMX_U8 || dtype > SSIMX_BF16) return SSIMX_EINVAL;
+  if (width < 1 || height < 1 || batch < 1 || batch > kMaxGridY || dtype < SSIMX_U8 || dtype > SSIMX_BF16)
+    return SSIMX_EINVAL;
+  if ((int64_t)width * height > kMaxPlaneElems) return SSIMX_EINVAL;
   if ((s = check_path(p, dtype)) != SSIMX_OK) return s;
   int Wo, Ho;
   map_dims(p, width, height, Wo, Ho);
@@ -123,12 +228,14 @@ ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int hei
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[tune_key(p, dtype, width, height, batch)] = best;
   }
+  if (const char* path = env_cache_path()) (void)ssimx_tune_cache_save(path);
   if (best_tile_out) *best_tile_out = best;
   return SSIMX_OK;
 }
 
 ssimx_status ssimx_tune_cache_save(const char* path) {
   if (!path) return SSIMX_EINVAL;
+  load_env_cache();
   FILE* f = fopen(path, "w");
   if (!f) return SSIMX_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -150,26 +257,11 @@ ssimx_status ssimx_tune_cache_load(const char* path) {
   std::string text;
   char buf[4096];
   size_t n;
-  while ((n = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+  while ((n = fread(buf, 1, sizeof(buf), f)) > 0 && text.size() < kCacheMaxBytes) text.append(buf, n);
   fclose(f);
-  const size_t ent = text.find("\"entries\"");
-  if (ent == std::string::npos) return SSIMX_EINVAL;
-  size_t pos = text.find('{', ent);
-  if (pos == std::string::npos) return SSIMX_EINVAL;
+  if (text.size() >= kCacheMaxBytes) return SSIMX_EINVAL;
   std::map<std::string, int> loaded;
-  while (true) {
-    const size_t q0 = text.find('"', pos + 1);
-    const size_t close = text.find('}', pos + 1);
-    if (q0 == std::string::npos || (close != std::string::npos && close < q0)) break;
-    const size_t q1 = text.find('"', q0 + 1);
-    if (q1 == std::string::npos) return SSIMX_EINVAL;
-    const size_t colon = text.find(':', q1);
-    if (colon == std::string::npos) return SSIMX_EINVAL;
-    const int v = atoi(text.c_str() + colon + 1);
-    if (v < 0 || v >= num_tile_cfgs()) return SSIMX_EINVAL;
-    loaded[text.substr(q0 + 1, q1 - q0 - 1)] = v;
-    pos = colon + 1;
-  }
+  if (!parse_cache(text, loaded)) return SSIMX_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (const auto& kv : loaded) g_tune_cache[kv.first] = kv.second;
   return SSIMX_OK;

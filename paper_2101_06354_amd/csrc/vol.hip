@@ -467,7 +467,7 @@ ssimx_status ssimx_ssim3d_workspace_size(const ssimx_params* p, int kt, int dtyp
                                          size_t* bytes) {
   ssimx_status s;
   if ((s = check_vol(p, kt)) != SSIMX_OK) return s;
-  if (!bytes) return SSIMX_EINVAL;
+  if (!bytes || frames > kMaxGridY) return SSIMX_EINVAL;
   if (dtype < SSIMX_U8 || dtype > SSIMX_BF16) return SSIMX_EDTYPE;
   if (frames < kt || width < p->k || height < p->k) return SSIMX_ETOOSMALL;
   *bytes = vol_ws_bytes(width, height, frames, p->k, kt, dtype);
@@ -494,7 +494,7 @@ ssimx_status ssimx_msssim3d_workspace_size(const ssimx_params* p, int kt, int n_
                                            int height, int frames, size_t* bytes) {
   ssimx_status s;
   if ((s = check_vol(p, kt)) != SSIMX_OK) return s;
-  if (!bytes || n_scales < 1 || n_scales > MAX_SCALES) return SSIMX_EINVAL;
+  if (!bytes || n_scales < 1 || n_scales > MAX_SCALES || frames > kMaxGridY) return SSIMX_EINVAL;
   if (dtype < SSIMX_U8 || dtype > SSIMX_BF16) return SSIMX_EDTYPE;
   if (frames < kt || width < 1 || height < 1) return SSIMX_ETOOSMALL;
   int Wj[MAX_SCALES], Hj[MAX_SCALES];

@@ -146,12 +146,14 @@ def _ms_flags(renorm: bool, cs_clamp: bool, aggregation: str, coarse_separate: b
 
 def ms_ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, weights=MS_WEIGHTS,
             n_scales: int = 5, renorm: bool = False, cs_clamp: bool = False, return_cs: bool = False,
-            aggregation: str = "product", coarse_separate: bool = False, **kw):
+            aggregation: str = "product", coarse_separate: bool = False, return_pyramid: bool = False, **kw):
     """MS-SSIM per frame (float32 [B]); with return_cs also [B, n_scales]
     holding CS_1..CS_{M-1} and S_M.  aggregation="sum" takes the weighted
     average of the same terms with normalised weights instead of the
     weighted product; coarse_separate=True reads the coarsest term as
-    mean(l) * mean(cs) instead of mean(l * cs)."""
+    mean(l) * mean(cs) instead of mean(l * cs).  return_pyramid=True also
+    returns the levels the call built, [(x_j, y_j) for j = 1 .. n_scales-1],
+    float32 [B, H_j, W_j] views of its workspace (ssimx_msssim_pyramid_layout)."""
     cfg = _cfg(cfg, kw)
     xi, yi, b = _pair(x, y)
     p = cfg.to_c()
@@ -163,7 +165,19 @@ def ms_ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, wei
                       ctypes.byref(yi), b, score.data_ptr(), cs.data_ptr() if cs is not None else None,
                       ws.data_ptr(), ws.numel(), _stream(x))
     L.check(st, "msssim")
-    return (score, cs) if return_cs else score
+    out = (score, cs) if return_cs else (score,)
+    if return_pyramid:
+        xo, yo = (ctypes.c_int64 * n_scales)(), (ctypes.c_int64 * n_scales)()
+        wj, hj = (ctypes.c_int * n_scales)(), (ctypes.c_int * n_scales)()
+        st = L.lib.ssimx_msssim_pyramid_layout(ctypes.byref(p), xi.dtype, xi.width, xi.height, b, n_scales, xo, yo,
+                                               wj, hj)
+        L.check(st, "ssimx_msssim_pyramid_layout")
+
+        def level(off, j):
+            n = b * hj[j] * wj[j] * 4
+            return ws[off:off + n].view(torch.float32).reshape(b, hj[j], wj[j])
+        out = out + ([(level(xo[j], j), level(yo[j], j)) for j in range(1, n_scales)],)
+    return out if len(out) > 1 else out[0]
 
 
 def ssim_backward(x: torch.Tensor, y: torch.Tensor, grad_score: torch.Tensor, cfg: SSIMConfig | None = None, **kw):

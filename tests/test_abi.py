@@ -277,3 +277,165 @@ def test_host_tensors_are_rejected_not_computed(L):
         P.ssim(x, x)
     with pytest.raises(ValueError):
         P.ssim3d(torch.zeros((4, 32, 32), dtype=torch.uint8), torch.zeros((4, 32, 32), dtype=torch.uint8), 2)
+
+
+# ---------------------------------------------------------------- launch limits
+def test_batch_beyond_grid_limit_is_refused_before_launch(L):
+    """Frames go on grid.y (65535 at most); the host refuses more with EINVAL
+    before any launch (the device pointers here are never dereferenced)."""
+    p = _params(L)
+    im = L.Image(4096, L.U8, 64, 64, 64, 4096)
+    sc, ws = ctypes.c_void_p(8192), ctypes.c_void_p(16384)
+    big = 1 << 30
+    for batch, want in ((65536, L.EINVAL), (70000, L.EINVAL)):
+        assert L.lib.ssim_pooled(ctypes.byref(p), ctypes.byref(im), ctypes.byref(im), batch, sc, ws, big,
+                                 None) == want
+        assert L.lib.ssim_map(ctypes.byref(p), ctypes.byref(im), ctypes.byref(im), batch, sc, 54, 54 * 54, sc, ws,
+                              big, None) == want
+        assert L.lib.ssim_pooled_backward(ctypes.byref(p), ctypes.byref(im), ctypes.byref(im), batch, sc, sc, 64,
+                                          4096, ws, big, None) == want
+        w = (ctypes.c_float * 2)(0.5, 0.5)
+        assert L.lib.msssim(ctypes.byref(p), w, 2, 0, ctypes.byref(im), ctypes.byref(im), batch, sc, None, ws, big,
+                            None) == want
+        n = ctypes.c_size_t()
+        assert L.lib.ssimx_workspace_size(ctypes.byref(p), L.OP_POOLED, L.U8, 64, 64, batch, 1,
+                                          ctypes.byref(n)) == want
+        assert L.lib.ssimx_rgb_to_luma(sc, L.F32, 64, 64, 64, 4096, 3 * 4096, batch, sc, None) == want
+        assert L.lib.ssimx_luma_grad_to_rgb(sc, 64, 64, batch, sc, 64, 4096, 3 * 4096, None) == want
+        pool = L.Pool(kind=L.POOL_MEAN, p=1.0, o=1.0, r=1.0)
+        assert L.lib.ssimx_pool_map(ctypes.byref(pool), sc, 64, 64, 64, 4096, batch, sc, ws, big, None) == want
+        assert L.lib.ssimx_pool_workspace_size(ctypes.byref(pool), 64, 64, batch, ctypes.byref(n)) == want
+        assert L.lib.ssimx_ssim3d_workspace_size(ctypes.byref(_params(L, window=L.WIN_BOX, k=8)), 3, L.U8, 64, 64,
+                                                 batch, ctypes.byref(n)) == want
+    # the colour path launches three channel frames per RGB frame
+    assert L.lib.ssimx_color_ssim(ctypes.byref(p), 0.125, 0.125, sc, sc, L.U8, 64, 64, 64, 4096, 3 * 4096, 21846,
+                                  sc, None, ws, big, None) == L.EINVAL
+    n = ctypes.c_size_t()
+    assert L.lib.ssimx_color_workspace_size(ctypes.byref(p), 64, 64, 21846, ctypes.byref(n)) == L.EINVAL
+    assert L.lib.ssimx_color_workspace_size(ctypes.byref(p), 64, 64, 21845, ctypes.byref(n)) == L.OK
+    # the largest accepted batch passes validation (and stops at the workspace check)
+    assert L.lib.ssim_pooled(ctypes.byref(p), ctypes.byref(im), ctypes.byref(im), 65535, sc, None, 0,
+                             None) == L.EWORKSPACE
+
+
+def test_plane_element_limit(L):
+    p = _params(L)
+    sc = ctypes.c_void_p(8192)
+    huge = L.Image(4096, L.U8, 1 << 16, 1 << 15, 1 << 16, 1 << 31)  # 2^31 pixels
+    assert L.lib.ssim_pooled(ctypes.byref(p), ctypes.byref(huge), ctypes.byref(huge), 1, sc, None, 0,
+                             None) == L.EINVAL
+    n = ctypes.c_size_t()
+    assert L.lib.ssimx_workspace_size(ctypes.byref(p), L.OP_POOLED, L.U8, 1 << 16, 1 << 15, 1, 1,
+                                      ctypes.byref(n)) == L.EINVAL
+    assert L.lib.ssimx_rgb_to_luma(sc, L.F32, 1 << 16, 1 << 15, 1 << 16, 1 << 31, 3 << 31, 1, sc,
+                                   None) == L.EINVAL
+
+
+def test_integral_image_refuses_16bit_windows(L):
+    """uint32 tables cannot hold a 16-bit window sum of squares from k = 2 up
+    (k^2 * 65535^2 >= 2^32): ENOTSUP, while the tile-sum algorithm accepts."""
+    sc = ctypes.c_void_p(8192)
+    im16 = L.Image(4096, L.U16, 64, 64, 64, 4096)
+    im8 = L.Image(4096, L.U8, 64, 64, 64, 4096)
+    for k in (2, 8, 16):
+        pb = _params(L, window=L.WIN_BOX, k=k, algo=L.ALGO_INTEGRAL_IMAGE)
+        assert L.lib.ssim_pooled(ctypes.byref(pb), ctypes.byref(im16), ctypes.byref(im16), 1, sc, None, 0,
+                                 None) == L.ENOTSUP
+        assert L.lib.ssim_pooled(ctypes.byref(pb), ctypes.byref(im8), ctypes.byref(im8), 1, sc, None, 0,
+                                 None) == L.EWORKSPACE
+        pa = _params(L, window=L.WIN_BOX, k=k, algo=L.ALGO_AUTO)
+        assert L.lib.ssim_pooled(ctypes.byref(pa), ctypes.byref(im16), ctypes.byref(im16), 1, sc, None, 0,
+                                 None) == L.EWORKSPACE
+    p1 = _params(L, window=L.WIN_BOX, k=1, algo=L.ALGO_INTEGRAL_IMAGE)
+    assert L.lib.ssim_pooled(ctypes.byref(p1), ctypes.byref(im16), ctypes.byref(im16), 1, sc, None, 0,
+                             None) == L.EWORKSPACE
+
+
+# ---------------------------------------------------------------- tune cache file
+def _cache_entries(L, tmp_path, name="dump.json"):
+    import json
+    out = tmp_path / name
+    assert L.lib.ssimx_tune_cache_save(str(out).encode()) == L.OK
+    return json.loads(out.read_text())["entries"]
+
+
+def test_tune_cache_round_trip_and_merge(L, tmp_path):
+    v = L.lib.ssimx_version()
+    f = tmp_path / "good.json"
+    f.write_text('{ "version" : %d ,\n "entries": {"cpu-test|a": 1, "cpu-test|b" :0} }\n' % v)
+    assert L.lib.ssimx_tune_cache_load(str(f).encode()) == L.OK
+    e = _cache_entries(L, tmp_path)
+    assert e["cpu-test|a"] == 1 and e["cpu-test|b"] == 0
+    # what save writes loads back unchanged
+    again = tmp_path / "dump.json"
+    assert L.lib.ssimx_tune_cache_load(str(again).encode()) == L.OK
+    assert _cache_entries(L, tmp_path, "dump2.json") == e
+    # an empty entries object is valid and changes nothing
+    f.write_text('{"version": %d, "entries": {}}' % v)
+    assert L.lib.ssimx_tune_cache_load(str(f).encode()) == L.OK
+    assert _cache_entries(L, tmp_path, "dump3.json") == e
+
+
+@pytest.mark.parametrize("text", [
+    "",                                                   # empty file
+    "{",                                                  # truncated
+    '{"version": %(v)d, "entries": {"cpu-bad|x": 1}',     # missing closing brace
+    '{"version": %(v)d, "entries": {"cpu-bad|x": 1,}}',   # trailing comma
+    '{"version": %(v)d, "entries": {"cpu-bad|x": }}',     # missing value
+    '{"version": %(v)d, "entries": {"cpu-bad|x": abc}}',  # non-numeric value
+    '{"version": %(v)d, "entries": {"cpu-bad|x": 1.5}}',  # fractional value
+    '{"version": %(v)d, "entries": {"cpu-bad|x": -1}}',   # tile index below range
+    '{"version": %(v)d, "entries": {"cpu-bad|x": 99}}',   # tile index above range
+    '{"version": %(v)d, "entries": {"cpu-bad|x": 1234567890123}}',  # overlong number
+    '{"version": %(v)d, "entries": {"cpu-bad|x": 1, "cpu-bad|x": 2}}',  # duplicate key
+    '{"version": %(v)d, "entries": {"cpu-bad|\\"x": 1}}',  # escaped quote in a key
+    '{"version": %(v)d, "entries": {"cpu-bad|x": 1}} trailing',  # trailing garbage
+    '{"version": 1, "entries": {"cpu-bad|x": 1}}',          # another version
+    '{"entries": {"cpu-bad|x": 1}}',                        # no version
+    '{"version": %(v)d}',                                   # no entries
+    '{"version": %(v)d, "entries": {"cpu-bad|x": 1}, "extra": 1}',  # unknown member
+    '{"version": %(v)d, "entries": ["cpu-bad|x", 1]}',      # wrong container
+    '{"version": %(v)d, "entries": {"cpu-bad|x" 1}}',       # missing colon
+    '{"version": %(v)d, "entries": {cpu-bad: 1}}',          # unquoted key
+    '{"version": %(v)d, "entries": {"cpu-bad|%(long)s": 1}}',  # key too long
+])
+def test_tune_cache_rejects_malformed_files(L, tmp_path, text):
+    v = L.lib.ssimx_version()
+    before = _cache_entries(L, tmp_path, "before.json")
+    f = tmp_path / "bad.json"
+    f.write_text(text % {"v": v, "long": "k" * 200} if "%(" in text else text)
+    assert L.lib.ssimx_tune_cache_load(str(f).encode()) == L.EINVAL
+    after = _cache_entries(L, tmp_path, "after.json")
+    assert after == before and not any(k.startswith("cpu-bad") for k in after)
+
+
+def test_tune_cache_rejects_missing_binary_and_oversized_files(L, tmp_path):
+    assert L.lib.ssimx_tune_cache_load(str(tmp_path / "absent.json").encode()) == L.EINVAL
+    assert L.lib.ssimx_tune_cache_load(None) == L.EINVAL
+    b = tmp_path / "binary.json"
+    b.write_bytes(b'{"version": 100, "entries": {"cpu-bad|\x01": 1}}')
+    assert L.lib.ssimx_tune_cache_load(str(b).encode()) == L.EINVAL
+    big = tmp_path / "big.json"
+    big.write_text('{"version": 100, "entries": {' + " " * (1 << 20) + "}}")
+    assert L.lib.ssimx_tune_cache_load(str(big).encode()) == L.EINVAL
+
+
+def test_tune_cache_environment_variable(tmp_path):
+    """SSIMX_TUNE_CACHE is loaded once, before the first save/tile choice, in
+    a fresh process (the variable is read only once per process)."""
+    import subprocess
+    import sys
+    src = tmp_path / "env.json"
+    out = tmp_path / "out.json"
+    script = (
+        "import sys, json; sys.path.insert(0, %r)\n"
+        "from paper_2101_06354_amd import _lib as L\n"
+        "v = L.lib.ssimx_version()\n"
+        "open(%r, 'w').write('{\"version\": %%d, \"entries\": {\"cpu-env|k\": 2}}' %% v)\n"
+        "assert L.lib.ssimx_tune_cache_save(%r.encode()) == L.OK\n"
+        "print(json.load(open(%r))['entries'])\n" % (ROOT, str(src), str(out), str(out)))
+    env = dict(os.environ, SSIMX_TUNE_CACHE=str(src))
+    # the file is written by the child before its first save, so the save sees it
+    r = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "'cpu-env|k': 2" in r.stdout

@@ -126,6 +126,69 @@ def test_autograd_matches_direct_calls(P, dev):
     assert torch.equal(yt.grad, g)
 
 
+def test_autograd_reference_plane_gradient(P, dev):
+    """Gradients flow to both planes: the reference plane's is the adjoint with
+    the planes swapped (SSIM and MS-SSIM are symmetric), checked against the
+    oracle's adjoint of the swapped pair."""
+    x, y = synth.config1(frames=2, h=96, w=120)
+    x32, y32 = x.astype(np.float32), y.astype(np.float32)
+    xt = to_dev(x32, dev).requires_grad_(True)
+    yt = to_dev(y32, dev).requires_grad_(True)
+    cfg = P.SSIMConfig()
+    P.autograd.ssim(xt, yt, cfg).sum().backward()
+    for f in range(2):
+        _cmp(xt.grad[f].cpu().numpy(), O.ssim_pooled_backward(y[f], x[f], 1.0, oparams(cfg)), f"ssim dx {f}")
+        _cmp(yt.grad[f].cpu().numpy(), O.ssim_pooled_backward(x[f], y[f], 1.0, oparams(cfg)), f"ssim dy {f}")
+    xt.grad = None
+    yt.grad = None
+    P.autograd.ms_ssim(xt, yt, cfg, n_scales=3, renorm=True).sum().backward()
+    for f in range(2):
+        gx = O.msssim_backward(y[f], x[f], 1.0, oparams(cfg), n_scales=3, renorm=True)
+        _cmp(xt.grad[f].cpu().numpy(), gx, f"ms dx {f}")
+        gy = O.msssim_backward(x[f], y[f], 1.0, oparams(cfg), n_scales=3, renorm=True)
+        _cmp(yt.grad[f].cpu().numpy(), gy, f"ms dy {f}")
+
+
+def test_bf16_storage_fp32_adjoint_full_contract(P, dev):
+    """The BF16-storage variant of the differentiable workload: bf16 planes,
+    float32 accumulation, the float32 adjoint returned by ms_ssim_backward
+    compared with the FP64 oracle gradient of the bf16-rounded planes at the
+    float32 contract (1e-4 relative L2, 1e-3 max per pixel) and with FP64
+    central differences (h = 1e-3) at 64 random pixels."""
+    B = 4
+    r, d = synth.config4(batch=B)
+    yr = np.stack([O.rgb_to_y_bt601(bf16_round(r[b])) for b in range(B)])
+    yd = np.stack([O.rgb_to_y_bt601(bf16_round(d[b])) for b in range(B)])
+    # luma planes rounded to bf16 storage (what the kernel reads)
+    yr16, yd16 = bf16_round(yr.astype(np.float32)), bf16_round(yd.astype(np.float32))
+    xt = to_dev(yr16.astype(np.float32), dev).bfloat16()
+    yt = to_dev(yd16.astype(np.float32), dev).bfloat16()
+    assert torch.equal(xt.double().cpu(), torch.from_numpy(yr16))
+    cfg = P.SSIMConfig(L=1.0)
+    ocfg = oparams(cfg)
+    ups = (1.0, -0.25, 0.5, 2.0)
+    g = P.ms_ssim_backward(xt, yt, torch.tensor(ups, device=dev), cfg, n_scales=3, renorm=True)
+    assert g.dtype == torch.float32
+    g = g.cpu().numpy()
+    score = P.ms_ssim(xt, yt, cfg, n_scales=3, renorm=True).cpu().numpy()
+    grefs = []
+    for b in range(B):
+        ms = O.msssim(yr16[b], yd16[b], ocfg, n_scales=3, renorm=True)["score"]
+        assert abs(float(score[b]) - ms) <= 1e-6
+        grefs.append(O.msssim_backward(yr16[b], yd16[b], ups[b], ocfg, n_scales=3, renorm=True))
+        _cmp(g[b], grefs[b], f"bf16 frame {b}")
+    rng = np.random.default_rng(65)
+    for _ in range(64):
+        b = int(rng.integers(0, 2))
+        i, j = int(rng.integers(0, 512)), int(rng.integers(0, 512))
+        dp, dm = yd16[b].copy(), yd16[b].copy()
+        dp[i, j] += 1e-3
+        dm[i, j] -= 1e-3
+        f = lambda dd: ups[b] * O.msssim(yr16[b], dd, ocfg, n_scales=3, renorm=True)["score"]  # noqa: E731
+        fd = (f(dp) - f(dm)) / 2e-3
+        assert abs(g[b, i, j] - fd) <= 1e-3 * np.abs(grefs[b]).max(), (b, i, j, g[b, i, j], fd)
+
+
 def _loss_grad_oracle(r, d, cfg, B):
     """FP64 gradient of mean_b(1 - MS(Y(r_b), Y(d_b))) with respect to d."""
     out = np.empty(d.shape)

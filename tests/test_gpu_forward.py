@@ -518,3 +518,60 @@ def test_nan_and_inf_inputs_propagate(P, dev, window, k, stride):
     x[40, 40] = np.nan
     ms = P.ms_ssim(to_dev(x, dev), to_dev(d[0, 0], dev), P.SSIMConfig(L=1.0), n_scales=2, renorm=True)
     assert np.isnan(float(ms[0]))
+
+
+@pytest.mark.parametrize("kind,h,w,n_scales,path", [
+    ("u8", 270, 480, 5, "fused"), ("u8", 133, 201, 4, "fused"), ("u16", 271, 479, 5, "fused"),
+    ("u16", 97, 131, 3, "fused"), ("u8", 133, 201, 4, "reflect"), ("u16", 150, 187, 3, "box"),
+    ("u8", 131, 190, 3, "stride2")])
+def test_msssim_pyramid_levels_bit_exact(P, dev, kind, h, w, n_scales, path):
+    """The 2x2 levels msssim builds (read back from its workspace through
+    ssimx_msssim_pyramid_layout) equal the oracle's pyramid bit for bit on
+    integer planes, odd sizes floored: both from the windowed pass that writes
+    the next scale (stride-1 Gaussian, valid borders) and from the separate
+    down-sampling pass (other borders, windows and strides)."""
+    if kind == "u8":
+        x, y = synth.config1(frames=2, h=h, w=w)
+        cfg = P.SSIMConfig()
+    else:
+        x, y = synth.config2(frames=2, h=h, w=w)
+        cfg = P.SSIMConfig(L=1023.0)
+    if path == "reflect":
+        cfg = P.SSIMConfig(padding="reflect")
+    elif path == "box":
+        cfg = P.SSIMConfig(window="box", k=8, L=1023.0)
+    elif path == "stride2":
+        cfg = P.SSIMConfig(stride=2)
+    score, levels = P.ms_ssim(to_dev(x, dev), to_dev(y, dev), cfg, n_scales=n_scales, renorm=True,
+                              return_pyramid=True)
+    assert len(levels) == n_scales - 1
+    for f in range(2):
+        px, py = O.pyramid(x[f], n_scales), O.pyramid(y[f], n_scales)
+        for j, (lx, ly) in enumerate(levels, start=1):
+            gx, gy = lx[f].cpu().numpy(), ly[f].cpu().numpy()
+            assert gx.shape == (h >> j, w >> j) and px[j].shape == gx.shape
+            # exact: the oracle's FP64 means are multiples of 4^-j with <= 20 significant bits
+            assert np.array_equal(px[j].astype(np.float32).astype(np.float64), px[j])
+            np.testing.assert_array_equal(gx.astype(np.float64), px[j])
+            np.testing.assert_array_equal(gy.astype(np.float64), py[j])
+        ms = O.msssim(x[f], y[f], oparams(cfg), n_scales=n_scales, renorm=True)["score"]
+        assert abs(float(score[f]) - ms) <= SCORE_TOL
+
+
+def test_msssim_pyramid_levels_float_planes(P, dev):
+    """On float planes the windowed pass forms the next scale from the staged
+    sums u = x + y and v = x - y ((u + v) / 8 over a block), which differs from
+    the plain 2x2 mean by float32 rounding only: within 4 ulp of the level's
+    magnitude, and the MS-SSIM score stays within the pooled tolerance."""
+    r, d = synth.config4(batch=2, h=200, w=262)
+    x, y = r[:, 0], d[:, 0]
+    cfg = P.SSIMConfig(L=1.0)
+    score, levels = P.ms_ssim(to_dev(x, dev), to_dev(y, dev), cfg, n_scales=3, renorm=True, return_pyramid=True)
+    for f in range(2):
+        px, py = O.pyramid(x[f].astype(np.float64), 3), O.pyramid(y[f].astype(np.float64), 3)
+        for j, (lx, ly) in enumerate(levels, start=1):
+            for got, want in ((lx[f], px[j]), (ly[f], py[j])):
+                got = got.cpu().numpy().astype(np.float64)
+                assert np.abs(got - want).max() <= 4 * np.finfo(np.float32).eps * np.abs(want).max()
+        ms = O.msssim(x[f], y[f], oparams(cfg), n_scales=3, renorm=True)["score"]
+        assert abs(float(score[f]) - ms) <= SCORE_TOL

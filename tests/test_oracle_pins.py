@@ -425,6 +425,58 @@ def test_rgb_luma():
     np.testing.assert_allclose(O.y_grad_to_rgb_bt601(np.ones((2, 2)))[:, 0, 0], O.BT601)
 
 
+def test_rgb_luma_pure_primaries():
+    """BT.601 luma of the pure primaries (channel order R, G, B on the leading
+    axis): red 0.299, green 0.587, blue 0.114 (Kr = 0.299, Kb = 0.114,
+    Kg = 1 - Kr - Kb); a swap of any two channel weights fails here."""
+    for c, want in enumerate((0.299, 0.587, 0.114)):
+        rgb = np.zeros((3, 2, 3))
+        rgb[c] = 1.0
+        np.testing.assert_allclose(O.rgb_to_y_bt601(rgb), want, rtol=0, atol=1e-15)
+    assert abs((1 - 0.299 - 0.114) - 0.587) < 1e-15
+    # yellow = red + green, cyan = green + blue, magenta = red + blue
+    for pair, want in (((0, 1), 0.886), ((1, 2), 0.701), ((0, 2), 0.413)):
+        rgb = np.zeros((3, 1, 1))
+        rgb[list(pair)] = 1.0
+        assert abs(float(O.rgb_to_y_bt601(rgb)[0, 0]) - want) < 1e-15
+
+
+def test_rgb_luma_gradient_is_the_adjoint():
+    """<Y(rgb), g> = <rgb, Y^T g> for random planes: the gradient map is the
+    transpose of the luma map (and channel c of it is w_c g)."""
+    rng = np.random.default_rng(5)
+    rgb = rng.normal(size=(3, 7, 9))
+    g = rng.normal(size=(7, 9))
+    lhs = float(np.sum(O.rgb_to_y_bt601(rgb) * g))
+    rhs = float(np.sum(rgb * O.y_grad_to_rgb_bt601(g)))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+
+
+def test_msssim_product_one_hot_and_two_hot_weights():
+    """Product aggregation with one-hot exponents gives exactly one scale's
+    term, CS_j at scale j < M (j = 1, 2) or S_M at the coarsest, each
+    recomputed from independently block-averaged planes; two non-zero
+    exponents give CS_1^a S_M^b.  A scale/exponent mix-up fails here."""
+    rng = np.random.default_rng(43)
+    x = synth.smooth_field(rng, 100, 104, 20, 230)
+    y = np.clip(0.9 * x + 10 + rng.normal(0, 12, x.shape), 0, 255)
+    p = O.SSIMParams()
+    x1, y1 = _block2(x), _block2(y)
+    x2, y2 = _block2(x1), _block2(y1)
+    cs0 = O.ssim_map(x, y, p)["cs"].mean()
+    cs1 = O.ssim_map(x1, y1, p)["cs"].mean()
+    s2 = O.ssim_pooled(x2, y2, p)
+    assert min(abs(cs0 - cs1), abs(cs1 - s2), abs(cs0 - s2)) > 1e-3  # the three terms are distinct
+    assert abs(O.msssim(x, y, p, (1.0, 0.0, 0.0), 3)["score"] - cs0) < 1e-14
+    assert abs(O.msssim(x, y, p, (0.0, 1.0, 0.0), 3)["score"] - cs1) < 1e-14
+    assert abs(O.msssim(x, y, p, (0.0, 0.0, 1.0), 3)["score"] - s2) < 1e-14
+    a, b = 0.7, 1.9
+    got = O.msssim(x, y, p, (a, 0.0, b), 3)["score"]
+    assert abs(got - cs0 ** a * s2 ** b) < 1e-14
+    got = O.msssim(x, y, p, (0.0, a, b), 3)["score"]
+    assert abs(got - cs1 ** a * s2 ** b) < 1e-14
+
+
 @pytest.mark.parametrize("padding,stride,window,k", [("valid", 1, "gaussian", 7), ("zero", 2, "gaussian", 5),
                                                    ("reflect", 3, "gaussian", 7), ("reflect", 1, "box", 4),
                                                    ("zero", 1, "box", 3)])
