@@ -264,15 +264,19 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
           }
         }
       }
-      const T* xs = (const T*)XY[0];
-      const T* ys = (const T*)XY[1];
+      // elements read back by byte copies (well defined for any element type)
+      const char* xs = (const char*)XY[0];
+      const char* ys = (const char*)XY[1];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int py = cy + 4 * gr + j;  // wave-uniform
         if (py >= qy_end || px >= a.g.W) continue;
         // staged row 4 gr + j, column c (quads are stored row-major, 16 per row)
-        const float xv = to_f32<T>(xs[(4 * gr + j) * kTW + c]);
-        const float yv = to_f32<T>(ys[(4 * gr + j) * kTW + c]);
+        const int e = ((4 * gr + j) * kTW + c) * (int)sizeof(T);
+        T xe, ye;
+        __builtin_memcpy(&xe, xs + e, sizeof(T));
+        __builtin_memcpy(&ye, ys + e, sizeof(T));
+        const float xv = to_f32<T>(xe), yv = to_f32<T>(ye);
         // dL/dy = W^T A + (u - t_u) W^T B_u - (v - t_v) W^T B_v
         float gy = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]) - ((xv - yv) - a.tv) * G[2][j];
         if (a.coarse) {

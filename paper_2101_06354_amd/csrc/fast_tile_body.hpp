@@ -40,8 +40,8 @@ namespace fast {
 
 
 constexpr int kTW = 64;   // map columns per tile
-constexpr int kTWP = 68;  // LDS row stride of the statistics band (4 floats of padding keep rows and
-                          // map planes off a common bank)
+constexpr int kTWP = 68;  // LDS row stride of the adjoint's coefficient band (4 floats of padding keep
+                          // rows and planes off a common bank)
 constexpr int kCH = 16;   // output rows per chunk
 constexpr int kNT = 256;  // threads per block
 
@@ -52,47 +52,14 @@ struct Shape {
   static constexpr int IWP = kTW - 4 + 4 * NREAD;      // LDS row length of the footprint
   static constexpr int NQ = IWP / 4;                   // float4 quads per footprint row
   static constexpr int BAND = kCH + HALO;              // rows of the row-statistics band
-  static constexpr int PL = BAND * kTWP;               // floats per statistics map
+  static constexpr int RS = 4 * (kTW + kTW / 8);       // floats per band row: a float4 per map column,
+                                                       // one float4 of padding after every 8 columns
+  static constexpr int BANDF = BAND * RS;              // floats of the band
   static constexpr int SHIFT = K / 2 + 1;              // centring offset of an item
   static_assert(IWP >= kTW + K - 1, "footprint row too short");
   static_assert(kCH >= HALO, "band copy needs CH >= K - 1");
   static_assert(SHIFT - 3 >= 0 && SHIFT < K, "shared centring value must lie in all 4 windows");
 };
-
-// Four consecutive elements of the padded plane (zeros outside), as floats.
-template <typename T>
-__device__ __forceinline__ void load4(const T* P, int64_t pitch, const Geom& g, int vec_ok, int py, int px,
-                                      float* o) {
-  if (vec_ok && g.pad == SSIMX_PAD_VALID && py < g.H && px + 3 < g.W) {
-    const T* s = P + (int64_t)py * pitch + px;
-    if constexpr (sizeof(T) == 1) {
-      const uint32_t w = *(const uint32_t*)s;
-      o[0] = (float)(w & 0xffu);
-      o[1] = (float)((w >> 8) & 0xffu);
-      o[2] = (float)((w >> 16) & 0xffu);
-      o[3] = (float)(w >> 24);
-    } else if constexpr (sizeof(T) == 2) {
-      const uint2 w = *(const uint2*)s;
-      const T* e = (const T*)&w;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) o[i] = to_f32<T>(e[i]);
-    } else {
-      const float4 w = *(const float4*)s;
-      o[0] = w.x;
-      o[1] = w.y;
-      o[2] = w.z;
-      o[3] = w.w;
-    }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int sy, sx;
-    o[i] = padded_source(py, px + i, g.H, g.W, g.pad, g.before, g.Hp, g.Wp, sy, sx)
-               ? to_f32<T>(P[(int64_t)sy * pitch + sx])
-               : 0.f;
-  }
-}
 
 // Raw footprint quad held in registers between the global load and the LDS
 // store (4 elements in the plane's own packing), so that the load latency of
@@ -106,9 +73,19 @@ struct Quad {
 
 template <typename T>
 __device__ __forceinline__ uint32_t elem_bits(T v) {
-  if constexpr (sizeof(T) == 4) return __float_as_uint(*(const float*)&v);
-  else if constexpr (sizeof(T) == 2) return (uint32_t)(*(const uint16_t*)&v);
-  else return (uint32_t)(*(const uint8_t*)&v);
+  if constexpr (sizeof(T) == 4) {
+    uint32_t b;
+    __builtin_memcpy(&b, &v, 4);
+    return b;
+  } else if constexpr (sizeof(T) == 2) {
+    uint16_t b;
+    __builtin_memcpy(&b, &v, 2);
+    return (uint32_t)b;
+  } else {
+    uint8_t b;
+    __builtin_memcpy(&b, &v, 1);
+    return (uint32_t)b;
+  }
 }
 
 template <typename T>
@@ -145,6 +122,14 @@ __device__ __forceinline__ void fetch4(const T* P, int64_t pitch, const Geom& g,
   }
 }
 
+// A 16-bit element given as the low bits of a word, as float.
+template <typename T>
+__device__ __forceinline__ float bits16_to_f32(uint32_t b) {
+  static_assert(sizeof(T) == 2, "16-bit element types only");
+  if constexpr (std::is_same<T, bf16_t>::value) return __uint_as_float(b << 16);
+  else return (float)b;
+}
+
 template <typename T>
 __device__ __forceinline__ void unpack4(const Quad<T>& q, float* o) {
   if constexpr (sizeof(T) == 1) {
@@ -153,9 +138,10 @@ __device__ __forceinline__ void unpack4(const Quad<T>& q, float* o) {
     o[2] = (float)((q.w[0] >> 16) & 0xffu);
     o[3] = (float)(q.w[0] >> 24);
   } else if constexpr (sizeof(T) == 2) {
-    const T* e = (const T*)&q.w[0];
+    // the 16-bit elements are taken out of the words by shifts (reading the
+    // word array through a 16-bit pointer would break type-based aliasing)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = to_f32<T>(e[i]);
+    for (int i = 0; i < 4; ++i) o[i] = bits16_to_f32<T>((q.w[i >> 1] >> (16 * (i & 1))) & 0xffffu);
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i) o[i] = __uint_as_float(q.w[i]);
@@ -210,30 +196,6 @@ constexpr bool is_rgb() {
   return std::is_same<T, Rgb8>::value;
 }
 
-// Stage `nrows` footprint rows starting at padded row py0 into U, V (u = x+y,
-// v = x-y).
-template <int K, typename T>
-__device__ __forceinline__ void stage_rows(const FastArgs& a, const T* X, const T* Y, int py0, int px0, int nrows,
-                                           float* U, float* V, int ch) {
-  using S = Shape<K>;
-  for (int it = threadIdx.x; it < nrows * S::NQ; it += kNT) {
-    const int r = it / S::NQ, q = it - r * S::NQ;
-    float xv[4], yv[4];
-    if constexpr (is_rgb<T>()) {
-      Quad<Rgb8> qa, qb;
-      fetch4_rgb((const uint8_t*)X, a.x.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qa);
-      fetch4_rgb((const uint8_t*)Y, a.y.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px0 + 4 * q, qb);
-      unpack4_rgb(qa, ch, xv);
-      unpack4_rgb(qb, ch, yv);
-    } else {
-      load4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, xv);
-      load4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px0 + 4 * q, yv);
-    }
-    *(float4*)&U[r * S::IWP + 4 * q] = make_float4(xv[0] + yv[0], xv[1] + yv[1], xv[2] + yv[2], xv[3] + yv[3]);
-    *(float4*)&V[r * S::IWP + 4 * q] = make_float4(xv[0] - yv[0], xv[1] - yv[1], xv[2] - yv[2], xv[3] - yv[3]);
-  }
-}
-
 // Chunk staging split in two halves: fetch_chunk issues the global loads of
 // kCH footprint rows into registers, store_chunk converts them to u, v and
 // writes LDS.  A thread's items are fixed for the whole tile: item 0 is row
@@ -262,22 +224,51 @@ __device__ __forceinline__ bool chunk_item(int i, int& r, int& q) {
   return threadIdx.x < 64 && (threadIdx.x & 3) < ChunkItems<K>::NQ - 16;
 }
 
+// The per-thread part of a chunk load, fixed for the whole tile: the byte
+// offsets of the thread's quads from the chunk's row base, and whether each
+// quad lies inside the plane's columns and may take one vector load.
+template <int K>
+struct ChunkLoad {
+  uint32_t xo[ChunkItems<K>::PER_THREAD], yo[ChunkItems<K>::PER_THREAD];
+  bool vec[ChunkItems<K>::PER_THREAD];
+};
+
 template <int K, typename T>
-__device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const T* Y, int py0, int px0, Quad<T>* qx,
-                                            Quad<T>* qy) {
-  const bool vec = a.vec_ok && a.g.pad == SSIMX_PAD_VALID;
-  // block-uniform row bases of the chunk
-  const char* xr = (const char*)(X + (int64_t)py0 * a.x.pitch);
-  const char* yr = (const char*)(Y + (int64_t)py0 * a.y.pitch);
+__device__ __forceinline__ ChunkLoad<K> chunk_load_init(const FastArgs& a, int px0) {
+  ChunkLoad<K> cl;
   constexpr uint32_t ES = is_rgb<T>() ? 1u : (uint32_t)sizeof(T);
+  const bool vec = a.vec_ok && a.g.pad == SSIMX_PAD_VALID;
 #pragma unroll
   for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
     int r, q;
-    if (!chunk_item<K>(i, r, q)) continue;
+    const bool live = chunk_item<K>(i, r, q);
     const int px = px0 + 4 * q;
-    if (vec && py0 + r < a.g.H && px + 3 < a.g.W) {
-      const uint32_t xo = (__umul24((uint32_t)r, (uint32_t)a.x.pitch) + (uint32_t)px) * ES;
-      const uint32_t yo = (__umul24((uint32_t)r, (uint32_t)a.y.pitch) + (uint32_t)px) * ES;
+    cl.vec[i] = live && vec && px + 3 < a.g.W;
+    cl.xo[i] = (__umul24((uint32_t)r, (uint32_t)a.x.pitch) + (uint32_t)px) * ES;
+    cl.yo[i] = (__umul24((uint32_t)r, (uint32_t)a.y.pitch) + (uint32_t)px) * ES;
+  }
+  return cl;
+}
+
+// EDGE = false: the tile reads only inside the plane's columns with vector
+// loads (valid borders, aligned planes), so no element-wise border path is
+// compiled in; rows past the plane (below the last valid window) read zero.
+template <int K, typename T, bool EDGE>
+__device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const T* Y, int py0, int px0,
+                                            const ChunkLoad<K>& cl, Quad<T>* qx, Quad<T>* qy, int nrows = kCH) {
+  // block-uniform row bases of the chunk
+  const char* xr = (const char*)(X + (int64_t)py0 * a.x.pitch);
+  const char* yr = (const char*)(Y + (int64_t)py0 * a.y.pitch);
+#pragma unroll
+  for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
+    int r, q;
+    if (!chunk_item<K>(i, r, q) || r >= nrows) continue;
+    const int px = px0 + 4 * q;
+    if ((!EDGE || cl.vec[i]) && py0 + r >= a.g.H) {
+#pragma unroll
+      for (int w = 0; w < Quad<T>::NW; ++w) qx[i].w[w] = qy[i].w[w] = 0u;
+    } else if (!EDGE || cl.vec[i]) {
+      const uint32_t xo = cl.xo[i], yo = cl.yo[i];
       if constexpr (is_rgb<T>()) {
         const int64_t cs = a.cstride;
         qx[i].w[0] = *(const uint32_t*)(xr + xo);
@@ -306,6 +297,7 @@ __device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const
         qy[i].w[2] = vy.z;
         qy[i].w[3] = vy.w;
       }
+    } else if constexpr (!EDGE) {
     } else if constexpr (is_rgb<T>()) {
       fetch4_rgb((const uint8_t*)X, a.x.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px, qx[i]);
       fetch4_rgb((const uint8_t*)Y, a.y.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px, qy[i]);
@@ -317,12 +309,13 @@ __device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const
 }
 
 template <int K, typename T>
-__device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy, float* U, float* V, int ch) {
+__device__ __forceinline__ void store_chunk(const Quad<T>* qx, const Quad<T>* qy, float* U, float* V, int ch,
+                                            int nrows = kCH) {
   using S = Shape<K>;
 #pragma unroll
   for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
     int r, q;
-    if (!chunk_item<K>(i, r, q)) continue;
+    if (!chunk_item<K>(i, r, q) || r >= nrows) continue;
     float xv[4], yv[4];
     if constexpr (is_rgb<T>()) {
       unpack4_rgb(qx[i], ch, xv);
@@ -370,7 +363,6 @@ __device__ __forceinline__ void row_pass(const float* taps, const float* U, cons
                                          int band0) {
   using S = Shape<K>;
   constexpr int NG = kTW / 4;
-  constexpr int PL = S::PL;
   for (int it = threadIdx.x; it < nrows * NG; it += kNT) {
     const int r = it / NG, gq = it - r * NG;
     float u[4 * S::NREAD], v[4 * S::NREAD];
@@ -405,43 +397,52 @@ __device__ __forceinline__ void row_pass(const float* taps, const float* U, cons
       vu[j] = fmaf(-au, au, qu);
       vv[j] = fmaf(-av, av, qv);
     }
-    const int o = (band0 + r) * kTWP + 4 * gq;
-    *(float4*)&HM[o] = make_float4(hu[0], hu[1], hu[2], hu[3]);
-    *(float4*)&HM[PL + o] = make_float4(hv[0], hv[1], hv[2], hv[3]);
-    *(float4*)&HM[2 * PL + o] = make_float4(vu[0], vu[1], vu[2], vu[3]);
-    *(float4*)&HM[3 * PL + o] = make_float4(vv[0], vv[1], vv[2], vv[3]);
+    // (mean_u, mean_v, var_u, var_v) of a column side by side: the column
+    // pass reads a band row of its column with one 16-byte load.  Column p
+    // sits in slot p + p / 8, so the 8 lanes of a 16-byte store phase (4
+    // columns apart) hit distinct banks.
+    float* o = HM + (band0 + r) * S::RS + 4 * (4 * gq + gq / 2);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *(float4*)&o[4 * j] = make_float4(hu[j], hv[j], vu[j], vv[j]);
   }
 }
 
-// Move band rows [CH, CH + HALO) to [0, HALO).
+// Move band rows [CH, CH + HALO) to [0, HALO): HALO contiguous rows of
+// float4, dealt round-robin to the threads (a thread's copies are the same for
+// every chunk of the tile).
+template <int K>
+struct BandCopy {
+  static constexpr int N = Shape<K>::HALO * Shape<K>::RS / 4;  // float4 copies
+  static constexpr int PER = (N + kNT - 1) / kNT;
+};
+
 template <int K>
 __device__ __forceinline__ void band_shift(float* HM) {
-  using S = Shape<K>;
-  constexpr int NV = S::HALO * kTW / 4;  // float4 per map
-  for (int it = threadIdx.x; it < 4 * NV; it += kNT) {
-    const int m = it / NV, e = it - m * NV;
-    const int row = e / (kTW / 4), q = e % (kTW / 4);
-    *(float4*)&HM[m * S::PL + row * kTWP + 4 * q] = *(const float4*)&HM[m * S::PL + (kCH + row) * kTWP + 4 * q];
+  using B = BandCopy<K>;
+  float4* d = (float4*)HM;
+#pragma unroll
+  for (int i = 0; i < B::PER; ++i) {
+    const int it = threadIdx.x + i * kNT;
+    if ((i + 1) * kNT <= B::N || it < B::N) d[it] = d[it + kCH * Shape<K>::RS / 4];
   }
 }
 
 
 template <int K>
 __host__ __device__ constexpr int fast_smem_floats() {
-  return 2 * kCH * Shape<K>::IWP + 4 * Shape<K>::PL;
+  return 2 * kCH * Shape<K>::IWP + Shape<K>::BANDF;
 }
 
 // One map tile: returns this thread's share of the tile's pooled sum (EPI 0:
 // forward; EPI 2: forward that also writes the 2x2 means of its input to
 // a.ds_x, a.ds_y) or 0 (EPI 1: adjoint coefficients).  `smem` holds
 // fast_smem_floats<K>() floats.
-template <int K, typename T, int EPI>
-__device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, int tile, float* smem) {
+template <int K, typename T, int EPI, bool EDGE>
+__device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int frame, int tile, float* smem) {
   using S = Shape<K>;
   float* U = smem;
   float* V = U + kCH * S::IWP;
   float* HM = V + kCH * S::IWP;
-  constexpr int PL = S::PL;
 
   const int tyi = tile / a.g.tiles_x, txi = tile - tyi * a.g.tiles_x;
   // block-uniform tile origin and chunk-loop bound (scalar loop control)
@@ -461,7 +462,10 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
   const int own_c1 = txi == a.g.tiles_x - 1 ? a.g.W : ox0 + kTW;
 
   // prologue: the first K-1 footprint rows
-  stage_rows<K, T>(a, X, Y, oy0, ox0, S::HALO, U, V, ch);
+  Quad<T> qx[ChunkItems<K>::PER_THREAD], qy[ChunkItems<K>::PER_THREAD];
+  const ChunkLoad<K> cl = chunk_load_init<K, T>(a, ox0);
+  fetch_chunk<K, T, EDGE>(a, X, Y, oy0, ox0, cl, qx, qy, S::HALO);
+  store_chunk<K, T>(qx, qy, U, V, ch, S::HALO);
   __syncthreads();
   if constexpr (down) emit_down<K>(a, U, V, oy0, S::HALO, ox0, oy0, own_r1, own_c1, frame);
   row_pass<K>(taps, U, V, S::HALO, HM, 0);
@@ -469,9 +473,9 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
   const float gframe = (EPI == 1 && !a.grad_map) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
   const float gl_frame = (EPI == 1 && a.mode == 3) ? a.gscale2[(int64_t)frame * a.gscale2_stride] * a.gmul : 0.f;
   float acc = 0.f;
+  const float c1x2 = 2.f * a.C1, c2x2 = 2.f * a.C2;
   const int oy_end = __builtin_amdgcn_readfirstlane(min(a.g.Ho, oy0 + a.g.TH));
-  Quad<T> qx[ChunkItems<K>::PER_THREAD], qy[ChunkItems<K>::PER_THREAD];
-  fetch_chunk<K, T>(a, X, Y, oy0 + S::HALO, ox0, qx, qy);
+  fetch_chunk<K, T, EDGE>(a, X, Y, oy0 + S::HALO, ox0, cl, qx, qy);
   for (int cy = oy0; cy < oy_end; cy += kCH) {
     __syncthreads();  // U, V free; band rows [0, HALO) ready
     store_chunk<K, T>(qx, qy, U, V, ch);
@@ -479,11 +483,11 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
     // passes run (the registers were just staged; with down-sampling, after
     // the 2x2 means are written, which keeps those registers free for it)
     if constexpr (!down)
-      if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
+      if (cy + kCH < oy_end) fetch_chunk<K, T, EDGE>(a, X, Y, cy + kCH + S::HALO, ox0, cl, qx, qy);
     __syncthreads();
     if constexpr (down) {
       emit_down<K>(a, U, V, cy + S::HALO, kCH, ox0, oy0, own_r1, own_c1, frame);
-      if (cy + kCH < oy_end) fetch_chunk<K, T>(a, X, Y, cy + kCH + S::HALO, ox0, qx, qy);
+      if (cy + kCH < oy_end) fetch_chunk<K, T, EDGE>(a, X, Y, cy + kCH + S::HALO, ox0, cl, qx, qy);
     }
     row_pass<K>(taps, U, V, kCH, HM, S::HALO);
     __syncthreads();
@@ -495,16 +499,18 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
     {
       const int gr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
       const int oj = ox0 + c;
+      const bool col_in = oj < a.g.Wo;
       const uint32_t cb = 4u * (uint32_t)oj;  // byte offset of the lane's column in a float row
-      const float* hu_ = HM + 4 * gr * kTWP + c;
-      const float Tu = hu_[S::SHIFT * kTWP], Tv = hu_[PL + S::SHIFT * kTWP];
+      const float4* hb = (const float4*)(HM + 4 * gr * S::RS) + (c + c / 8);  // (mean_u, mean_v, var_u, var_v)
+      const float Tu = hb[S::SHIFT * (S::RS / 4)].x, Tv = hb[S::SHIFT * (S::RS / 4)].y;
       float Mu[4] = {0.f, 0.f, 0.f, 0.f}, Mv[4] = {0.f, 0.f, 0.f, 0.f};
       float Su[4] = {0.f, 0.f, 0.f, 0.f}, Sv[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int m = 0; m < K + 3; ++m) {
-        const float du = hu_[m * kTWP] - Tu, dv = hu_[PL + m * kTWP] - Tv;
-        const float su = fmaf(du, du, hu_[2 * PL + m * kTWP]);
-        const float sv = fmaf(dv, dv, hu_[3 * PL + m * kTWP]);
+        const float4 h = hb[m * (S::RS / 4)];
+        const float du = h.x - Tu, dv = h.y - Tv;
+        const float su = fmaf(du, du, h.z);
+        const float sv = fmaf(dv, dv, h.w);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int t = m - j;
@@ -517,21 +523,35 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
           }
         }
       }
+      // value epilogue, with the (uniform) mode resolved once per chunk
+      auto values = [&](auto mode_c) {
+        constexpr int M = decltype(mode_c)::value;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int oi = cy + 4 * gr + j;  // wave-uniform
-        if (oi >= oy_end || oj >= a.g.Wo) continue;
-        const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
-        const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
-        const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
-        if constexpr (EPI != 1) {
-          const float val = ssim_value(t, a.mode);
+        for (int j = 0; j < 4; ++j) {
+          const int oi = cy + 4 * gr + j;  // wave-uniform
+          if (oi >= oy_end || !col_in) continue;
+          const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
+          const float val = ssim_value_uv_m<M>(Tu + Mu[j], Tv + Mv[j], var_u, var_v, c1x2, c2x2);
           if (a.map) {
             char* row = (char*)(a.map + (int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch);
             *(float*)(row + cb) = val;
           }
           acc += val;
-        } else {
+        }
+      };
+      if constexpr (EPI != 1) {
+        if (a.mode == 1) values(std::integral_constant<int, 1>{});
+        else if (a.mode == 3) values(std::integral_constant<int, 3>{});
+        else values(std::integral_constant<int, 0>{});
+      }
+#pragma unroll
+      for (int j = 0; j < 4 && EPI == 1; ++j) {
+        const int oi = cy + 4 * gr + j;  // wave-uniform
+        if (oi >= oy_end || !col_in) continue;
+        const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
+        const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
+        {
+          const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
           float g = gframe;
           if (a.grad_map) {
             const char* row = (const char*)(a.grad_map + (int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch);
@@ -576,6 +596,18 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
   return acc;
 }
 
+
+// A tile whose footprint columns lie inside an aligned plane with valid
+// borders takes the body without the element-wise border path (the common
+// case); edge tiles, other borders and unaligned planes take the full one.
+// The choice is uniform over the workgroup.
+template <int K, typename T, int EPI>
+__device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, int tile, float* smem) {
+  const int txi = tile % a.g.tiles_x;
+  const bool interior = a.vec_ok && a.g.pad == SSIMX_PAD_VALID && txi * kTW + Shape<K>::IWP <= a.g.W;
+  return interior ? fast_stats_tile_body<K, T, EPI, false>(a, frame, tile, smem)
+                  : fast_stats_tile_body<K, T, EPI, true>(a, frame, tile, smem);
+}
 
 }  // namespace fast
 }  // namespace ssimx

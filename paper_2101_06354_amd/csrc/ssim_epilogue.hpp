@@ -48,6 +48,34 @@ __device__ __forceinline__ float ssim_value(const SsimTerms& t, int mode) {
   return fmaf(-n, __builtin_amdgcn_rcpf(t.B1 * t.B2), 1.f);
 }
 
+// The same Q (mode 0), cs (mode 1) or l (mode 3) straight from the u, v
+// statistics, with the numerator and denominator of l and of cs both doubled
+// (a ratio does not change): with a = mu_u^2, b = mu_v^2,
+//   B1 = a + b + 2 C1,  A1 = B1 - 2 b,  B2 = var_u + 2 C2 + var_v,  A2 = B2 - 2 var_v,
+//   1 - Q = 2 (b A2 + var_v B1) / (B1 B2),
+// which needs neither A1 nor the halvings.  x == y still gives b = var_v = 0
+// and Q == 1.0f exactly, and swapping x and y leaves b and var_v unchanged.
+// c1x2 = 2 C1, c2x2 = 2 C2.
+template <int MODE>
+__device__ __forceinline__ float ssim_value_uv_m(float mean_u, float mean_v, float var_u, float var_v, float c1x2,
+                                                 float c2x2) {
+  const float b = mean_v * mean_v;
+  const float s = var_u + c2x2;
+  if constexpr (MODE == 1) return fmaf(-2.f * var_v, __builtin_amdgcn_rcpf(s + var_v), 1.f);
+  const float B1 = fmaf(mean_u, mean_u, b) + c1x2;
+  if constexpr (MODE == 3) return fmaf(-2.f * b, __builtin_amdgcn_rcpf(B1), 1.f);
+  const float B2 = s + var_v, A2 = s - var_v;
+  const float n = fmaf(b, A2, var_v * B1);
+  return fmaf(n, -2.f * __builtin_amdgcn_rcpf(B1 * B2), 1.f);
+}
+
+__device__ __forceinline__ float ssim_value_uv(float mean_u, float mean_v, float var_u, float var_v, float c1x2,
+                                               float c2x2, int mode) {
+  if (mode == 1) return ssim_value_uv_m<1>(mean_u, mean_v, var_u, var_v, c1x2, c2x2);
+  if (mode == 3) return ssim_value_uv_m<3>(mean_u, mean_v, var_u, var_v, c1x2, c2x2);
+  return ssim_value_uv_m<0>(mean_u, mean_v, var_u, var_v, c1x2, c2x2);
+}
+
 // Same terms from exact integer window sums of a k x k rectangular window
 // (the statistics of the integral-image method): every numerator below is an
 // exact integer and is rounded to float once.

@@ -209,9 +209,8 @@ __device__ __forceinline__ float strided_tile(const FastArgs& a, int frame, int 
         Sv = fmaf(taps[m], fmaf(dv, dv, h[3 * Sh::PLB + m * Sh::BWP]), Sv);
       }
       if (oi >= oy_end || oj >= a.g.Wo) continue;
-      const SsimTerms t =
-          ssim_terms_uv(Tu + Mu, Tv + Mv, fmaf(-Mu, Mu, Su), fmaf(-Mv, Mv, Sv), a.C1, a.C2);
-      const float val = ssim_value(t, a.mode);
+      const float val = ssim_value_uv(Tu + Mu, Tv + Mv, fmaf(-Mu, Mu, Su), fmaf(-Mv, Mv, Sv), 2.f * a.C1,
+                                      2.f * a.C2, a.mode);
       if (a.map) a.map[(int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + oj] = val;
       acc += val;
     }
