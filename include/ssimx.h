@@ -63,7 +63,9 @@ typedef enum {
   SSIMX_EWORKSPACE = -4, /* ws is NULL or ws_bytes below ssimx_workspace_size() */
   SSIMX_EHIP = -5,       /* a HIP runtime call failed; see ssimx_last_hip_error() */
   SSIMX_ENOTSUP = -6,    /* valid but unsupported combination */
-  SSIMX_ENOMEM = -7      /* plan creation could not allocate */
+  SSIMX_ENOMEM = -7,     /* plan creation could not allocate */
+  SSIMX_ESCRATCH = -8    /* ssim_pooled_noalloc: the call needs more scratch than
+                            its static per-device buffer holds */
 } ssimx_status;
 
 typedef enum { SSIMX_U8 = 0, SSIMX_U16 = 1, SSIMX_F32 = 2, SSIMX_BF16 = 3 } ssimx_dtype;
@@ -150,6 +152,21 @@ ssimx_status ssim_map(const ssimx_params* p, const ssimx_image* ref, const ssimx
 /* Mean SSIM per frame pair, without writing the map.  score_out: float32 [batch]. */
 ssimx_status ssim_pooled(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
                          float* score_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ssim_pooled for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same scores as ssim_pooled, without a workspace argument.  The scratch
+ * ssim_pooled would take from `ws` comes from one static device buffer of
+ * ssimx_noalloc_scratch_bytes() bytes (8 MiB) per GPU, held from the first
+ * call on that GPU until the process ends; a call whose ssimx_workspace_size
+ * (SSIMX_OP_POOLED) exceeds it returns SSIMX_ESCRATCH before any launch.  The
+ * call allocates no memory of any kind.  It runs on the calling thread's
+ * current device, and `stream` must belong to that device.  Every call on a
+ * GPU shares that GPU's buffer: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller. */
+ssimx_status ssim_pooled_noalloc(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                                 float* score_out, void* stream);
+size_t ssimx_noalloc_scratch_bytes(void);
 
 /* MS-SSIM over n_scales (1..8) dyadic scales built by 2x2 averaging (odd
  * sizes floored).  weights: HOST float [n_scales] exponents.

@@ -1,7 +1,7 @@
 """ctypes declarations of libssimx.so (include/ssimx.h).
 
 Argument marshalling only: every computation runs in the HIP library.  The
-library must have been built (``python -m paper_2101_06354_amd.build_lib``);
+library must have been built (``python paper_2101_06354_amd/build_lib.py``);
 importing this module without it raises ImportError -- there is no fallback.
 """
 from __future__ import annotations
@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libssimx.so")
 
 # status codes
-OK, EINVAL, EDTYPE, ETOOSMALL, EWORKSPACE, EHIP, ENOTSUP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, EDTYPE, ETOOSMALL, EWORKSPACE, EHIP, ENOTSUP, ENOMEM, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8
 # dtypes
 U8, U16, F32, BF16 = 0, 1, 2, 3
 # windows / algorithms / padding
@@ -75,6 +75,8 @@ _SIGS = {
     "msssim": (c_int, [_P, _F, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ssimx_msssim_pyramid_layout": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, POINTER(c_int64),
                                             POINTER(c_int64), POINTER(c_int), POINTER(c_int)]),
+    "ssim_pooled_noalloc": (c_int, [_P, _I, _I, c_int, c_void_p, c_void_p]),
+    "ssimx_noalloc_scratch_bytes": (c_size_t, []),
     "ssim_map_backward": (c_int, [_P, _I, _I, c_int, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_int64,
                                   c_void_p, c_size_t, c_void_p]),
     "ssim_pooled_backward": (c_int, [_P, _I, _I, c_int, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_size_t,

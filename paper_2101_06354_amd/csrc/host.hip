@@ -668,6 +668,7 @@ const char* ssimx_strerror(int status) {
     case SSIMX_EHIP: return "HIP runtime error";
     case SSIMX_ENOTSUP: return "unsupported parameter combination";
     case SSIMX_ENOMEM: return "out of memory";
+    case SSIMX_ESCRATCH: return "call needs more scratch than the static no-allocation buffer holds";
     default: return "unknown status";
   }
 }

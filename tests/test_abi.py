@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "ssimx.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:ssimx_status|const char\*|int)\s+([a-z_0-9]+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:ssimx_status|const char\*|int|size_t)\s+([a-z_0-9]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
@@ -439,3 +439,24 @@ def test_tune_cache_environment_variable(tmp_path):
     r = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     assert "'cpu-env|k': 2" in r.stdout
+
+
+def test_noalloc_entry_refuses_on_the_host(L):
+    """ssim_pooled_noalloc validates like ssim_pooled and refuses, before any
+    launch, a call whose scratch would exceed its static buffer."""
+    p = _params(L)
+    sc = ctypes.c_void_p(8192)
+    im = L.Image(4096, L.U8, 64, 64, 64, 4096)
+    assert L.lib.ssimx_noalloc_scratch_bytes() == 8 << 20
+    assert L.lib.ssim_pooled_noalloc(ctypes.byref(p), ctypes.byref(im), ctypes.byref(im), 1, None, None) == L.EINVAL
+    assert L.lib.ssim_pooled_noalloc(ctypes.byref(p), ctypes.byref(im), ctypes.byref(im), 65536, sc,
+                                     None) == L.EINVAL
+    tiny = L.Image(4096, L.U8, 8, 8, 8, 64)
+    assert L.lib.ssim_pooled_noalloc(ctypes.byref(p), ctypes.byref(tiny), ctypes.byref(tiny), 1, sc,
+                                     None) == L.ETOOSMALL
+    # five uint32 integral images of a 1080p frame (~41 MB) exceed the 8 MiB buffer
+    big = L.Image(4096, L.U8, 1920, 1080, 1920, 1920 * 1080)
+    pb = _params(L, window=L.WIN_BOX, k=8, algo=L.ALGO_INTEGRAL_IMAGE)
+    assert L.lib.ssim_pooled_noalloc(ctypes.byref(pb), ctypes.byref(big), ctypes.byref(big), 1, sc,
+                                     None) == L.ESCRATCH
+    assert L.lib.ssimx_strerror(L.ESCRATCH).decode().startswith("call needs more scratch")
