@@ -253,6 +253,44 @@ __device__ __forceinline__ ChunkLoad<K> chunk_load_init(const FastArgs& a, int p
 // EDGE = false: the tile reads only inside the plane's columns with vector
 // loads (valid borders, aligned planes), so no element-wise border path is
 // compiled in; rows past the plane (below the last valid window) read zero.
+// One quad of 4 elements (the R, G, B words for RGB sources) with vector
+// loads from p (aligned).
+template <typename T>
+__device__ __forceinline__ Quad<T> load_quad(const char* p, int64_t cs) {
+  Quad<T> q;
+  if constexpr (is_rgb<T>()) {
+    q.w[0] = *(const uint32_t*)p;
+    q.w[1] = *(const uint32_t*)(p + cs);
+    q.w[2] = *(const uint32_t*)(p + 2 * cs);
+  } else if constexpr (sizeof(T) == 1) {
+    q.w[0] = *(const uint32_t*)p;
+  } else if constexpr (sizeof(T) == 2) {
+    const uint2 v = *(const uint2*)p;
+    q.w[0] = v.x;
+    q.w[1] = v.y;
+  } else {
+    const uint4 v = *(const uint4*)p;
+    q.w[0] = v.x;
+    q.w[1] = v.y;
+    q.w[2] = v.z;
+    q.w[3] = v.w;
+  }
+  return q;
+}
+
+template <typename T>
+__device__ __forceinline__ Quad<T> zero_quad() {
+  Quad<T> q;
+#pragma unroll
+  for (int w = 0; w < Quad<T>::NW; ++w) q.w[w] = 0u;
+  return q;
+}
+
+// EDGE = false: the tile reads only inside the plane's columns with vector
+// loads (valid borders, aligned planes), so no element-wise border path is
+// compiled in; rows past the plane (below the last valid window) read zero.
+// Every branch yields whole quad values that are stored once (stores to the
+// register arrays from several branches would keep them out of registers).
 template <int K, typename T, bool EDGE>
 __device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const T* Y, int py0, int px0,
                                             const ChunkLoad<K>& cl, Quad<T>* qx, Quad<T>* qy, int nrows = kCH) {
@@ -263,48 +301,24 @@ __device__ __forceinline__ void fetch_chunk(const FastArgs& a, const T* X, const
   for (int i = 0; i < ChunkItems<K>::PER_THREAD; ++i) {
     int r, q;
     if (!chunk_item<K>(i, r, q) || r >= nrows) continue;
-    const int px = px0 + 4 * q;
-    if ((!EDGE || cl.vec[i]) && py0 + r >= a.g.H) {
-#pragma unroll
-      for (int w = 0; w < Quad<T>::NW; ++w) qx[i].w[w] = qy[i].w[w] = 0u;
-    } else if (!EDGE || cl.vec[i]) {
-      const uint32_t xo = cl.xo[i], yo = cl.yo[i];
-      if constexpr (is_rgb<T>()) {
-        const int64_t cs = a.cstride;
-        qx[i].w[0] = *(const uint32_t*)(xr + xo);
-        qx[i].w[1] = *(const uint32_t*)(xr + cs + xo);
-        qx[i].w[2] = *(const uint32_t*)(xr + 2 * cs + xo);
-        qy[i].w[0] = *(const uint32_t*)(yr + yo);
-        qy[i].w[1] = *(const uint32_t*)(yr + cs + yo);
-        qy[i].w[2] = *(const uint32_t*)(yr + 2 * cs + yo);
-      } else if constexpr (sizeof(T) == 1) {
-        qx[i].w[0] = *(const uint32_t*)(xr + xo);
-        qy[i].w[0] = *(const uint32_t*)(yr + yo);
-      } else if constexpr (sizeof(T) == 2) {
-        const uint2 vx = *(const uint2*)(xr + xo), vy = *(const uint2*)(yr + yo);
-        qx[i].w[0] = vx.x;
-        qx[i].w[1] = vx.y;
-        qy[i].w[0] = vy.x;
-        qy[i].w[1] = vy.y;
-      } else {
-        const uint4 vx = *(const uint4*)(xr + xo), vy = *(const uint4*)(yr + yo);
-        qx[i].w[0] = vx.x;
-        qx[i].w[1] = vx.y;
-        qx[i].w[2] = vx.z;
-        qx[i].w[3] = vx.w;
-        qy[i].w[0] = vy.x;
-        qy[i].w[1] = vy.y;
-        qy[i].w[2] = vy.z;
-        qy[i].w[3] = vy.w;
+    Quad<T> nx = zero_quad<T>(), ny = zero_quad<T>();
+    if (!EDGE || cl.vec[i]) {
+      if (py0 + r < a.g.H) {
+        nx = load_quad<T>(xr + cl.xo[i], a.cstride);
+        ny = load_quad<T>(yr + cl.yo[i], a.cstride);
       }
-    } else if constexpr (!EDGE) {
-    } else if constexpr (is_rgb<T>()) {
-      fetch4_rgb((const uint8_t*)X, a.x.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px, qx[i]);
-      fetch4_rgb((const uint8_t*)Y, a.y.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px, qy[i]);
-    } else {
-      fetch4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px, qx[i]);
-      fetch4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px, qy[i]);
+    } else if constexpr (EDGE) {
+      const int px = px0 + 4 * q;
+      if constexpr (is_rgb<T>()) {
+        fetch4_rgb((const uint8_t*)X, a.x.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px, nx);
+        fetch4_rgb((const uint8_t*)Y, a.y.pitch, a.cstride, a.g, a.vec_ok, py0 + r, px, ny);
+      } else {
+        fetch4<T>(X, a.x.pitch, a.g, a.vec_ok, py0 + r, px, nx);
+        fetch4<T>(Y, a.y.pitch, a.g, a.vec_ok, py0 + r, px, ny);
+      }
     }
+    qx[i] = nx;
+    qy[i] = ny;
   }
 }
 
