@@ -501,13 +501,24 @@ def _variants_c4(P, dev, stream, rec):
     rt = torch.from_numpy(r4).to(dev)
     dt = torch.from_numpy(d4).to(dev).requires_grad_(True)
     c4 = P.SSIMConfig(L=1.0)
+    px = 16 * 512 * 512
 
-    def step():
+    def step(loss_fn):
         dt.grad = None
-        loss = P.autograd.ms_ssim_loss_rgb(rt, dt, c4, n_scales=3, renorm=True)
+        loss = loss_fn(rt, dt, c4, n_scales=3, renorm=True)
         loss.backward()
-    ms = _time(step, stream=stream)
-    rec("c4_msssim_loss_fwd_bwd", ms, 16 * 512 * 512, "16x3x512x512 f32 RGB, BT.601 luma, 3 scales, fwd+bwd")
+    ms = _time(lambda: step(P.autograd.ms_ssim_loss_rgb), stream=stream)
+    rec("c4_msssim_loss_fwd_bwd", ms, px, "16x3x512x512 f32 RGB, BT.601 luma, 3 scales, loss + gradient "
+        "(autograd: one graph replay of a cached loss plan, then the upstream scaling)")
+    plan = P.LossPlan(c4, torch.float32, 16, 512, 512, device=dev)
+    ms = _time(lambda: plan.run(rt, dt.detach()), stream=stream)
+    rec("c4_msssim_loss_plan_replay", ms, px, "the same loss and gradient, one LossPlan graph replay per step")
+    plan.close()
+    ms = _time(lambda: P.msssim_loss_rgb(rt, dt.detach(), c4), stream=stream)
+    rec("c4_msssim_loss_eager_call", ms, px, "the same loss and gradient, one eager library call per step")
+    ms = _time(lambda: step(P.autograd.ms_ssim_loss_rgb_composed), stream=stream)
+    rec("c4_msssim_loss_composed", ms, px, "the same loss from the separate differentiable pieces (luma, "
+        "MS-SSIM, torch mean) under autograd")
 
 
 if __name__ == "__main__":

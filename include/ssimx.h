@@ -421,6 +421,47 @@ ssimx_status ssimx_plan_destroy(ssimx_plan* plan);
 /* Host: number of (pair, tile) work items and persistent blocks of a plan. */
 ssimx_status ssimx_plan_info(const ssimx_plan* plan, int* n_items, int* n_blocks);
 
+/* ---------------- differentiable MS-SSIM loss (training objective) ---------
+ * The use of MS-SSIM as a training objective (Off-the-shelf Performance
+ * subsection) in one call: BT.601 luma Y = 0.299 R + 0.587 G + 0.114 B of two
+ * planar RGB batches (dtype SSIMX_F32 or SSIMX_BF16; element (b, c, r, x) at
+ * b * batch_stride + c * channel_stride + r * pitch + x, strides in elements),
+ * MS-SSIM of the luma planes with msssim's weights / n_scales / flags
+ * semantics, and
+ *   loss_out[0] = (1 / batch) sum_b (1 - MS-SSIM_b)      (device float [1]),
+ * score_out (nullable, device float [batch]) the per-frame MS-SSIM, and
+ * grad_rgb (nullable) d loss / d dis_rgb in grad_dtype (SSIMX_F32 or
+ * SSIMX_BF16, rounded to nearest even), same layout rules with grad_pitch,
+ * grad_channel_stride, grad_batch_stride.  The gradient is msssim_backward's
+ * adjoint (moments recomputed) through the luma map; nothing is kept between
+ * calls.  Workspace: ssimx_msssim_loss_workspace_size (any grad_dtype). */
+ssimx_status ssimx_msssim_loss_workspace_size(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                              int dtype, int width, int height, int batch, size_t* bytes);
+ssimx_status ssimx_msssim_loss_rgb(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                   const void* ref_rgb, const void* dis_rgb, int dtype, int width, int height,
+                                   int64_t pitch, int64_t channel_stride, int64_t batch_stride, int batch,
+                                   float* loss_out, float* score_out, void* grad_rgb, int grad_dtype,
+                                   int64_t grad_pitch, int64_t grad_channel_stride, int64_t grad_batch_stride,
+                                   void* ws, size_t ws_bytes, void* stream);
+
+/* A loss plan: the same computation for one shape, replayed as one HIP graph.
+ * Create allocates the plan's workspace and a device argument block (and a
+ * small pinned ring); the first run with and the first run without a
+ * gradient each capture the launches once.  Every run copies its pointers
+ * and strides into the argument block (one asynchronous host-to-device copy on
+ * `stream`, ordered before the graph), so new tensors need no new capture.
+ * Results equal ssimx_msssim_loss_rgb's bit for bit.  Runs of one plan must be
+ * issued on one stream (or otherwise serialised): they share the plan's
+ * workspace and argument block.  Destroy after the last run has completed. */
+typedef struct ssimx_loss_plan ssimx_loss_plan;
+ssimx_status ssimx_loss_plan_create(const ssimx_params* p, const float* weights, int n_scales, int flags, int dtype,
+                                    int grad_dtype, int width, int height, int batch, ssimx_loss_plan** out);
+ssimx_status ssimx_loss_plan_run(ssimx_loss_plan* plan, const void* ref_rgb, const void* dis_rgb, int64_t pitch,
+                                 int64_t channel_stride, int64_t batch_stride, float* loss_out, float* score_out,
+                                 void* grad_rgb, int64_t grad_pitch, int64_t grad_channel_stride,
+                                 int64_t grad_batch_stride, void* stream);
+ssimx_status ssimx_loss_plan_destroy(ssimx_loss_plan* plan);
+
 /* ---------------- autotuning ----------------------------------------------
  * Times the candidate tile shapes of the forward kernel for (params, dtype,
  * width, height, batch) on `stream` (allocating and freeing its own scratch

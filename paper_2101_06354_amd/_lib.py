@@ -117,6 +117,16 @@ _SIGS = {
     "ssimx_msssim3d_workspace_size": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, c_int, POINTER(c_size_t)]),
     "ssimx_msssim3d": (c_int, [_P, c_int, _F, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_void_p, c_size_t,
                                c_void_p]),
+    "ssimx_msssim_loss_workspace_size": (c_int, [_P, _F, c_int, c_int, c_int, c_int, c_int, c_int,
+                                                 POINTER(c_size_t)]),
+    "ssimx_msssim_loss_rgb": (c_int, [_P, _F, c_int, c_int, c_void_p, c_void_p, c_int, c_int, c_int, c_int64,
+                                      c_int64, c_int64, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int64,
+                                      c_int64, c_int64, c_void_p, c_size_t, c_void_p]),
+    "ssimx_loss_plan_create": (c_int, [_P, _F, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
+                                       POINTER(c_void_p)]),
+    "ssimx_loss_plan_run": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p,
+                                    c_void_p, c_int64, c_int64, c_int64, c_void_p]),
+    "ssimx_loss_plan_destroy": (c_int, [c_void_p]),
     "ssimx_strerror": (c_char_p, [c_int]),
     "ssimx_last_hip_error": (c_int, []),
     "ssimx_version": (c_int, []),

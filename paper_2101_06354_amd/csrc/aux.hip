@@ -210,7 +210,6 @@ int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w
 }
 
 // BT.601 luma of planar RGB and its adjoint.
-constexpr float kBt601R = 0.299f, kBt601G = 0.587f, kBt601B = 0.114f;
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void rgb_to_luma_kernel(const T* rgb, int W, int H, int64_t pitch, int64_t cstride,

@@ -449,12 +449,7 @@ static SsimBwdLayout ssim_bwd_layout(const ssimx_params* p, int W, int H, int ba
   return L;
 }
 
-struct MsBwdLayout {
-  MsLayout fwd;
-  size_t msval, up, up2, coef, gpad, glev[MAX_SCALES], total;
-};
-
-static MsBwdLayout ms_bwd_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int M) {
+MsBwdLayout ms_bwd_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int M) {
   MsBwdLayout L{};
   L.fwd = ms_layout(p, dtype, W, H, batch, M);
   Ws ws;
@@ -539,6 +534,21 @@ static ssimx_status ms_bwd_impl(const ssimx_params* p, const float* weights, int
     vals = (const float*)(base + L.fwd.vals_off);
     msv = (const float*)(base + L.msval);
   }
+  return ms_bwd_levels(p, w, n_scales, flags, ref, dis, batch, vals, msv, grad_score, grad_dis, grad_pitch,
+                       grad_batch_stride, base, L, st);
+}
+
+// The per-scale part of the MS-SSIM adjoint, once the workspace holds the
+// pyramid levels (L.fwd) of a forward on these planes: the upstream of every
+// scale's pooled term from the per-scale values `vals` [batch][M], the scores
+// `msv` [batch] and dL/dscore `grad_score`, then coefficients and the
+// transposed window from the coarsest scale down, each finer scale adding the
+// 2x2 transpose of the coarser gradient.
+ssimx_status ms_bwd_levels(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
+                           const ssimx_image* dis, int batch, const float* vals, const float* msv,
+                           const float* grad_score, float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
+                           char* base, const MsBwdLayout& L, hipStream_t st) {
+  ssimx_status s;
   UpArgs u{};
   for (int j = 0; j < n_scales; ++j) {
     int Wo, Ho;

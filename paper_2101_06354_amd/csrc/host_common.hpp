@@ -57,6 +57,19 @@ struct MsLayout {
 };
 MsLayout ms_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int n_scales);
 
+// MS-SSIM adjoint workspace: the forward's layout, then the score, the
+// per-scale upstreams, the coefficient planes, the padded gradient and the
+// per-scale gradients.
+struct MsBwdLayout {
+  MsLayout fwd;
+  size_t msval, up, up2, coef, gpad, glev[MAX_SCALES], total;
+};
+MsBwdLayout ms_bwd_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int M);
+ssimx_status ms_bwd_levels(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
+                           const ssimx_image* dis, int batch, const float* vals, const float* msv,
+                           const float* grad_score, float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
+                           char* base, const MsBwdLayout& L, hipStream_t st);
+
 // ds_x, ds_y (nullable): also write the 2x2-average down-sampled planes
 // float32 [batch][H/2][W/2] (fused into the stride-1 band kernel when it runs
 // with valid borders, else a separate down-sampling launch).

@@ -13,6 +13,8 @@ constexpr int KMAX_GAUSS = 41;  // largest Gaussian window (odd)
 constexpr int KMAX_BOX = 64;    // largest rectangular window
 constexpr int BLOCK = 256;      // threads per block of the tiled kernels
 constexpr int MAX_SCALES = 8;
+// BT.601 luma weights of the differentiable-loss workload (R, G, B).
+constexpr float kBt601R = 0.299f, kBt601G = 0.587f, kBt601B = 0.114f;
 // Launch limits checked on the host before any launch: frames go on grid.y
 // (65535 at most; the colour path puts 3 channel frames per RGB frame
 // there), and per-plane element grids are formed in 32-bit ints.

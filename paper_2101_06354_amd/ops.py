@@ -466,6 +466,100 @@ def num_tile_configs() -> int:
     return L.lib.ssimx_num_tile_configs()
 
 
+def _rgb(t: torch.Tensor) -> torch.Tensor:
+    t = t.unsqueeze(0) if t.dim() == 3 else t
+    if t.dim() != 4 or t.shape[1] != 3 or t.stride(3) != 1 or not t.is_cuda:
+        raise ValueError("RGB planes must be a device tensor (B, 3, H, W) with contiguous rows")
+    if t.dtype not in (torch.float32, torch.bfloat16):
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return t
+
+
+def msssim_loss_rgb(ref: torch.Tensor, dis: torch.Tensor, cfg: SSIMConfig | None = None, weights=MS_WEIGHTS,
+                    n_scales: int = 3, renorm: bool = True, cs_clamp: bool = False, aggregation: str = "product",
+                    with_grad: bool = True, grad_dtype=None, **kw):
+    """Loss mean_b(1 - MS-SSIM_b) on BT.601 luma of planar RGB (B, 3, H, W)
+    float32/bfloat16, in one library call: returns (loss 0-dim float32,
+    per-frame MS-SSIM [B], d loss / d dis in grad_dtype (default dis.dtype) or
+    None)."""
+    cfg = _cfg(cfg, kw)
+    r, d = _rgb(ref), _rgb(dis)
+    if r.shape != d.shape or r.dtype != d.dtype:
+        raise ValueError("ref and dis must have equal shapes and dtypes")
+    b, _, h, w = r.shape
+    p = cfg.to_c()
+    wts = _weights(weights, n_scales)
+    flags = _ms_flags(renorm, cs_clamp, aggregation)
+    dt = _DTYPES[r.dtype]
+    n = ctypes.c_size_t()
+    L.check(L.lib.ssimx_msssim_loss_workspace_size(ctypes.byref(p), wts, n_scales, flags, dt, w, h, b,
+                                                   ctypes.byref(n)), "ssimx_msssim_loss_workspace_size")
+    ws = _workspace(n.value, r.device)
+    loss = torch.empty(1, dtype=torch.float32, device=r.device)
+    score = torch.empty(b, dtype=torch.float32, device=r.device)
+    gdt = grad_dtype or d.dtype
+    grad = torch.empty((b, 3, h, w), dtype=gdt, device=r.device) if with_grad else None
+    st = L.lib.ssimx_msssim_loss_rgb(ctypes.byref(p), wts, n_scales, flags, r.data_ptr(), d.data_ptr(), dt, w, h,
+                                     r.stride(2), r.stride(1), r.stride(0), b, loss.data_ptr(), score.data_ptr(),
+                                     grad.data_ptr() if grad is not None else None, _DTYPES[gdt],
+                                     grad.stride(2) if grad is not None else 0,
+                                     grad.stride(1) if grad is not None else 0,
+                                     grad.stride(0) if grad is not None else 0, ws.data_ptr(), ws.numel(), _stream(r))
+    L.check(st, "ssimx_msssim_loss_rgb")
+    return loss.reshape(()), score, grad
+
+
+class LossPlan:
+    """The MS-SSIM loss of msssim_loss_rgb for one shape, replayed as one HIP
+    graph per run (the plan owns its workspace; inputs and outputs may be new
+    tensors on every run).  Runs must be issued on one stream."""
+
+    def __init__(self, cfg: SSIMConfig | None, dtype, batch: int, height: int, width: int, weights=MS_WEIGHTS,
+                 n_scales: int = 3, renorm: bool = True, cs_clamp: bool = False, aggregation: str = "product",
+                 grad_dtype=None, device=None):
+        self.cfg = cfg or SSIMConfig()
+        self.dtype, self.grad_dtype = dtype, grad_dtype or dtype
+        self.shape = (batch, 3, height, width)
+        self.device = torch.device(device or "cuda")
+        p = self.cfg.to_c()
+        self._h = ctypes.c_void_p()
+        st = L.lib.ssimx_loss_plan_create(ctypes.byref(p), _weights(weights, n_scales), n_scales,
+                                          _ms_flags(renorm, cs_clamp, aggregation), _DTYPES[dtype],
+                                          _DTYPES[self.grad_dtype], width, height, batch, ctypes.byref(self._h))
+        L.check(st, "ssimx_loss_plan_create")
+
+    def run(self, ref: torch.Tensor, dis: torch.Tensor, with_grad: bool = True):
+        """(loss 0-dim, per-frame MS-SSIM [B], gradient or None), as msssim_loss_rgb."""
+        r, d = _rgb(ref), _rgb(dis)
+        if tuple(r.shape) != self.shape or tuple(d.shape) != self.shape or r.dtype != self.dtype or \
+                d.dtype != self.dtype:
+            raise ValueError(f"the plan takes {self.shape} {self.dtype} planes")
+        b, _, h, w = self.shape
+        loss = torch.empty(1, dtype=torch.float32, device=r.device)
+        score = torch.empty(b, dtype=torch.float32, device=r.device)
+        grad = torch.empty((b, 3, h, w), dtype=self.grad_dtype, device=r.device) if with_grad else None
+        st = L.lib.ssimx_loss_plan_run(self._h, r.data_ptr(), d.data_ptr(), r.stride(2), r.stride(1), r.stride(0),
+                                       loss.data_ptr(), score.data_ptr(),
+                                       grad.data_ptr() if grad is not None else None,
+                                       grad.stride(2) if grad is not None else 0,
+                                       grad.stride(1) if grad is not None else 0,
+                                       grad.stride(0) if grad is not None else 0, _stream(r))
+        L.check(st, "ssimx_loss_plan_run")
+        return loss.reshape(()), score, grad
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize(self.device)
+            L.lib.ssimx_loss_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class BatchPlan:
     """Ragged batch of independent pairs: one persistent, graph-captured
     launch per run().  pairs: list of dicts {ref, dis, cfg (SSIMConfig),

@@ -460,3 +460,43 @@ def test_noalloc_entry_refuses_on_the_host(L):
     assert L.lib.ssim_pooled_noalloc(ctypes.byref(pb), ctypes.byref(big), ctypes.byref(big), 1, sc,
                                      None) == L.ESCRATCH
     assert L.lib.ssimx_strerror(L.ESCRATCH).decode().startswith("call needs more scratch")
+
+
+def test_loss_entry_points_validate_on_the_host(L):
+    p = _params(L, C1=1e-4, C2=9e-4)
+    w = (ctypes.c_float * 3)(0.2, 0.3, 0.5)
+    sc = ctypes.c_void_p(8192)
+    n = ctypes.c_size_t()
+    ok = L.lib.ssimx_msssim_loss_workspace_size(ctypes.byref(p), w, 3, L.MS_RENORM, L.F32, 512, 512, 16,
+                                                ctypes.byref(n))
+    assert ok == L.OK and n.value > 3 * 16 * 512 * 512 * 4
+    assert L.lib.ssimx_msssim_loss_workspace_size(ctypes.byref(p), w, 3, L.MS_RENORM, L.U8, 512, 512, 16,
+                                                  ctypes.byref(n)) == L.EDTYPE
+    assert L.lib.ssimx_msssim_loss_workspace_size(ctypes.byref(p), w, 3, L.MS_RENORM, L.F32, 512, 512, 65536,
+                                                  ctypes.byref(n)) == L.EINVAL
+    # 40 x 40 at 3 scales leaves 10 x 10 < 11 at the coarsest
+    assert L.lib.ssimx_msssim_loss_workspace_size(ctypes.byref(p), w, 3, L.MS_RENORM, L.F32, 40, 40, 1,
+                                                  ctypes.byref(n)) == L.ETOOSMALL
+
+    def call(**kw):
+        a = dict(ref=sc, dis=sc, dtype=L.F32, w=64, h=64, pitch=64, cs=4096, bs=3 * 4096, b=2, loss=sc, score=None,
+                 grad=sc, gdt=L.F32, gp=64, gcs=4096, gbs=3 * 4096, ws=None, wsb=0)
+        a.update(kw)
+        return L.lib.ssimx_msssim_loss_rgb(ctypes.byref(p), w, 3, L.MS_RENORM, a["ref"], a["dis"], a["dtype"],
+                                           a["w"], a["h"], a["pitch"], a["cs"], a["bs"], a["b"], a["loss"],
+                                           a["score"], a["grad"], a["gdt"], a["gp"], a["gcs"], a["gbs"], a["ws"],
+                                           a["wsb"], None)
+    assert call() == L.EWORKSPACE
+    assert call(loss=None) == L.EINVAL
+    assert call(dis=None) == L.EINVAL
+    assert call(dtype=L.U16) == L.EDTYPE
+    assert call(gdt=L.U8) == L.EDTYPE
+    assert call(cs=100) == L.EINVAL       # channels overlap
+    assert call(gbs=4096) == L.EINVAL     # gradient frames overlap
+    assert call(grad=None, gdt=L.U8) == L.EWORKSPACE  # no gradient: its dtype is not looked at
+    h = ctypes.c_void_p()
+    assert L.lib.ssimx_loss_plan_create(ctypes.byref(p), w, 3, L.MS_RENORM, L.F32, L.U8, 64, 64, 2,
+                                        ctypes.byref(h)) == L.EDTYPE
+    assert L.lib.ssimx_loss_plan_create(ctypes.byref(p), w, 3, L.MS_RENORM, L.F32, L.F32, 64, 64, 2, None) == L.EINVAL
+    assert L.lib.ssimx_loss_plan_run(None, sc, sc, 64, 4096, 3 * 4096, sc, None, None, 0, 0, 0, None) == L.EINVAL
+    assert L.lib.ssimx_loss_plan_destroy(None) == L.EINVAL
