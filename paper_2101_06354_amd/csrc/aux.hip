@@ -12,32 +12,8 @@ __global__ __launch_bounds__(BLOCK) void finalize_kernel(const float* partial, i
                                                          int64_t out_stride) {
   __shared__ float hs[BLOCK], ls[BLOCK];
   const int frame = blockIdx.x;
-  const float* p = partial + (int64_t)frame * tiles;
-  float s = 0.f, c = 0.f;
-  for (int i = threadIdx.x; i < tiles; i += BLOCK) {
-    float e;
-    two_sum(s, p[i], s, e);
-    c += e;
-  }
-  hs[threadIdx.x] = s;
-  ls[threadIdx.x] = c;
-  __syncthreads();
-  for (int w = BLOCK / 2; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      float e, t;
-      two_sum(hs[threadIdx.x], hs[threadIdx.x + w], t, e);
-      hs[threadIdx.x] = t;
-      ls[threadIdx.x] += ls[threadIdx.x + w] + e;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    // (hi + lo) * inv_count with the low part kept through the product
-    const float hi = hs[0], lo = ls[0];
-    const float ph = hi * inv_count;
-    const float pe = fmaf(hi, inv_count, -ph);
-    out[(int64_t)frame * out_stride] = ph + (pe + lo * inv_count);
-  }
+  const float m = tile_mean(partial + (int64_t)frame * tiles, tiles, inv_count, hs, ls);
+  if (threadIdx.x == 0) out[(int64_t)frame * out_stride] = m;
 }
 
 int launch_finalize(const float* partial, int tiles, int batch, int count_per_frame, float /*scale*/, float* out,
@@ -185,19 +161,8 @@ __global__ void ms_combine_kernel(const float* vals, int n_scales, int batch, Ms
                                   const float* lvals, float* score_out, float* cs_out) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= batch) return;
-  float score = sum ? 0.f : 1.f;
-  for (int j = 0; j < n_scales; ++j) {
-    float v = vals[(int64_t)f * n_scales + j];
-    if (lvals && j == n_scales - 1) v *= lvals[f];
-    if (cs_out) cs_out[(int64_t)f * n_scales + j] = v;
-    if (sum) {
-      score = fmaf(w.w[j], v, score);
-      continue;
-    }
-    if (clamp) v = fmaxf(v, 0.f);
-    score *= powf(v, w.w[j]);
-  }
-  score_out[f] = score;
+  score_out[f] = ms_combine_frame(vals + (int64_t)f * n_scales, n_scales, w.w, clamp, sum, lvals ? lvals[f] : 1.f,
+                                  lvals != nullptr, cs_out ? cs_out + (int64_t)f * n_scales : nullptr);
 }
 
 int launch_ms_combine(const float* vals, int n_scales, int batch, const float* w, int flags, float* score_out,

@@ -243,19 +243,8 @@ __global__ void ms_upstream_kernel(const float* vals, const float* ms, const flo
                                    int clamp, int sum, int batch, const float* lv, float* up, float* up2) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= batch) return;
-  for (int j = 0; j < M; ++j) {
-    const float c = vals[(int64_t)f * M + j];
-    const bool split = lv && j == M - 1;
-    const float v = split ? c * lv[f] : c;
-    float r = sum ? gscore[f] * u.w[j] * u.inv_count[j] : gscore[f] * ms[f] * u.w[j] / v * u.inv_count[j];
-    if (!sum && clamp && !(v > 0.f)) r = 0.f;
-    if (split) {
-      up[(int64_t)f * M + j] = r * lv[f];
-      up2[f] = r * c;
-    } else {
-      up[(int64_t)f * M + j] = r;
-    }
-  }
+  ms_upstream_frame(vals + (int64_t)f * M, M, lv ? lv[f] : 1.f, lv != nullptr, ms[f], gscore[f], u.w, u.inv_count,
+                    clamp, sum, up + (int64_t)f * M, up2 + f);
 }
 
 // ---------------------------------------------------------------- host side
@@ -547,7 +536,7 @@ static ssimx_status ms_bwd_impl(const ssimx_params* p, const float* weights, int
 ssimx_status ms_bwd_levels(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
                            const ssimx_image* dis, int batch, const float* vals, const float* msv,
                            const float* grad_score, float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
-                           char* base, const MsBwdLayout& L, hipStream_t st) {
+                           char* base, const MsBwdLayout& L, hipStream_t st, bool up_ready) {
   ssimx_status s;
   UpArgs u{};
   for (int j = 0; j < n_scales; ++j) {
@@ -559,11 +548,13 @@ ssimx_status ms_bwd_levels(const ssimx_params* p, const float* w, int n_scales, 
   float* up = (float*)(base + L.up);
   float* up2 = (float*)(base + L.up2);
   const bool sep = (flags & SSIMX_MS_COARSE_SEPARATE) != 0;
-  hipLaunchKernelGGL(ms_upstream_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, vals, msv, grad_score, u, n_scales,
-                     (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, batch,
-                     sep ? (const float*)(base + L.fwd.lvals_off) : nullptr, up, up2);
-  int err = (int)hipGetLastError();
-  if (err) return hip_status(err);
+  if (!up_ready) {
+    hipLaunchKernelGGL(ms_upstream_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, vals, msv, grad_score, u,
+                       n_scales, (flags & SSIMX_MS_CS_CLAMP) ? 1 : 0, (flags & SSIMX_MS_SUM) ? 1 : 0, batch,
+                       sep ? (const float*)(base + L.fwd.lvals_off) : nullptr, up, up2);
+    const int err = (int)hipGetLastError();
+    if (err) return hip_status(err);
+  }
   for (int j = n_scales - 1; j >= 0; --j) {
     BwdLevel lv;
     float* out;

@@ -374,7 +374,8 @@ void ms_weights(const float* weights, int n_scales, int flags, float* w) {
 // of the pooled term written to out[frame * out_stride].
 ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, int mode,
                       float* map, int64_t map_pitch, int64_t map_bstride, float* out, int64_t out_stride,
-                      float* partial, uint32_t* sat, int tile_idx, hipStream_t st, float* ds_x, float* ds_y) {
+                      float* partial, uint32_t* sat, int tile_idx, hipStream_t st, float* ds_x, float* ds_y,
+                      int* tiles_out) {
   const Path path = choose_path(p, dtype);
   const float C1 = (float)p->C1, C2 = (float)p->C2;
   int err = 0, tiles = 0;
@@ -464,6 +465,7 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
     tiles = sat_ssim_tiles(g, dtype, mode, tile_idx);
   }
   if (err) return hip_status(err);
+  if (tiles_out) *tiles_out = tiles;
   if (out) {
     err = launch_finalize(partial, tiles, batch, g.Wo * g.Ho, 1.f, out, out_stride, st);
     if (err) return hip_status(err);

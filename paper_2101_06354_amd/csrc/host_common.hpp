@@ -65,10 +65,12 @@ struct MsBwdLayout {
   size_t msval, up, up2, coef, gpad, glev[MAX_SCALES], total;
 };
 MsBwdLayout ms_bwd_layout(const ssimx_params* p, int dtype, int W, int H, int batch, int M);
+// up_ready: the caller has already written the per-scale upstreams (L.up,
+// L.up2) and vals, msv, grad_score are not read.
 ssimx_status ms_bwd_levels(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
                            const ssimx_image* dis, int batch, const float* vals, const float* msv,
                            const float* grad_score, float* grad_dis, int64_t grad_pitch, int64_t grad_batch_stride,
-                           char* base, const MsBwdLayout& L, hipStream_t st);
+                           char* base, const MsBwdLayout& L, hipStream_t st, bool up_ready = false);
 
 // ds_x, ds_y (nullable): also write the 2x2-average down-sampled planes
 // float32 [batch][H/2][W/2] (fused into the stride-1 band kernel when it runs
@@ -76,7 +78,7 @@ ssimx_status ms_bwd_levels(const ssimx_params* p, const float* w, int n_scales, 
 ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, int mode,
                       float* map, int64_t map_pitch, int64_t map_bstride, float* out, int64_t out_stride,
                       float* partial, uint32_t* sat, int tile_idx, hipStream_t st, float* ds_x = nullptr,
-                      float* ds_y = nullptr);
+                      float* ds_y = nullptr, int* tiles_out = nullptr);
 ssimx_status ms_forward(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
                         const ssimx_image* dis, int batch, float* score_out, float* cs_out, void* ws,
                         const MsLayout& L, hipStream_t st);

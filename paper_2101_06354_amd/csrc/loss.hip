@@ -52,34 +52,58 @@ __global__ __launch_bounds__(BLOCK) void loss_luma_kernel(LossIO iov, const Loss
   (blockIdx.z == 0 ? yr : yd)[(int64_t)b * W * H + idx] = fmaf(kBt601R, R, fmaf(kBt601G, G, kBt601B * B));
 }
 
-// loss = (1/batch) sum_b (1 - score_b) in a fixed-order compensated sum; the
-// upstream of every frame's score is -1/batch; the scores are copied out.
-__global__ __launch_bounds__(BLOCK) void loss_value_kernel(LossIO iov, const LossIO* iod, const float* score,
-                                                           int batch, float* gscore) {
-  const LossIO& io = io_of(iov, iod);
+// Per frame (one workgroup each): the pooled value of every scale from the
+// forward's tile partials (the finalize arithmetic), the MS-SSIM score (the
+// combine arithmetic), 1 - score, and the upstream of every scale's pooled
+// term for dL/dscore = gscore (the adjoint's upstream arithmetic).  One launch
+// in place of the per-scale finalize, the combine and the upstream launches;
+// the score equals msssim's bit for bit.
+struct LossReduceArgs {
+  const float* part[MAX_SCALES];
+  int tiles[MAX_SCALES];
+  float inv[MAX_SCALES];  // 1 / map positions
+  float w[MAX_SCALES];
+  int M, clamp, sum, split;
+  const float* lpart;  // split: tile partials of the coarsest mean(l)
+  int ltiles;
+  float gscore;
+  float *score, *om, *up, *up2;
+};
+
+__global__ __launch_bounds__(BLOCK) void loss_reduce_kernel(LossReduceArgs a) {
   __shared__ float hs[BLOCK], ls[BLOCK];
-  const float inv = 1.f / (float)batch;
-  float s = 0.f, c = 0.f;
-  for (int b = threadIdx.x; b < batch; b += BLOCK) {
-    float e;
-    two_sum(s, 1.f - score[b], s, e);
-    c += e;
-    gscore[b] = -inv;
-    if (io.score) io.score[b] = score[b];
-  }
-  hs[threadIdx.x] = s;
-  ls[threadIdx.x] = c;
-  __syncthreads();
-  for (int w = BLOCK / 2; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      float e, t;
-      two_sum(hs[threadIdx.x], hs[threadIdx.x + w], t, e);
-      hs[threadIdx.x] = t;
-      ls[threadIdx.x] += ls[threadIdx.x + w] + e;
-    }
+  __shared__ float v[MAX_SCALES + 1];
+  const int f = blockIdx.x;
+  for (int j = 0; j < a.M; ++j) {
+    const float m = tile_mean(a.part[j] + (int64_t)f * a.tiles[j], a.tiles[j], a.inv[j], hs, ls);
+    if (threadIdx.x == 0) v[j] = m;
     __syncthreads();
   }
-  if (threadIdx.x == 0) io.loss[0] = (hs[0] + ls[0]) * inv;
+  if (a.split) {
+    const float m = tile_mean(a.lpart + (int64_t)f * a.ltiles, a.ltiles, a.inv[a.M - 1], hs, ls);
+    if (threadIdx.x == 0) v[MAX_SCALES] = m;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float lval = a.split ? v[MAX_SCALES] : 1.f;
+    const float s = ms_combine_frame(v, a.M, a.w, a.clamp, a.sum, lval, a.split != 0, nullptr);
+    a.score[f] = s;
+    a.om[f] = 1.f - s;
+    ms_upstream_frame(v, a.M, lval, a.split != 0, s, a.gscore, a.w, a.inv, a.clamp, a.sum, a.up + (int64_t)f * a.M,
+                      a.up2 + f);
+  }
+}
+
+// loss = mean over the batch of (1 - score) in the finalize's compensated
+// tree; the scores copied out.
+__global__ __launch_bounds__(BLOCK) void loss_total_kernel(LossIO iov, const LossIO* iod, const float* score,
+                                                           const float* om, int batch) {
+  const LossIO& io = io_of(iov, iod);
+  __shared__ float hs[BLOCK], ls[BLOCK];
+  const float loss = tile_mean(om, batch, 1.f / (float)batch, hs, ls);
+  if (threadIdx.x == 0) io.loss[0] = loss;
+  if (io.score)
+    for (int b = threadIdx.x; b < batch; b += BLOCK) io.score[b] = score[b];
 }
 
 // Gradient of the RGB planes from the luma gradient (the transpose of the
@@ -117,7 +141,7 @@ struct LossShape {
 };
 
 struct LossLayout {
-  size_t yr, yd, ygrad, score, gscore, ms, total;
+  size_t yr, yd, ygrad, score, om, lpart, ms, total;
   MsBwdLayout L;
 };
 
@@ -129,9 +153,11 @@ LossLayout loss_layout(const LossShape& sh) {
   l.yd = ws.take(plane);
   l.ygrad = ws.take(plane);
   l.score = ws.take(sizeof(float) * sh.batch);
-  l.gscore = ws.take(sizeof(float) * sh.batch);
-  l.ms = ws.take(0);
+  l.om = ws.take(sizeof(float) * sh.batch);
   l.L = ms_bwd_layout(&sh.p, SSIMX_F32, sh.W, sh.H, sh.batch, sh.n_scales);
+  const int M = sh.n_scales;
+  l.lpart = ws.take(sizeof(float) * (size_t)sh.batch * max_partials(&sh.p, SSIMX_F32, l.L.fwd.W[M - 1], l.L.fwd.H[M - 1]));
+  l.ms = ws.take(0);
   l.total = l.ms + l.L.total;
   return l;
 }
@@ -181,17 +207,56 @@ ssimx_status loss_launches(const LossShape& sh, const LossIO& io, const LossIO* 
   const ssimx_image ri{yr, SSIMX_F32, sh.W, sh.H, sh.W, (int64_t)sh.W * sh.H};
   const ssimx_image di{yd, SSIMX_F32, sh.W, sh.H, sh.W, (int64_t)sh.W * sh.H};
   char* msb = ws + l.ms;
+  const MsLayout& F = l.L.fwd;
+  // the windowed pass of every scale (each writing the next scale's 2x2
+  // means), without their finalize launches
+  const int M = sh.n_scales;
+  const bool split = (sh.flags & SSIMX_MS_COARSE_SEPARATE) != 0;
+  LossReduceArgs ra{};
+  for (int j = 0; j < M; ++j) {
+    const PlaneArg x = j == 0 ? PlaneArg{yr, sh.W, (int64_t)sh.W * sh.H}
+                              : PlaneArg{msb + F.lvl_x_off[j], F.W[j], (int64_t)F.W[j] * F.H[j]};
+    const PlaneArg y = j == 0 ? PlaneArg{yd, sh.W, (int64_t)sh.W * sh.H}
+                              : PlaneArg{msb + F.lvl_y_off[j], F.W[j], (int64_t)F.W[j] * F.H[j]};
+    const int mode = (j + 1 < M || split) ? 1 : 0;
+    const int tile = pick_tile(&sh.p, SSIMX_F32, F.W[j], F.H[j], sh.batch);
+    float* nx = j + 1 < M ? (float*)(msb + F.lvl_x_off[j + 1]) : nullptr;
+    float* ny = j + 1 < M ? (float*)(msb + F.lvl_y_off[j + 1]) : nullptr;
+    ra.part[j] = (const float*)(msb + F.partial_off[j]);
+    ssimx_status s = fwd_pass(&sh.p, SSIMX_F32, x, y, F.W[j], F.H[j], sh.batch, mode, nullptr, 0, 0, nullptr, 0,
+                              (float*)ra.part[j], nullptr, tile, st, nx, ny, &ra.tiles[j]);
+    if (s != SSIMX_OK) return s;
+    int Wo, Ho;
+    map_dims(&sh.p, F.W[j], F.H[j], Wo, Ho);
+    ra.inv[j] = (float)(1.0 / ((double)Wo * Ho));
+    ra.w[j] = sh.w[j];
+    if (split && j + 1 == M) {  // coarsest term mean(l) * mean(cs): the l partials too
+      ra.lpart = (const float*)(ws + l.lpart);
+      s = fwd_pass(&sh.p, SSIMX_F32, x, y, F.W[j], F.H[j], sh.batch, 3, nullptr, 0, 0, nullptr, 0,
+                   (float*)ra.lpart, nullptr, tile, st, nullptr, nullptr, &ra.ltiles);
+      if (s != SSIMX_OK) return s;
+    }
+  }
   float* score = (float*)(ws + l.score);
-  ssimx_status s = ms_forward(&sh.p, sh.w, sh.n_scales, sh.flags, &ri, &di, sh.batch, score, nullptr, msb, l.L.fwd, st);
-  if (s != SSIMX_OK) return s;
-  float* gscore = (float*)(ws + l.gscore);
-  hipLaunchKernelGGL(loss_value_kernel, dim3(1), dim3(BLOCK), 0, st, io, iod, score, sh.batch, gscore);
+  float* om = (float*)(ws + l.om);
+  ra.M = M;
+  ra.clamp = (sh.flags & SSIMX_MS_CS_CLAMP) ? 1 : 0;
+  ra.sum = (sh.flags & SSIMX_MS_SUM) ? 1 : 0;
+  ra.split = split ? 1 : 0;
+  ra.gscore = -1.f / (float)sh.batch;
+  ra.score = score;
+  ra.om = om;
+  ra.up = (float*)(msb + l.L.up);
+  ra.up2 = (float*)(msb + l.L.up2);
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(sh.batch), dim3(BLOCK), 0, st, ra);
+  if ((err = (int)hipGetLastError())) return hip_status(err);
+  hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(BLOCK), 0, st, io, iod, score, om, sh.batch);
   if ((err = (int)hipGetLastError())) return hip_status(err);
   if (!with_grad) return SSIMX_OK;
   float* ygrad = (float*)(ws + l.ygrad);
-  // the forward's per-scale values and pyramid are still in the workspace
-  s = ms_bwd_levels(&sh.p, sh.w, sh.n_scales, sh.flags, &ri, &di, sh.batch, (const float*)(msb + l.L.fwd.vals_off),
-                    score, gscore, ygrad, sh.W, (int64_t)sh.W * sh.H, msb, l.L, st);
+  // the forward's pyramid is still in the workspace and the upstreams are set
+  ssimx_status s = ms_bwd_levels(&sh.p, sh.w, M, sh.flags, &ri, &di, sh.batch, nullptr, nullptr, nullptr, ygrad,
+                                 sh.W, (int64_t)sh.W * sh.H, msb, l.L, st, true);
   if (s != SSIMX_OK) return s;
   const dim3 gg((sh.W * sh.H + BLOCK - 1) / BLOCK, sh.batch);
   if (sh.grad_dtype == SSIMX_F32)

@@ -84,6 +84,79 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
+// Mean of one frame's tile partials in a fixed-order compensated (TwoSum) tree
+// over the block: (hi + lo) * inv_count with the low part kept through the
+// product.  hs, ls: LDS arrays of blockDim.x floats.  Result valid in thread 0.
+__device__ __forceinline__ float tile_mean(const float* p, int tiles, float inv_count, float* hs, float* ls) {
+  float s = 0.f, c = 0.f;
+  for (int i = threadIdx.x; i < tiles; i += blockDim.x) {
+    float e;
+    two_sum(s, p[i], s, e);
+    c += e;
+  }
+  hs[threadIdx.x] = s;
+  ls[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      float e, t;
+      two_sum(hs[threadIdx.x], hs[threadIdx.x + w], t, e);
+      hs[threadIdx.x] = t;
+      ls[threadIdx.x] += ls[threadIdx.x + w] + e;
+    }
+    __syncthreads();
+  }
+  const float hi = hs[0], lo = ls[0];
+  const float ph = hi * inv_count;
+  const float pe = fmaf(hi, inv_count, -ph);
+  return ph + (pe + lo * inv_count);
+}
+
+// MS-SSIM of one frame from its per-scale values v[0..M-1] (CS_j, then the
+// coarsest term): the weighted product S_M^{w_M} prod CS_j^{w_j} (clamp: of
+// max(v, 0)), or (sum) the weighted average sum w_j v_j.  With `split` the
+// coarsest term is v[M-1] * lval (mean(l) * mean(cs)).  cs (nullable) gets the
+// terms as combined.
+__device__ __forceinline__ float ms_combine_frame(const float* v, int M, const float* w, int clamp, int sum,
+                                                  float lval, bool split, float* cs) {
+  float score = sum ? 0.f : 1.f;
+  for (int j = 0; j < M; ++j) {
+    float t = v[j];
+    if (split && j == M - 1) t *= lval;
+    if (cs) cs[j] = t;
+    if (sum) {
+      score = fmaf(w[j], t, score);
+      continue;
+    }
+    if (clamp) t = fmaxf(t, 0.f);
+    score *= powf(t, w[j]);
+  }
+  return score;
+}
+
+// Upstream of every pooled per-scale term of one frame's MS-SSIM, from its
+// values c[0..M-1] (split: the coarsest term is c[M-1] * lval), the score ms
+// and dL/dscore g, with weights w and 1/(map positions) inv: for the weighted
+// product g ms w_j / T_j / N_j (zero where a clamped term is not positive), for
+// the weighted average g w_j / N_j.  With split, up[M-1] is the upstream of
+// mean(cs) and *up2 that of mean(l).
+__device__ __forceinline__ void ms_upstream_frame(const float* c, int M, float lval, bool split, float ms, float g,
+                                                  const float* w, const float* inv, int clamp, int sum, float* up,
+                                                  float* up2) {
+  for (int j = 0; j < M; ++j) {
+    const bool sp = split && j == M - 1;
+    const float v = sp ? c[j] * lval : c[j];
+    float r = sum ? g * w[j] * inv[j] : g * ms * w[j] / v * inv[j];
+    if (!sum && clamp && !(v > 0.f)) r = 0.f;
+    if (sp) {
+      up[j] = r * lval;
+      *up2 = r * c[j];
+    } else {
+      up[j] = r;
+    }
+  }
+}
+
 // Deterministic block sum of one float per thread (fixed shuffle order, then
 // fixed order across waves).  Result valid in thread 0.
 template <int NT>
