@@ -248,10 +248,21 @@ __global__ void ms_upstream_kernel(const float* vals, const float* ms, const flo
 }
 
 // ---------------------------------------------------------------- host side
-static float shift_guess(const ssimx_params* p) {
+float shift_guess(const ssimx_params* p) {
   // t_u = 2 * mid-range, with the range L recovered from C2 = (0.03 L)^2.
   // Only the rounding of the combine step depends on it.
   return (float)(sqrt(p->C2) / 0.03);
+}
+
+// Pixel tiles of the fast adjoint: 256-row tiles halve the share of the
+// K - 1 prologue rows when the launch still holds >= 4096 workgroups;
+// smaller launches take 128 rows, halved down to 32 while they would hold
+// fewer than 1024 workgroups.
+void adjoint_tiles(FastArgs& fa, int W, int H, int batch) {
+  fa.qtiles_x = (W + 63) / 64;
+  fa.QH = (int64_t)fa.qtiles_x * ((H + 255) / 256) * batch >= 4096 ? 256 : 128;
+  while (fa.QH > 32 && (int64_t)fa.qtiles_x * ((H + fa.QH - 1) / fa.QH) * batch < 1024) fa.QH /= 2;
+  fa.qtiles_y = (H + fa.QH - 1) / fa.QH;
 }
 
 static Geom scat_geom_fit(const Geom& g, int& QW, int& QH, int& MR, int& MC, int& qtx, int& qty) {
@@ -346,13 +357,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
     if (err) return hip_status(err);
   }
   if (fast && valid && cpitch < kFastMaxPitch) {  // coefficient offsets: 24-bit multiplies of cpitch
-    // 256-row tiles halve the share of the K - 1 prologue rows when the
-    // launch still holds >= 4096 workgroups; smaller launches take 128 rows,
-    // halved down to 32 while they would hold fewer than 1024 workgroups
-    fa.qtiles_x = (lv.W + 63) / 64;
-    fa.QH = (int64_t)fa.qtiles_x * ((lv.H + 255) / 256) * batch >= 4096 ? 256 : 128;
-    while (fa.QH > 32 && (int64_t)fa.qtiles_x * ((lv.H + fa.QH - 1) / fa.QH) * batch < 1024) fa.QH /= 2;
-    fa.qtiles_y = (lv.H + fa.QH - 1) / fa.QH;
+    adjoint_tiles(fa, lv.W, lv.H, batch);
     fa.out = out;
     fa.out_pitch = out_pitch;
     fa.out_bstride = out_bstride;

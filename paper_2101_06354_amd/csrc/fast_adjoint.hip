@@ -193,16 +193,15 @@ __device__ __forceinline__ void coef_band_shift(float* HM) {
 
 }  // namespace
 
+// The adjoint of one (tile, frame): 64 pixel columns by a.QH pixel rows.
 template <int K, typename T>
-__global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
+__device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, int tile) {
   using S = AShape<K>;
   static_assert(S::CH == 16 && kTW == 64 && kNT == 256, "one pixel quad per thread and plane per chunk");
   __shared__ __align__(16) float C[kNM * S::CH * S::IWP];
   __shared__ __align__(16) float HM[kNM * S::PL];
   __shared__ __align__(16) uint32_t XY[2][S::CH * kTW * sizeof(T) / 4];  // the chunk's x, y in their own packing
   constexpr int PL = S::PL;
-  int tile, frame;
-  xcd_tile(tile, frame);
   const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
   const int qx0 = __builtin_amdgcn_readfirstlane(txi * kTW), qy0 = __builtin_amdgcn_readfirstlane(tyi * a.QH);
   const int c0 = qx0 - S::HALO - S::LP;
@@ -295,6 +294,22 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   }
 }
 
+template <int K, typename T>
+__global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
+  int tile, frame;
+  xcd_tile(tile, frame);
+  fast_adjoint_tile<K, T>(a, frame, tile);
+}
+
+template <int K>
+__global__ __launch_bounds__(kNT, 4) void fast_adjoint_segs_kernel(FastSegs m) {
+  const int s = seg_of(m.start, m.n);
+  const FastArgs& a = m.seg[s];
+  int tile, frame;
+  seg_tile(m.start, s, a.qtiles_x * a.qtiles_y, tile, frame);
+  fast_adjoint_tile<K, float>(a, frame, tile);
+}
+
 // ---------------------------------------------------------------- dispatch
 template <int K>
 static int launch_adj_k(int dtype, const FastArgs& a, dim3 grid, hipStream_t st) {
@@ -317,6 +332,19 @@ int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st)
     case 13: return launch_adj_k<13>(dtype, a, grid, st);
     default: return (int)hipErrorInvalidValue;
   }
+}
+
+int launch_fast_adjoint_segs(const FastSegs& s, hipStream_t st) {
+  if (s.n < 1 || s.n > kMaxSegs) return (int)hipErrorInvalidValue;
+  const dim3 grid(s.start[s.n]);
+  switch (s.seg[0].g.k) {
+    case 7: hipLaunchKernelGGL((fast_adjoint_segs_kernel<7>), grid, dim3(kNT), 0, st, s); break;
+    case 9: hipLaunchKernelGGL((fast_adjoint_segs_kernel<9>), grid, dim3(kNT), 0, st, s); break;
+    case 11: hipLaunchKernelGGL((fast_adjoint_segs_kernel<11>), grid, dim3(kNT), 0, st, s); break;
+    case 13: hipLaunchKernelGGL((fast_adjoint_segs_kernel<13>), grid, dim3(kNT), 0, st, s); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
 }
 
 }  // namespace ssimx

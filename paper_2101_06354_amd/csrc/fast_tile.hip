@@ -41,6 +41,22 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
   }
 }
 
+template <int K, int EPI>
+__global__ __launch_bounds__(kNT, 3) void fast_stats_segs_kernel(FastSegs m) {
+  __shared__ __align__(16) float smem[fast_smem_floats<K>()];
+  __shared__ float red[kNT / 64];
+  const int s = seg_of(m.start, m.n);
+  const FastArgs& a = m.seg[s];
+  const int tiles = a.g.tiles_x * a.g.tiles_y;
+  int tile, frame;
+  seg_tile(m.start, s, tiles, tile, frame);
+  const float acc = fast_stats_tile<K, float, EPI>(a, frame, tile, smem);
+  if constexpr (EPI != 1) {
+    const float tot = block_sum<kNT>(acc, red);
+    if (threadIdx.x == 0) a.partial[(int64_t)frame * tiles + tile] = tot;
+  }
+}
+
 // ---------------------------------------------------------------- dispatch
 bool fast_supported(int k, int stride) {
   return stride == 1 && (k == 7 || k == 9 || k == 11 || k == 13);
@@ -84,6 +100,27 @@ int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStrea
     default: return (int)hipErrorInvalidValue;
   }
 #undef SSIMX_K
+}
+
+int launch_fast_stats_segs(int epi, const FastSegs& s, hipStream_t st) {
+  if (s.n < 1 || s.n > kMaxSegs || (epi != 0 && epi != 1)) return (int)hipErrorInvalidValue;
+  const dim3 grid(s.start[s.n]);
+#define SSIMX_K(KK)                                                                                        \
+  case KK:                                                                                                 \
+    if (epi == 0)                                                                                          \
+      hipLaunchKernelGGL((fast_stats_segs_kernel<KK, 0>), grid, dim3(kNT), 0, st, s);                     \
+    else                                                                                                   \
+      hipLaunchKernelGGL((fast_stats_segs_kernel<KK, 1>), grid, dim3(kNT), 0, st, s);                     \
+    break;
+  switch (s.seg[0].g.k) {
+    SSIMX_K(7)
+    SSIMX_K(9)
+    SSIMX_K(11)
+    SSIMX_K(13)
+    default: return (int)hipErrorInvalidValue;
+  }
+#undef SSIMX_K
+  return (int)hipGetLastError();
 }
 
 }  // namespace ssimx

@@ -52,10 +52,28 @@ struct FastArgs {
   float taps[KMAX_GAUSS];
 };
 
+// Several stride-1 passes over float32 plane pairs with one window in one
+// launch (the scales of an MS-SSIM pyramid): segment i owns workgroups
+// [start[i], start[i + 1]) and runs seg[i]'s pass over its (tile, frame)
+// grid, so the small scales fill the tail of the large one instead of
+// running as launches of their own.  Partials are indexed by the segment's
+// own tile count.  Seven argument blocks keep the launch under the 4 KiB
+// kernel-argument limit.
+constexpr int kMaxSegs = 7;
+struct FastSegs {
+  FastArgs seg[kMaxSegs];
+  int start[kMaxSegs + 1];
+  int n;
+};
+
 bool fast_supported(int k, int stride);
 // epi 0: forward, 1: adjoint coefficients, 2: forward + 2x2 means (a.ds_x, a.ds_y)
 int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStream_t st);
 int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st);
+// Segmented forms (float32 planes, window seg[0].g.k): epi 0 or 1 of the
+// statistics kernel; the adjoint over each segment's (qtiles, frames) grid.
+int launch_fast_stats_segs(int epi, const FastSegs& s, hipStream_t st);
+int launch_fast_adjoint_segs(const FastSegs& s, hipStream_t st);
 // Colour path: pooled partials of the three YCbCr channels of `batch` 8-bit
 // RGB frames, staged frames 3 b + c (EPI 0, mode 0).
 int launch_fast_stats_rgb(const FastArgs& a, int batch, hipStream_t st);

@@ -40,6 +40,10 @@ bool band_eligible(const ssimx_params* p, int dtype);
 bool aligned_vec(const void* p, int64_t pitch, int64_t bstride, int esize);
 bool use_fast(const ssimx_params* p, int dtype);
 void fill_fast_common(FastArgs& a, const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, const Geom& g);
+// Backward: the shift t_u of the u basis in the coefficient planes, and the
+// pixel tiles (QH, qtiles_x, qtiles_y) of the fast adjoint for a W x H level.
+float shift_guess(const ssimx_params* p);
+void adjoint_tiles(FastArgs& fa, int W, int H, int batch);
 
 // Bump allocator over a caller workspace (256-byte aligned slices).
 struct Ws {

@@ -180,14 +180,33 @@ __device__ __forceinline__ float block_sum(float v, float* lds_scratch) {
 // each XCD walks a contiguous range of tiles and neighbouring tiles, which
 // read the same halo cache lines, meet in the same L2.  Returns (tile, frame)
 // for a (tiles, frames) grid; the mapping is a bijection on [0, n).
+__device__ __forceinline__ int xcd_perm(int b, int n) {
+  const int per = n >> 3, rem = n & 7, x = b & 7, i = b >> 3;
+  return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
 __device__ __forceinline__ void xcd_tile(int& tile, int& frame) {
   const int nx = gridDim.x;
-  const int n = nx * gridDim.y;
-  const int b = blockIdx.x + nx * blockIdx.y;
-  const int per = n >> 3, rem = n & 7, x = b & 7, i = b >> 3;
-  const int l = x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+  const int l = xcd_perm(blockIdx.x + nx * blockIdx.y, nx * gridDim.y);
   frame = l / nx;
   tile = l - frame * nx;
+}
+
+// A launch made of segments, segment s owning workgroups [start[s],
+// start[s + 1]) of a one-dimensional grid (start[0] = 0), each laid over its
+// own (tiles, frames) grid with the XCD mapping above taken within the
+// segment (a segment that does not start on a multiple of 8 keeps each XCD's
+// share contiguous, shifted by the start).
+__device__ __forceinline__ int seg_of(const int* start, int nseg) {
+  int s = 0;
+  while (s + 1 < nseg && (int)blockIdx.x >= start[s + 1]) ++s;
+  return __builtin_amdgcn_readfirstlane(s);
+}
+
+__device__ __forceinline__ void seg_tile(const int* start, int s, int tiles, int& tile, int& frame) {
+  const int l = xcd_perm((int)blockIdx.x - start[s], start[s + 1] - start[s]);
+  frame = l / tiles;
+  tile = l - frame * tiles;
 }
 
 struct PlaneArg {

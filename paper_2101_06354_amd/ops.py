@@ -477,7 +477,7 @@ def _rgb(t: torch.Tensor) -> torch.Tensor:
 
 def msssim_loss_rgb(ref: torch.Tensor, dis: torch.Tensor, cfg: SSIMConfig | None = None, weights=MS_WEIGHTS,
                     n_scales: int = 3, renorm: bool = True, cs_clamp: bool = False, aggregation: str = "product",
-                    with_grad: bool = True, grad_dtype=None, **kw):
+                    with_grad: bool = True, grad_dtype=None, coarse_separate: bool = False, **kw):
     """Loss mean_b(1 - MS-SSIM_b) on BT.601 luma of planar RGB (B, 3, H, W)
     float32/bfloat16, in one library call: returns (loss 0-dim float32,
     per-frame MS-SSIM [B], d loss / d dis in grad_dtype (default dis.dtype) or
@@ -489,7 +489,7 @@ def msssim_loss_rgb(ref: torch.Tensor, dis: torch.Tensor, cfg: SSIMConfig | None
     b, _, h, w = r.shape
     p = cfg.to_c()
     wts = _weights(weights, n_scales)
-    flags = _ms_flags(renorm, cs_clamp, aggregation)
+    flags = _ms_flags(renorm, cs_clamp, aggregation, coarse_separate)
     dt = _DTYPES[r.dtype]
     n = ctypes.c_size_t()
     L.check(L.lib.ssimx_msssim_loss_workspace_size(ctypes.byref(p), wts, n_scales, flags, dt, w, h, b,
@@ -516,7 +516,7 @@ class LossPlan:
 
     def __init__(self, cfg: SSIMConfig | None, dtype, batch: int, height: int, width: int, weights=MS_WEIGHTS,
                  n_scales: int = 3, renorm: bool = True, cs_clamp: bool = False, aggregation: str = "product",
-                 grad_dtype=None, device=None):
+                 grad_dtype=None, device=None, coarse_separate: bool = False):
         self.cfg = cfg or SSIMConfig()
         self.dtype, self.grad_dtype = dtype, grad_dtype or dtype
         self.shape = (batch, 3, height, width)
@@ -524,7 +524,8 @@ class LossPlan:
         p = self.cfg.to_c()
         self._h = ctypes.c_void_p()
         st = L.lib.ssimx_loss_plan_create(ctypes.byref(p), _weights(weights, n_scales), n_scales,
-                                          _ms_flags(renorm, cs_clamp, aggregation), _DTYPES[dtype],
+                                          _ms_flags(renorm, cs_clamp, aggregation, coarse_separate),
+                                          _DTYPES[dtype],
                                           _DTYPES[self.grad_dtype], width, height, batch, ctypes.byref(self._h))
         L.check(st, "ssimx_loss_plan_create")
 

@@ -70,21 +70,79 @@ def test_loss_call_against_oracle(P, dev, storage):
     assert g2 is None and torch.equal(l2, loss) and torch.equal(s2, score)
 
 
+def _composed(P, rt, dt, cfg, **ms_kw):
+    yr, yd = P.rgb_to_luma(rt.contiguous()), P.rgb_to_luma(dt.contiguous())
+    ms = P.ms_ssim(yr, yd, cfg, **ms_kw)
+    B = rt.shape[0]
+    gy = P.ms_ssim_backward(yr, yd, torch.full((B,), -1.0 / B, device=rt.device), cfg, **ms_kw)
+    return ms, P.luma_grad_to_rgb(gy)
+
+
 def test_loss_call_against_composed_path(P, dev):
-    """Same luma and MS-SSIM kernels: equal scores bit for bit; the gradient
-    uses the forward's own pyramid (float planes: equal to rounding)."""
+    """The same luma map and windowed kernels as the separate calls.  The
+    loss builds its pyramid from the luma planes directly (the composed
+    forward forms the 2x2 means from its staged u = x + y, v = x - y), so
+    scores agree to float32 rounding, within the pooled-score bound."""
     r, d = synth.config4(batch=4, h=130, w=171)
     rt, dt = to_dev(r, dev), to_dev(d, dev)
     cfg = P.SSIMConfig(L=1.0)
     loss, score, grad = P.msssim_loss_rgb(rt, dt, cfg)
-    yr, yd = P.rgb_to_luma(rt), P.rgb_to_luma(dt)
-    ms = P.ms_ssim(yr, yd, cfg, n_scales=3, renorm=True)
-    assert torch.equal(score, ms)
-    assert abs(float(loss) - float((1 - ms.double()).mean())) <= 1e-7
-    gy = P.ms_ssim_backward(yr, yd, torch.full((4,), -0.25, device=dev), cfg, n_scales=3, renorm=True)
-    g2 = P.luma_grad_to_rgb(gy)
+    ms, g2 = _composed(P, rt, dt, cfg, n_scales=3, renorm=True)
+    assert float((score - ms).abs().max()) <= 1e-6
+    assert abs(float(loss) - float((1 - ms.double()).mean())) <= 1e-6
     rel = float(torch.linalg.vector_norm(grad - g2) / torch.linalg.vector_norm(g2))
     assert rel <= 1e-5, rel
+
+
+# Options of the loss call: the one-launch-per-pass route at five scales (two
+# pyramid levels from the luma kernel, the rest down-sampled), with the split
+# coarsest term (a seventh pass), cs clamping and the weighted-sum
+# aggregation; the level-by-level route with padded borders; rows that are not
+# 16-byte aligned (a view of wider planes) and bfloat16 storage.
+@pytest.mark.parametrize("case", ["five_scales_split_clamp", "sum", "reflect", "unaligned_rows", "bf16_unaligned"])
+def test_loss_options_against_composed_path(P, dev, case):
+    h, w, kw = 144, 186, dict(n_scales=3, renorm=True)
+    cfg = P.SSIMConfig(L=1.0)
+    if case == "five_scales_split_clamp":
+        h, w, kw = 181, 195, dict(n_scales=5, renorm=True, cs_clamp=True, coarse_separate=True)
+    elif case == "sum":
+        kw = dict(n_scales=4, renorm=False, aggregation="sum")
+    elif case == "reflect":
+        cfg = P.SSIMConfig(L=1.0, padding="reflect")
+    r, d = synth.config4(batch=3, h=h, w=w + 1, stream=2)
+    rt, dt = to_dev(r, dev), to_dev(d, dev)
+    if case.startswith("bf16"):
+        rt, dt = rt.bfloat16(), dt.bfloat16()
+    if case.endswith("unaligned"):
+        rt, dt = rt[..., 1:], dt[..., 1:]  # row pitch w + 1, planes start one element in
+        assert rt.stride(2) == w + 1 and rt.data_ptr() % 16 != 0
+    else:
+        rt, dt = rt[..., :w].contiguous(), dt[..., :w].contiguous()
+    loss, score, grad = P.msssim_loss_rgb(rt, dt, cfg, grad_dtype=torch.float32, **kw)
+    ms, g2 = _composed(P, rt, dt, cfg, **kw)
+    assert float((score - ms).abs().max()) <= 1e-6, case
+    assert abs(float(loss) - float((1 - ms.double()).mean())) <= 1e-6, case
+    rel = float(torch.linalg.vector_norm(grad - g2) / torch.linalg.vector_norm(g2))
+    assert rel <= 1e-5, (case, rel)
+
+
+def test_five_scale_loss_against_oracle(P, dev):
+    """Five scales: levels 3 and 4 of the pyramid come from the stand-alone
+    down-sampling of the luma kernel's level 2."""
+    B = 2
+    r, d = synth.config4(batch=B, h=176, w=180, stream=3)
+    cfg = P.SSIMConfig(L=1.0)
+    loss, score, grad = P.msssim_loss_rgb(to_dev(r, dev), to_dev(d, dev), cfg, n_scales=5, renorm=True)
+    oc = oparams(cfg)
+    r64, d64 = r.astype(np.float64), d.astype(np.float64)
+    yr = [O.rgb_to_y_bt601(r64[b]) for b in range(B)]
+    yd = [O.rgb_to_y_bt601(d64[b]) for b in range(B)]
+    ms = np.array([O.msssim(yr[b], yd[b], oc, n_scales=5, renorm=True)["score"] for b in range(B)])
+    g = np.stack([O.y_grad_to_rgb_bt601(O.msssim_backward(yr[b], yd[b], -1.0 / B, oc, n_scales=5, renorm=True))
+                  for b in range(B)])
+    assert np.abs(score.cpu().numpy() - ms).max() <= 1e-6
+    assert abs(float(loss) - float(np.mean(1 - ms))) <= 1e-6
+    _cmp(grad.cpu().numpy(), g, "five scales")
 
 
 def test_plan_graph_replays_equal_the_eager_call(P, dev):
