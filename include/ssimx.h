@@ -444,6 +444,25 @@ ssimx_status ssimx_msssim_loss_rgb(const ssimx_params* p, const float* weights, 
                                    int64_t grad_pitch, int64_t grad_channel_stride, int64_t grad_batch_stride,
                                    void* ws, size_t ws_bytes, void* stream);
 
+/* The same evaluation in two calls, for autograd-style callers whose upstream
+ * d(objective)/d(loss) is known only later.  _deferred computes loss_out and
+ * score_out as ssimx_msssim_loss_rgb does and leaves the luma-level gradients
+ * of the loss in ws; _grad (same p, weights, n_scales, flags, dtype, sizes and
+ * ws, any later point on the stream, ws untouched in between) writes
+ * grad_rgb = upstream[0] * d loss / d dis_rgb, upstream a device float [1]
+ * (nullable: 1).  With upstream null or 1 the gradient equals
+ * ssimx_msssim_loss_rgb's bit for bit. */
+ssimx_status ssimx_msssim_loss_rgb_deferred(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                            const void* ref_rgb, const void* dis_rgb, int dtype, int width,
+                                            int height, int64_t pitch, int64_t channel_stride, int64_t batch_stride,
+                                            int batch, float* loss_out, float* score_out, void* ws, size_t ws_bytes,
+                                            void* stream);
+ssimx_status ssimx_msssim_loss_rgb_grad(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                        int dtype, int width, int height, int batch, const float* upstream,
+                                        void* grad_rgb, int grad_dtype, int64_t grad_pitch,
+                                        int64_t grad_channel_stride, int64_t grad_batch_stride, const void* ws,
+                                        size_t ws_bytes, void* stream);
+
 /* A loss plan: the same computation for one shape, replayed as one HIP graph.
  * Create allocates the plan's workspace and a device argument block (and a
  * small pinned ring); the first run with and the first run without a

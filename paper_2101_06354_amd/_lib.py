@@ -122,6 +122,11 @@ _SIGS = {
     "ssimx_msssim_loss_rgb": (c_int, [_P, _F, c_int, c_int, c_void_p, c_void_p, c_int, c_int, c_int, c_int64,
                                       c_int64, c_int64, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int64,
                                       c_int64, c_int64, c_void_p, c_size_t, c_void_p]),
+    "ssimx_msssim_loss_rgb_deferred": (c_int, [_P, _F, c_int, c_int, c_void_p, c_void_p, c_int, c_int, c_int,
+                                               c_int64, c_int64, c_int64, c_int, c_void_p, c_void_p, c_void_p,
+                                               c_size_t, c_void_p]),
+    "ssimx_msssim_loss_rgb_grad": (c_int, [_P, _F, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p,
+                                           c_int, c_int64, c_int64, c_int64, c_void_p, c_size_t, c_void_p]),
     "ssimx_loss_plan_create": (c_int, [_P, _F, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
                                        POINTER(c_void_p)]),
     "ssimx_loss_plan_run": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p,

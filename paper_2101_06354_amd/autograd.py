@@ -87,50 +87,41 @@ def luma(rgb):
 
 
 class MSSSIMLossFunction(torch.autograd.Function):
-    """mean_b(1 - MS-SSIM_b) on BT.601 luma with the gradient for the
-    distorted planes computed in the same library pass (one graph replay of a
-    cached loss plan); backward scales it by the upstream."""
+    """mean_b(1 - MS-SSIM_b) on BT.601 luma.  The forward runs the whole
+    library evaluation up to the luma-level gradients (kept in a per-call
+    workspace); the backward writes the RGB gradient with the upstream
+    folded into the same kernel, so no separate scaling pass is needed."""
 
     @staticmethod
-    def forward(ctx, ref, dis, plan):
-        loss, _, grad = plan.run(ref, dis, with_grad=ctx.needs_input_grad[1])
-        ctx.save_for_backward(grad if grad is not None else loss)
-        ctx.has_grad = grad is not None
+    def forward(ctx, ref, dis, cfg, n_scales, renorm):
+        if ctx.needs_input_grad[1]:
+            loss, _, ctx.state = ops.msssim_loss_rgb_deferred(ref, dis, cfg, n_scales=n_scales, renorm=renorm)
+        else:
+            loss, _, _ = ops.msssim_loss_rgb(ref, dis, cfg, n_scales=n_scales, renorm=renorm, with_grad=False)
+            ctx.state = None
+        ctx.grad_dtype = dis.dtype
         return loss
 
     @staticmethod
     def backward(ctx, g):
-        (grad,) = ctx.saved_tensors
-        return None, (grad * g.to(grad.dtype) if ctx.has_grad else None), None
-
-
-_LOSS_PLANS: dict = {}
-
-
-def _loss_plan(ref, cfg, n_scales, renorm):
-    key = (ref.device, ref.dtype, tuple(ref.shape), cfg.window, cfg.k, cfg.sigma, cfg.c1(), cfg.c2(), cfg.stride,
-           cfg.padding, cfg.algo, n_scales, renorm)
-    plan = _LOSS_PLANS.get(key)
-    if plan is None:
-        b, _, h, w = ref.shape
-        plan = ops.LossPlan(cfg, ref.dtype, b, h, w, n_scales=n_scales, renorm=renorm, device=ref.device)
-        _LOSS_PLANS[key] = plan
-    return plan
+        if ctx.state is None:
+            return None, None, None, None, None
+        return None, ops.msssim_loss_rgb_grad(ctx.state, g, ctx.grad_dtype), None, None, None
 
 
 def ms_ssim_loss_rgb(ref_rgb, dis_rgb, cfg: ops.SSIMConfig | None = None, n_scales: int = 3, renorm: bool = True,
                      **kw):
     """1 - MS-SSIM on BT.601 luma, averaged over the batch (the training loss
     of the differentiable workload).  When only the distorted planes need a
-    gradient (the training case) the loss and that gradient come from one
-    graph replay of a cached loss plan; otherwise the composed path gives
-    gradients to both planes."""
+    gradient (the training case) the loss and that gradient come from the
+    library's loss calls; otherwise the composed path gives gradients to both
+    planes."""
     cfg = ops._cfg(cfg, kw)
     ref4 = ref_rgb.unsqueeze(0) if ref_rgb.dim() == 3 else ref_rgb
     dis4 = dis_rgb.unsqueeze(0) if dis_rgb.dim() == 3 else dis_rgb
     if not ref4.requires_grad and ref4.shape == dis4.shape and ref4.dtype == dis4.dtype and \
             ref4.dtype in (torch.float32, torch.bfloat16) and ref4.stride(3) == 1 and dis4.stride(3) == 1:
-        return MSSSIMLossFunction.apply(ref4, dis4, _loss_plan(ref4, cfg, n_scales, renorm))
+        return MSSSIMLossFunction.apply(ref4, dis4, cfg, n_scales, renorm)
     return ms_ssim_loss_rgb_composed(ref_rgb, dis_rgb, cfg, n_scales=n_scales, renorm=renorm)
 
 

@@ -188,11 +188,14 @@ struct GradPyr {
 // of each 2x2 mean adds a quarter of the coarser level's gradient to each of
 // its four sources, composed from the coarsest level a pixel reaches down to
 // level 0 (s_j = a_j + s_{j+1} / 4, the order of the level-by-level
-// backward), then the transpose of the luma map.  One thread per 4 pixels of
-// a row; float32 or bfloat16 (round to nearest even) output.
+// backward), times the upstream d(objective)/d(loss) when given, then the
+// transpose of the luma map.  One thread per 4 pixels of a row; float32 or
+// bfloat16 (round to nearest even) output.
 template <typename G>
-__global__ __launch_bounds__(BLOCK) void loss_grad_pyr_kernel(LossIO iov, const LossIO* iod, GradPyr gp, int nqx) {
+__global__ __launch_bounds__(BLOCK) void loss_grad_pyr_kernel(LossIO iov, const LossIO* iod, GradPyr gp, int nqx,
+                                                              const float* upstream) {
   const LossIO io = io_of(iov, iod);
+  const float us = upstream ? *upstream : 1.f;
   const int W = gp.W[0], H = gp.H[0];
   const int idx = blockIdx.x * BLOCK + threadIdx.x;
   if (idx >= nqx * H) return;
@@ -225,6 +228,7 @@ __global__ __launch_bounds__(BLOCK) void loss_grad_pyr_kernel(LossIO iov, const 
       }
     }
     if (have) v[j] = v[j] + 0.25f * s;
+    v[j] *= us;
   }
   constexpr float wc[3] = {kBt601R, kBt601G, kBt601B};
   G* p = (G*)io.grad + (int64_t)f * io.gbstride + (int64_t)r * io.gpitch + c0;
@@ -316,17 +320,18 @@ __global__ __launch_bounds__(BLOCK) void loss_total_kernel(LossIO iov, const Los
     for (int b = threadIdx.x; b < batch; b += BLOCK) io.score[b] = score[b];
 }
 
-// Gradient of the RGB planes from the luma gradient (the transpose of the
-// luma map), written as float32 or bfloat16 (round to nearest even).
+// Gradient of the RGB planes from the luma gradient (times the upstream when
+// given; the transpose of the luma map), written as float32 or bfloat16
+// (round to nearest even).
 template <typename G>
 __global__ __launch_bounds__(BLOCK) void loss_grad_kernel(LossIO iov, const LossIO* iod, const float* gy, int W,
-                                                          int H) {
+                                                          int H, const float* upstream) {
   const LossIO io = io_of(iov, iod);
   const int idx = blockIdx.x * BLOCK + threadIdx.x;
   if (idx >= W * H) return;
   const int b = blockIdx.y;
   const int r = idx / W, c = idx - r * W;
-  const float v = gy[(int64_t)b * W * H + idx];
+  const float v = gy[(int64_t)b * W * H + idx] * (upstream ? *upstream : 1.f);
   G* p = (G*)io.grad + (int64_t)b * io.gbstride + (int64_t)r * io.gpitch + c;
   const float g[3] = {kBt601R * v, kBt601G * v, kBt601B * v};
 #pragma unroll
@@ -410,17 +415,19 @@ ssimx_status check_loss_shape(const ssimx_params* p, const float* weights, int n
   return SSIMX_OK;
 }
 
+ssimx_status check_loss_grad(const LossShape& sh, const LossIO& io) {
+  if (sh.grad_dtype != SSIMX_F32 && sh.grad_dtype != SSIMX_BF16) return SSIMX_EDTYPE;
+  if (!io.grad || io.gpitch < sh.W || io.gcstride < io.gpitch * (int64_t)sh.H ||
+      (sh.batch > 1 && io.gbstride < 3 * io.gcstride))
+    return SSIMX_EINVAL;
+  return SSIMX_OK;
+}
+
 ssimx_status check_loss_io(const LossShape& sh, const LossIO& io, bool with_grad) {
   if (!io.ref || !io.dis || !io.loss) return SSIMX_EINVAL;
   if (io.pitch < sh.W || io.cstride < io.pitch * (int64_t)sh.H || (sh.batch > 1 && io.bstride < 3 * io.cstride))
     return SSIMX_EINVAL;
-  if (with_grad) {
-    if (sh.grad_dtype != SSIMX_F32 && sh.grad_dtype != SSIMX_BF16) return SSIMX_EDTYPE;
-    if (io.gpitch < sh.W || io.gcstride < io.gpitch * (int64_t)sh.H ||
-        (sh.batch > 1 && io.gbstride < 3 * io.gcstride))
-      return SSIMX_EINVAL;
-  }
-  return SSIMX_OK;
+  return with_grad ? check_loss_grad(sh, io) : SSIMX_OK;
 }
 
 // The per-frame reduction and the batch mean after the forward passes; `ra`
@@ -532,9 +539,8 @@ ssimx_status seg_forward(const LossShape& sh, const LossLayout& l, const LossIO&
 
 // Segmented route, backward: every scale's coefficient planes in one launch,
 // every scale's adjoint in one launch (level j's gradient into its own
-// plane), then the RGB gradient composed from the levels.
-ssimx_status seg_backward(const LossShape& sh, const LossLayout& l, const LossIO& io, const LossIO* iod, char* ws,
-                          hipStream_t st) {
+// plane; the output kernel composes them).
+ssimx_status seg_backward(const LossShape& sh, const LossLayout& l, char* ws, hipStream_t st) {
   const MsLayout& F = l.L.fwd;
   char* msb = ws + l.ms;
   const int M = sh.n_scales, B = sh.batch;
@@ -545,8 +551,6 @@ ssimx_status seg_backward(const LossShape& sh, const LossLayout& l, const LossIO
   float* up = (float*)(msb + l.L.up);
   float* up2 = (float*)(msb + l.L.up2);
   FastSegs fs{};
-  GradPyr gp{};
-  gp.M = M;
   int64_t nb = 0;
   for (int j = 0; j < M; ++j) {
     const int64_t pl = (int64_t)F.W[j] * F.H[j];
@@ -571,9 +575,6 @@ ssimx_status seg_backward(const LossShape& sh, const LossLayout& l, const LossIO
     a.out_pitch = F.W[j];
     a.out_bstride = pl;
     a.coarse = nullptr;
-    gp.g[j] = a.out;
-    gp.W[j] = F.W[j];
-    gp.H[j] = F.H[j];
     fs.start[j] = (int)nb;
     nb += (int64_t)g.tiles_x * g.tiles_y * B;
     if (nb > INT32_MAX) return SSIMX_EINVAL;
@@ -589,28 +590,56 @@ ssimx_status seg_backward(const LossShape& sh, const LossLayout& l, const LossIO
     if (nb > INT32_MAX) return SSIMX_EINVAL;
   }
   fs.start[M] = (int)nb;
-  if ((err = launch_fast_adjoint_segs(fs, st))) return hip_status(err);
-  const int nqx = (sh.W + 3) / 4;
-  const dim3 gg((unsigned)(((int64_t)nqx * sh.H + BLOCK - 1) / BLOCK), B);
-  if (sh.grad_dtype == SSIMX_F32)
-    hipLaunchKernelGGL(loss_grad_pyr_kernel<float>, gg, dim3(BLOCK), 0, st, io, iod, gp, nqx);
-  else
-    hipLaunchKernelGGL(loss_grad_pyr_kernel<bf16_t>, gg, dim3(BLOCK), 0, st, io, iod, gp, nqx);
+  return hip_status(launch_fast_adjoint_segs(fs, st));
+}
+
+// The RGB gradient from the luma-level gradients a backward left in the
+// workspace, times *upstream when given.
+ssimx_status loss_output(const LossShape& sh, const LossLayout& l, const LossIO& io, const LossIO* iod,
+                         const float* upstream, char* ws, hipStream_t st) {
+  if (l.segs) {
+    const MsLayout& F = l.L.fwd;
+    GradPyr gp{};
+    gp.M = sh.n_scales;
+    for (int j = 0; j < sh.n_scales; ++j) {
+      gp.g[j] = j ? (const float*)(ws + l.ms + l.L.glev[j]) : (const float*)(ws + l.ygrad);
+      gp.W[j] = F.W[j];
+      gp.H[j] = F.H[j];
+    }
+    const int nqx = (sh.W + 3) / 4;
+    const dim3 gg((unsigned)(((int64_t)nqx * sh.H + BLOCK - 1) / BLOCK), sh.batch);
+    if (sh.grad_dtype == SSIMX_F32)
+      hipLaunchKernelGGL(loss_grad_pyr_kernel<float>, gg, dim3(BLOCK), 0, st, io, iod, gp, nqx, upstream);
+    else
+      hipLaunchKernelGGL(loss_grad_pyr_kernel<bf16_t>, gg, dim3(BLOCK), 0, st, io, iod, gp, nqx, upstream);
+  } else {
+    const float* ygrad = (const float*)(ws + l.ygrad);
+    const dim3 gg((sh.W * sh.H + BLOCK - 1) / BLOCK, sh.batch);
+    if (sh.grad_dtype == SSIMX_F32)
+      hipLaunchKernelGGL(loss_grad_kernel<float>, gg, dim3(BLOCK), 0, st, io, iod, ygrad, sh.W, sh.H, upstream);
+    else
+      hipLaunchKernelGGL(loss_grad_kernel<bf16_t>, gg, dim3(BLOCK), 0, st, io, iod, ygrad, sh.W, sh.H, upstream);
+  }
   return hip_status((int)hipGetLastError());
 }
+
+// How far a loss evaluation goes: the loss alone, the loss and the luma-level
+// gradients left in the workspace, or both and the RGB gradient.
+enum LossPhase { kLossOnly, kLossLevels, kLossGrad };
 
 // Every launch of one loss evaluation on `st`.  iod non-null: the kernels that
 // touch caller memory read the pointers from that device block (graph
 // capture); else from `io`.
-ssimx_status loss_launches(const LossShape& sh, const LossIO& io, const LossIO* iod, bool with_grad, char* ws,
+ssimx_status loss_launches(const LossShape& sh, const LossIO& io, const LossIO* iod, LossPhase phase, char* ws,
                            hipStream_t st) {
   const LossLayout l = loss_layout(sh);
   if (l.segs) {
     LossReduceArgs ra{};
     ssimx_status s = seg_forward(sh, l, io, iod, ws, ra, st);
     if (s != SSIMX_OK) return s;
-    if ((s = loss_reduce_total(sh, l, io, iod, ws, ra, st)) != SSIMX_OK || !with_grad) return s;
-    return seg_backward(sh, l, io, iod, ws, st);
+    if ((s = loss_reduce_total(sh, l, io, iod, ws, ra, st)) != SSIMX_OK || phase == kLossOnly) return s;
+    if ((s = seg_backward(sh, l, ws, st)) != SSIMX_OK || phase == kLossLevels) return s;
+    return loss_output(sh, l, io, iod, nullptr, ws, st);
   }
   float* yr = (float*)(ws + l.yr);
   float* yd = (float*)(ws + l.yd);
@@ -651,18 +680,13 @@ ssimx_status loss_launches(const LossShape& sh, const LossIO& io, const LossIO* 
     }
   }
   ssimx_status s = loss_reduce_total(sh, l, io, iod, ws, ra, st);
-  if (s != SSIMX_OK || !with_grad) return s;
+  if (s != SSIMX_OK || phase == kLossOnly) return s;
   float* ygrad = (float*)(ws + l.ygrad);
   // the forward's pyramid is still in the workspace and the upstreams are set
   s = ms_bwd_levels(&sh.p, sh.w, M, sh.flags, &ri, &di, sh.batch, nullptr, nullptr, nullptr, ygrad, sh.W,
                     (int64_t)sh.W * sh.H, msb, l.L, st, true);
-  if (s != SSIMX_OK) return s;
-  const dim3 gg((sh.W * sh.H + BLOCK - 1) / BLOCK, sh.batch);
-  if (sh.grad_dtype == SSIMX_F32)
-    hipLaunchKernelGGL(loss_grad_kernel<float>, gg, dim3(BLOCK), 0, st, io, iod, ygrad, sh.W, sh.H);
-  else
-    hipLaunchKernelGGL(loss_grad_kernel<bf16_t>, gg, dim3(BLOCK), 0, st, io, iod, ygrad, sh.W, sh.H);
-  return hip_status((int)hipGetLastError());
+  if (s != SSIMX_OK || phase == kLossLevels) return s;
+  return loss_output(sh, l, io, iod, nullptr, ws, st);
 }
 
 LossShape make_shape(const ssimx_params* p, const float* weights, int n_scales, int flags, int dtype, int grad_dtype,
@@ -739,7 +763,37 @@ ssimx_status ssimx_msssim_loss_rgb(const ssimx_params* p, const float* weights, 
                   grad_pitch, grad_channel_stride, grad_batch_stride};
   if ((s = check_loss_io(sh, io, grad_rgb != nullptr)) != SSIMX_OK) return s;
   if (!ws || ws_bytes < loss_layout(sh).total) return SSIMX_EWORKSPACE;
-  return loss_launches(sh, io, nullptr, grad_rgb != nullptr, (char*)ws, (hipStream_t)stream);
+  return loss_launches(sh, io, nullptr, grad_rgb ? kLossGrad : kLossOnly, (char*)ws, (hipStream_t)stream);
+}
+
+ssimx_status ssimx_msssim_loss_rgb_deferred(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                            const void* ref_rgb, const void* dis_rgb, int dtype, int width,
+                                            int height, int64_t pitch, int64_t channel_stride, int64_t batch_stride,
+                                            int batch, float* loss_out, float* score_out, void* ws, size_t ws_bytes,
+                                            void* stream) {
+  ssimx_status s;
+  if ((s = check_loss_shape(p, weights, n_scales, flags, dtype, width, height, batch)) != SSIMX_OK) return s;
+  const LossShape sh = make_shape(p, weights, n_scales, flags, dtype, SSIMX_F32, width, height, batch);
+  const LossIO io{ref_rgb, dis_rgb, pitch, channel_stride, batch_stride, loss_out, score_out, nullptr, 0, 0, 0};
+  if ((s = check_loss_io(sh, io, false)) != SSIMX_OK) return s;
+  if (!ws || ws_bytes < loss_layout(sh).total) return SSIMX_EWORKSPACE;
+  return loss_launches(sh, io, nullptr, kLossLevels, (char*)ws, (hipStream_t)stream);
+}
+
+ssimx_status ssimx_msssim_loss_rgb_grad(const ssimx_params* p, const float* weights, int n_scales, int flags,
+                                        int dtype, int width, int height, int batch, const float* upstream,
+                                        void* grad_rgb, int grad_dtype, int64_t grad_pitch,
+                                        int64_t grad_channel_stride, int64_t grad_batch_stride, const void* ws,
+                                        size_t ws_bytes, void* stream) {
+  ssimx_status s;
+  if ((s = check_loss_shape(p, weights, n_scales, flags, dtype, width, height, batch)) != SSIMX_OK) return s;
+  const LossShape sh = make_shape(p, weights, n_scales, flags, dtype, grad_dtype, width, height, batch);
+  const LossIO io{nullptr, nullptr, 0, 0, 0, nullptr, nullptr, grad_rgb, grad_pitch, grad_channel_stride,
+                  grad_batch_stride};
+  if ((s = check_loss_grad(sh, io)) != SSIMX_OK) return s;
+  const LossLayout l = loss_layout(sh);
+  if (!ws || ws_bytes < l.total) return SSIMX_EWORKSPACE;
+  return loss_output(sh, l, io, nullptr, upstream, (char*)ws, (hipStream_t)stream);
 }
 
 ssimx_status ssimx_loss_plan_create(const ssimx_params* p, const float* weights, int n_scales, int flags, int dtype,
@@ -781,7 +835,7 @@ ssimx_status ssimx_loss_plan_run(ssimx_loss_plan* pl, const void* ref_rgb, const
   if (!pl->exec[v]) {  // first run of this variant: capture the launches once
     err = (int)hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
     if (err) return hip_status(err);
-    s = loss_launches(pl->sh, io, pl->io_dev, with_grad, (char*)pl->ws, pl->cap);
+    s = loss_launches(pl->sh, io, pl->io_dev, with_grad ? kLossGrad : kLossOnly, (char*)pl->ws, pl->cap);
     hipGraph_t g = nullptr;
     err = (int)hipStreamEndCapture(pl->cap, &g);
     if (s != SSIMX_OK) {

@@ -509,6 +509,51 @@ def msssim_loss_rgb(ref: torch.Tensor, dis: torch.Tensor, cfg: SSIMConfig | None
     return loss.reshape(()), score, grad
 
 
+def msssim_loss_rgb_deferred(ref: torch.Tensor, dis: torch.Tensor, cfg: SSIMConfig | None = None,
+                             weights=MS_WEIGHTS, n_scales: int = 3, renorm: bool = True, cs_clamp: bool = False,
+                             aggregation: str = "product", coarse_separate: bool = False, **kw):
+    """First half of msssim_loss_rgb for callers that learn the upstream
+    later: returns (loss, per-frame MS-SSIM, state); state holds the
+    workspace with the luma-level gradients for msssim_loss_rgb_grad."""
+    cfg = _cfg(cfg, kw)
+    r, d = _rgb(ref), _rgb(dis)
+    if r.shape != d.shape or r.dtype != d.dtype:
+        raise ValueError("ref and dis must have equal shapes and dtypes")
+    b, _, h, w = r.shape
+    p = cfg.to_c()
+    wts = _weights(weights, n_scales)
+    flags = _ms_flags(renorm, cs_clamp, aggregation, coarse_separate)
+    dt = _DTYPES[r.dtype]
+    n = ctypes.c_size_t()
+    L.check(L.lib.ssimx_msssim_loss_workspace_size(ctypes.byref(p), wts, n_scales, flags, dt, w, h, b,
+                                                   ctypes.byref(n)), "ssimx_msssim_loss_workspace_size")
+    ws = _workspace(n.value, r.device)
+    loss = torch.empty(1, dtype=torch.float32, device=r.device)
+    score = torch.empty(b, dtype=torch.float32, device=r.device)
+    st = L.lib.ssimx_msssim_loss_rgb_deferred(ctypes.byref(p), wts, n_scales, flags, r.data_ptr(), d.data_ptr(), dt,
+                                              w, h, r.stride(2), r.stride(1), r.stride(0), b, loss.data_ptr(),
+                                              score.data_ptr(), ws.data_ptr(), ws.numel(), _stream(r))
+    L.check(st, "ssimx_msssim_loss_rgb_deferred")
+    return loss.reshape(()), score, (p, wts, n_scales, flags, dt, (b, 3, h, w), ws)
+
+
+def msssim_loss_rgb_grad(state, upstream: torch.Tensor | None = None, grad_dtype=torch.float32) -> torch.Tensor:
+    """d loss / d dis (B, 3, H, W) in grad_dtype, times the device scalar
+    `upstream` when given, from msssim_loss_rgb_deferred's state."""
+    p, wts, n_scales, flags, dt, shape, ws = state
+    b, _, h, w = shape
+    grad = torch.empty(shape, dtype=grad_dtype, device=ws.device)
+    up = None
+    if upstream is not None:
+        up = upstream.detach().to(device=ws.device, dtype=torch.float32).reshape(1).contiguous()
+    st = L.lib.ssimx_msssim_loss_rgb_grad(ctypes.byref(p), wts, n_scales, flags, dt, w, h, b,
+                                          up.data_ptr() if up is not None else None, grad.data_ptr(),
+                                          _DTYPES[grad_dtype], grad.stride(2), grad.stride(1), grad.stride(0),
+                                          ws.data_ptr(), ws.numel(), _stream(grad))
+    L.check(st, "ssimx_msssim_loss_rgb_grad")
+    return grad
+
+
 class LossPlan:
     """The MS-SSIM loss of msssim_loss_rgb for one shape, replayed as one HIP
     graph per run (the plan owns its workspace; inputs and outputs may be new

@@ -500,3 +500,20 @@ def test_loss_entry_points_validate_on_the_host(L):
     assert L.lib.ssimx_loss_plan_create(ctypes.byref(p), w, 3, L.MS_RENORM, L.F32, L.F32, 64, 64, 2, None) == L.EINVAL
     assert L.lib.ssimx_loss_plan_run(None, sc, sc, 64, 4096, 3 * 4096, sc, None, None, 0, 0, 0, None) == L.EINVAL
     assert L.lib.ssimx_loss_plan_destroy(None) == L.EINVAL
+    # the two-call form: same shape checks; the gradient half checks its own layout
+    assert L.lib.ssimx_msssim_loss_rgb_deferred(ctypes.byref(p), w, 3, L.MS_RENORM, sc, sc, L.F32, 64, 64, 64, 4096,
+                                                3 * 4096, 2, sc, None, None, 0, None) == L.EWORKSPACE
+    assert L.lib.ssimx_msssim_loss_rgb_deferred(ctypes.byref(p), w, 3, L.MS_RENORM, sc, sc, L.F32, 64, 64, 64, 4096,
+                                                3 * 4096, 2, None, None, None, 0, None) == L.EINVAL
+
+    def grad(**kw):
+        a = dict(grad=sc, gdt=L.F32, gp=64, gcs=4096, gbs=3 * 4096, ws=None, wsb=0, h=64)
+        a.update(kw)
+        return L.lib.ssimx_msssim_loss_rgb_grad(ctypes.byref(p), w, 3, L.MS_RENORM, L.F32, 64, a["h"], 2, None,
+                                                a["grad"], a["gdt"], a["gp"], a["gcs"], a["gbs"], a["ws"], a["wsb"],
+                                                None)
+    assert grad() == L.EWORKSPACE
+    assert grad(grad=None) == L.EINVAL
+    assert grad(gdt=L.U16) == L.EDTYPE
+    assert grad(gcs=100) == L.EINVAL
+    assert grad(h=20) == L.ETOOSMALL

@@ -172,16 +172,41 @@ def test_plan_graph_replays_equal_the_eager_call(P, dev):
         plan.close()
 
 
+@pytest.mark.parametrize("route", ["segmented", "level_by_level"])
+def test_deferred_gradient_equals_the_one_call_form(P, dev, route):
+    """Loss and scores from the first call, the gradient from the second,
+    equal to ssimx_msssim_loss_rgb's; an upstream scalar (a power of two,
+    exact in either product order) scales it."""
+    r, d = synth.config4(batch=3, h=100, w=133, stream=4)
+    rt, dt = to_dev(r, dev), to_dev(d, dev)
+    cfg = P.SSIMConfig(L=1.0, padding="valid" if route == "segmented" else "zero")
+    el, es, eg = P.msssim_loss_rgb(rt, dt, cfg)
+    loss, score, state = P.ops.msssim_loss_rgb_deferred(rt, dt, cfg)
+    assert torch.equal(loss, el) and torch.equal(score, es)
+    g1 = P.ops.msssim_loss_rgb_grad(state)
+    g2 = P.ops.msssim_loss_rgb_grad(state, torch.tensor(0.25, device=dev))  # the workspace is read, not consumed
+    g3 = P.ops.msssim_loss_rgb_grad(state, torch.tensor(-2.0, device=dev), grad_dtype=torch.bfloat16)
+    assert torch.equal(g1, eg) and torch.equal(g2, 0.25 * eg)
+    assert torch.equal(g3, (-2.0 * eg).bfloat16())
+
+
 def test_autograd_loss_takes_the_fused_path(P, dev):
     r, d = synth.config4(batch=2, h=96, w=120)
     cfg = P.SSIMConfig(L=1.0)
     rt = to_dev(r, dev)
     dt = to_dev(d, dev).requires_grad_(True)
     loss = P.autograd.ms_ssim_loss_rgb(rt, dt, cfg, n_scales=3, renorm=True)
-    (3.0 * loss).backward()
+    (4.0 * loss).backward()  # the upstream 4 is folded into the gradient kernel (exact for a power of two)
     el, _, eg = P.msssim_loss_rgb(rt, dt.detach(), cfg)
     assert torch.equal(loss.detach(), el)
-    assert torch.allclose(dt.grad, 3.0 * eg, rtol=0, atol=0)
+    assert torch.equal(dt.grad, 4.0 * eg)
+    # bfloat16 storage: the gradient comes back in bfloat16, scaled before rounding
+    rb = rt.bfloat16()
+    db = dt.detach().bfloat16().requires_grad_(True)
+    lb = P.autograd.ms_ssim_loss_rgb(rb, db, cfg, n_scales=3, renorm=True)
+    (0.5 * lb).backward()
+    _, _, gb = P.msssim_loss_rgb(rb, db.detach(), cfg, grad_dtype=torch.float32)
+    assert db.grad.dtype == torch.bfloat16 and torch.equal(db.grad, (0.5 * gb).bfloat16())
     # with a reference that needs a gradient the composed path serves both planes
     rt2 = to_dev(r, dev).requires_grad_(True)
     dt2 = to_dev(d, dev).requires_grad_(True)
