@@ -354,8 +354,8 @@ ssimx_status ssimx_color_ssim(const ssimx_params* p, double alpha, double beta, 
  * p: window must be SSIMX_WIN_BOX, stride 1, SSIMX_PAD_VALID, k <= 16
  *    (else ENOTSUP); algo is ignored.  kt: 1..64 (else EINVAL).
  * ref, dis: clips of `frames` frames; frame f of a clip is its image `f`
- *    (batch_stride apart).  Any dtype: 8-bit clips use exact uint32 sums,
- *    others float64 sums.
+ *    (batch_stride apart), row pitch at most 2^26 elements (else EINVAL).
+ *    Any dtype: 8-bit clips use exact uint32 sums, others float64 sums.
  * map_out (nullable): float32 [frames-kt+1][height-k+1][map_pitch] with frame
  *    stride map_frame_stride; score_out (nullable, not both null): float32
  *    [frames-kt+1] mean of each map frame.

@@ -8,10 +8,17 @@
 // Every thread keeps, in registers, the temporal sums of x, y, x^2, y^2 and
 // x*y over the last kt frames for the footprint pixels it owns, updated per
 // frame by adding the entering frame and subtracting the one that leaves (the
-// recurrence T(k) = T(k-1) - I(k - kt) + I(k)).  Per frame the sums go to LDS,
-// a horizontal pass forms k-wide running sums along the rows, a vertical pass
-// forms k-tall running sums down the columns, and the SSIM epilogue writes the
-// map and the tile's share of the per-frame mean.
+// recurrence T(k) = T(k-1) - I(k - kt) + I(k)).  Per frame the sums go to one
+// LDS array, a column pass turns each column into k-tall running sums in
+// place (one thread per column and moment), and a row pass forms the k-wide
+// running sums of 4 adjacent outputs from 16-byte aligned row reads and runs
+// the SSIM epilogue (map and the tile's share of the per-frame mean).  One
+// array instead of separate input and partial-sum arrays halves the LDS of a
+// workgroup, so twice as many workgroups share a CU.  Footprint pixels
+// outside the frame hold arbitrary (loaded) values: they only enter windows
+// of positions outside the map, which are neither written nor pooled, and
+// every running sum reaches them only after the last in-map position of its
+// row or column.
 //
 // 8-bit clips accumulate in uint32 (exact while k^2 kt 255^2 < 2^32); other
 // dtypes accumulate in float64 (exact for integer-valued planes, such as the
@@ -32,10 +39,10 @@ namespace {
 
 constexpr int kVolNT = 256;
 constexpr int kVolOW = 64;   // map columns per tile
-constexpr int kVolSeg = 16;  // map columns per horizontal task
 constexpr int kVolKMax = 16;
 constexpr int kVolKtMax = 64;
 constexpr int kVolWaves = kVolNT / 64;  // pooled partials per tile and map frame
+constexpr int64_t kVolMaxPitch = int64_t(1) << 26;  // elements per row
 
 struct VolArgs {
   PlaneArg x, y;
@@ -58,12 +65,9 @@ template <typename Acc, int OH, int KCAP>
 struct VolShape {
   static constexpr int IH = OH + KCAP - 1;
   static constexpr int IW = kVolOW + KCAP - 1;
-  static constexpr int IWP = IW | 1;     // odd row stride of the sums
-  static constexpr int HSP = kVolOW + 1; // odd row stride of the row sums
+  static constexpr int IWP = (IW + 3) & ~3;  // row stride of the sums: 16-byte aligned rows
   static constexpr int T_WORDS = 5 * IH * IWP;
-  static constexpr int H_WORDS = 5 * IH * HSP;
   static constexpr int PPT = (IH * IW + kVolNT - 1) / kVolNT;  // footprint pixels per thread
-  static constexpr size_t LDS = sizeof(Acc) * (size_t)(T_WORDS + H_WORDS);
 };
 
 // Raw sample as loaded: the byte for 8-bit clips, float otherwise.
@@ -72,7 +76,7 @@ using Raw = typename std::conditional<std::is_same<Acc, uint32_t>::value, uint32
 
 // Element `off` of a frame whose base is `fb` (block-uniform).
 template <typename T, typename Acc>
-__device__ __forceinline__ Raw<T, Acc> vol_load(const T* fb, int64_t off) {
+__device__ __forceinline__ Raw<T, Acc> vol_load(const T* fb, uint32_t off) {
   const T* p = fb + off;
   if constexpr (std::is_same<Acc, uint32_t>::value)
     return (uint32_t)*p;
@@ -85,16 +89,85 @@ __device__ __forceinline__ Acc widen(R v) {
   return (Acc)v;
 }
 
-// Product of two samples in the accumulation type.  Integer sums take
-// samples below 2^24 whose products stay below 2^32 (8-bit values and sums of
-// four of them), so the full-rate 24-bit multiply is exact.
+// Entering or leaving samples of a thread's footprint pixels, one register
+// per sample (combining them at load time would make each load wait).
+template <typename Acc, int PPT>
+struct VolSamples {
+  using R = Raw<void, Acc>;
+  R xs[PPT], ys[PPT];
+  __device__ __forceinline__ void set(int i, R x, R y) {
+    xs[i] = x;
+    ys[i] = y;
+  }
+  __device__ __forceinline__ Acc x(int i) const { return (Acc)xs[i]; }
+  __device__ __forceinline__ Acc y(int i) const { return (Acc)ys[i]; }
+};
+
+typedef unsigned short vol_us2 __attribute__((ext_vector_type(2)));
+// Temporal sums of one footprint pixel: sum x, sum y, sum x^2, sum y^2,
+// sum x y over the frames in the box.  Integer sums keep sum x and sum y as
+// one pair of 16-bit halves (at most 64 frames of samples below 1021 stay
+// below 2^16), updated by one packed 16-bit add per frame.
 template <typename Acc>
-__device__ __forceinline__ Acc sprod(Acc a, Acc b) {
-  if constexpr (std::is_same<Acc, uint32_t>::value)
-    return __umul24(a, b);
-  else
-    return a * b;
-}
+struct VolSums {
+  Acc v[5];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) v[m] = (Acc)0;
+  }
+  template <class Sm>
+  __device__ __forceinline__ void add(const Sm& sm, int i) {
+    const Acc x = sm.x(i), y = sm.y(i);
+    v[0] += x;
+    v[1] += y;
+    v[2] += x * x;
+    v[3] += y * y;
+    v[4] += x * y;
+  }
+  template <class Sm>
+  __device__ __forceinline__ void sub(const Sm& sm, int i) {
+    const Acc x = sm.x(i), y = sm.y(i);
+    v[0] -= x;
+    v[1] -= y;
+    v[2] -= x * x;
+    v[3] -= y * y;
+    v[4] -= x * y;
+  }
+  __device__ __forceinline__ Acc get(int m) const { return v[m]; }
+};
+template <>
+struct VolSums<uint32_t> {
+  vol_us2 s01;
+  uint32_t s2, s3, s4;
+  __device__ __forceinline__ void zero() {
+    s01 = vol_us2{0, 0};
+    s2 = s3 = s4 = 0u;
+  }
+  // integer samples are below 2^16, so the 24-bit multiplies are exact
+  __device__ __forceinline__ void add(uint32_t x, uint32_t y) {
+    s01 += vol_us2{(unsigned short)x, (unsigned short)y};
+    s2 += __umul24(x, x);
+    s3 += __umul24(y, y);
+    s4 += __umul24(x, y);
+  }
+  __device__ __forceinline__ void sub(uint32_t x, uint32_t y) {
+    s01 -= vol_us2{(unsigned short)x, (unsigned short)y};
+    s2 -= __umul24(x, x);
+    s3 -= __umul24(y, y);
+    s4 -= __umul24(x, y);
+  }
+  template <class Sm>
+  __device__ __forceinline__ void add(const Sm& sm, int i) {
+    add(sm.x(i), sm.y(i));
+  }
+  template <class Sm>
+  __device__ __forceinline__ void sub(const Sm& sm, int i) {
+    sub(sm.x(i), sm.y(i));
+  }
+  __device__ __forceinline__ uint32_t get(int m) const {
+    return m == 0 ? (uint32_t)s01.x : m == 1 ? (uint32_t)s01.y : m == 2 ? s2 : m == 3 ? s3 : s4;
+  }
+};
 
 // SSIM terms from the five box sums (as float64 values, exact for 8-bit clips).
 __device__ __forceinline__ float vol_value(double sx, double sy, double sxx, double syy, double sxy, double N,
@@ -113,16 +186,139 @@ __device__ __forceinline__ float vol_value(double sx, double sy, double sxx, dou
   return ssim_value(t, mode);
 }
 
-// KC > 0: the window size is the compile-time constant KC (loops unroll);
-// KC == 0: runtime k <= KCAP.  G map rows per column task (OH = multiple of G,
-// 64 * OH / G <= 256 tasks).
-template <typename T, typename Acc, int OH, int G, int KC, int KCAP>
-__global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
-  static_assert(OH % G == 0 && kVolOW * (OH / G) <= kVolNT, "column tasks must fit the workgroup");
+// The footprint pixels a thread owns, their temporal sums and the samples
+// of the entering and leaving frames.  Pixel path: pixels p = tid + i NT of
+// the row-major footprint, each loaded on its own.  Per pixel its element
+// offset from the tile origin within an x frame (32-bit: the host keeps row
+// pitches below 2^26), 0 outside the frame, and its LDS slot or -1 past the
+// footprint; the y offset is the same for equal pitches, else it is derived
+// from the slot.  Pixels outside the frame load the tile origin (always
+// inside), so that no load sits behind a branch.
+template <typename T, typename Acc, class S>
+struct VolPixels {
+  uint32_t xo[S::PPT];
+  int li[S::PPT];
+  VolSums<Acc> st[S::PPT];
+  VolSamples<Acc, S::PPT> en, lv;
+
+  __device__ __forceinline__ void init(const VolArgs& a, int tid, int row0, int col0, int IW, int IH) {
+#pragma unroll
+    for (int i = 0; i < S::PPT; ++i) {
+      const int p = tid + i * kVolNT;
+      const int pr = p / IW, pc = p - pr * IW;
+      const bool in = p < IW * IH && row0 + pr < a.H && col0 + pc < a.W;
+      li[i] = p < IW * IH ? pr * S::IWP + pc : -1;
+      xo[i] = in ? (uint32_t)(pr * (int)a.x.pitch + pc) : 0u;
+      st[i].zero();
+    }
+  }
+  // fx, fy: the frame's tile origin (block-uniform)
+  __device__ __forceinline__ void fetch(const T* fx, const T* fy, int dpitch, VolSamples<Acc, S::PPT>& v) {
+    if (dpitch == 0) {
+#pragma unroll
+      for (int i = 0; i < S::PPT; ++i) v.set(i, vol_load<T, Acc>(fx, xo[i]), vol_load<T, Acc>(fy, xo[i]));
+    } else {
+#pragma unroll
+      for (int i = 0; i < S::PPT; ++i) {
+        const uint32_t oy = xo[i] ? xo[i] + (uint32_t)((li[i] / S::IWP) * dpitch) : 0u;
+        v.set(i, vol_load<T, Acc>(fx, xo[i]), vol_load<T, Acc>(fy, oy));
+      }
+    }
+  }
+  __device__ __forceinline__ void update(bool drop) {
+#pragma unroll
+    for (int i = 0; i < S::PPT; ++i) {
+      st[i].add(en, i);
+      if (drop) st[i].sub(lv, i);
+    }
+  }
+  __device__ __forceinline__ void store(Acc* tsum, int IH) const {
+#pragma unroll
+    for (int i = 0; i < S::PPT; ++i)
+      if (li[i] >= 0) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) tsum[m * IH * S::IWP + li[i]] = st[i].get(m);
+      }
+  }
+};
+
+// Quad path (integer clips, 8-bit or the 16-bit 2x2 sums, whose rows hold
+// whole quads: base, row and frame strides aligned to 4 elements, width a
+// multiple of 4): a thread owns quads of 4 adjacent footprint pixels,
+// q = tid + i NT over rows of IWP / 4 quads, so a frame costs one 4- or
+// 8-byte load per quad and plane and each moment of a quad goes to LDS as one
+// 16-byte store.  A quad lies wholly inside or outside the frame; outside
+// quads load the tile origin.  The columns of the last quad of a row past
+// the footprint land in the row's padding.
+template <typename T, class S>
+struct VolQuads {
+  static constexpr int IWQ = S::IWP / 4;
+  static constexpr int QPT = (S::IH * IWQ + kVolNT - 1) / kVolNT;
+  using Q = typename std::conditional<sizeof(T) == 1, uint32_t, uint2>::type;  // 4 samples
+  uint32_t xo[QPT], yo[QPT];
+  int li[QPT];
+  VolSums<uint32_t> st[QPT][4];
+  Q enx[QPT], eny[QPT], lvx[QPT], lvy[QPT];
+
+  static __device__ __forceinline__ uint32_t sample(const Q& q, int j) {
+    if constexpr (sizeof(T) == 1)
+      return (q >> (8 * j)) & 0xffu;
+    else
+      return ((j < 2 ? q.x : q.y) >> (16 * (j & 1))) & 0xffffu;
+  }
+  __device__ __forceinline__ void init(const VolArgs& a, int tid, int row0, int col0, int IW, int IH) {
+    const int nq = (IW + 3) >> 2;
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      const int q = tid + i * kVolNT;
+      const int pr = q / nq, qc = q - pr * nq;
+      const bool slot = q < nq * IH;
+      const bool in = slot && row0 + pr < a.H && col0 + 4 * qc < a.W;
+      li[i] = slot ? pr * S::IWP + 4 * qc : -1;
+      xo[i] = in ? (uint32_t)(pr * (int)a.x.pitch + 4 * qc) : 0u;
+      yo[i] = in ? (uint32_t)(pr * (int)a.y.pitch + 4 * qc) : 0u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) st[i][j].zero();
+    }
+  }
+  __device__ __forceinline__ void fetch(const T* fx, const T* fy, Q* vx, Q* vy) const {
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      vx[i] = *(const Q*)(fx + xo[i]);
+      vy[i] = *(const Q*)(fy + yo[i]);
+    }
+  }
+  __device__ __forceinline__ void update(bool drop) {
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        st[i][j].add(sample(enx[i], j), sample(eny[i], j));
+        if (drop) st[i][j].sub(sample(lvx[i], j), sample(lvy[i], j));
+      }
+  }
+  __device__ __forceinline__ void store(uint32_t* tsum, int IH) const {
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+      if (li[i] >= 0) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m)
+          *(uint4*)&tsum[m * IH * S::IWP + li[i]] =
+              make_uint4(st[i][0].get(m), st[i][1].get(m), st[i][2].get(m), st[i][3].get(m));
+      }
+  }
+};
+
+// KC > 0: the window size is the compile-time constant KC (loops unroll and
+// the column pass keeps the last KC sums of its column in registers);
+// KC == 0: runtime k <= KCAP (the column pass leaves prefix sums and the row
+// pass takes their differences).
+template <typename T, typename Acc, int OH, int KC, int KCAP, bool QUAD>
+__global__ __launch_bounds__(kVolNT, (QUAD && KC > 0) ? 4 : 2) void vol_kernel(VolArgs a) {
+  static_assert(OH * (kVolOW / 4) <= kVolNT && OH % 4 == 0, "one row task per thread, 4 rows per wave");
+  static_assert(!QUAD || std::is_same<Acc, uint32_t>::value, "quads: integer sums");
   using S = VolShape<Acc, OH, (KC > 0 ? KC : KCAP)>;
-  using RawT = Raw<T, Acc>;
-  __shared__ Acc tsum[S::T_WORDS];  // [5][IH][IWP] temporal sums of the footprint
-  __shared__ Acc hsum[S::H_WORDS];  // [5][IH][HSP] k-wide row sums
+  __shared__ __align__(16) Acc tsum[S::T_WORDS];  // [5][IH][IWP] temporal sums, then their column sums
 
   int tile, seg;
   xcd_tile(tile, seg);
@@ -134,144 +330,128 @@ __global__ __launch_bounds__(kVolNT) void vol_kernel(VolArgs a) {
   const int k = KC > 0 ? KC : a.k;
   const int kt = a.kt;
   const int IW = kVolOW + k - 1, IH = OH + k - 1;
-  const int npx = IW * IH;
   const int tid = threadIdx.x;
 
-  // footprint pixels owned by this thread: p = tid + i * NT, and their
-  // element offsets within a frame (fixed for the tile: a frame's loads only
-  // change the block-uniform frame base)
-  int pr[S::PPT], pc[S::PPT];
-  bool pin[S::PPT];
-  int64_t xoff[S::PPT], yoff[S::PPT];
-#pragma unroll
-  for (int i = 0; i < S::PPT; ++i) {
-    const int p = tid + i * kVolNT;
-    pr[i] = p / IW;
-    pc[i] = p - pr[i] * IW;
-    pin[i] = p < npx && row0 + pr[i] < a.H && col0 + pc[i] < a.W;
-    xoff[i] = (int64_t)(row0 + pr[i]) * a.x.pitch + col0 + pc[i];
-    yoff[i] = (int64_t)(row0 + pr[i]) * a.y.pitch + col0 + pc[i];
-  }
-
-  Acc st[S::PPT][5];
-#pragma unroll
-  for (int i = 0; i < S::PPT; ++i)
-#pragma unroll
-    for (int m = 0; m < 5; ++m) st[i][m] = (Acc)0;
-
-  RawT nx[S::PPT], ny[S::PPT], ox[S::PPT], oy[S::PPT];
-  auto fetch = [&](int f, RawT* vx, RawT* vy) {
-    const T* fx = (const T*)a.x.data + (int64_t)f * a.x.bstride;
-    const T* fy = (const T*)a.y.data + (int64_t)f * a.y.bstride;
-#pragma unroll
-    for (int i = 0; i < S::PPT; ++i) {
-      vx[i] = (RawT)0;
-      vy[i] = (RawT)0;
-      if (pin[i]) {
-        vx[i] = vol_load<T, Acc>(fx, xoff[i]);
-        vy[i] = vol_load<T, Acc>(fy, yoff[i]);
-      }
+  using Own = typename std::conditional<QUAD, VolQuads<T, S>, VolPixels<T, Acc, S>>::type;
+  Own own;
+  own.init(a, tid, row0, col0, IW, IH);
+  const int dpitch = (int)(a.y.pitch - a.x.pitch);  // block-uniform
+  const int64_t xorg = (int64_t)row0 * a.x.pitch + col0, yorg = (int64_t)row0 * a.y.pitch + col0;
+  auto fetch = [&](int f, bool entering) {
+    const T* fx = (const T*)a.x.data + (f * a.x.bstride + xorg);
+    const T* fy = (const T*)a.y.data + (f * a.y.bstride + yorg);
+    if constexpr (QUAD) {
+      if (entering)
+        own.fetch(fx, fy, own.enx, own.eny);
+      else
+        own.fetch(fx, fy, own.lvx, own.lvy);
+    } else {
+      own.fetch(fx, fy, dpitch, entering ? own.en : own.lv);
     }
   };
 
   const int f_first_out = t0 + kt - 1;
   const int f_last = t0 + nseg + kt - 2;
-  fetch(t0, nx, ny);
+  fetch(t0, true);
   for (int f = t0; f <= f_last; ++f) {
-    const bool drop = f - kt >= t0;  // frame f - kt leaves the box
-#pragma unroll
-    for (int i = 0; i < S::PPT; ++i) {
-      const Acc xn = widen<Acc>(nx[i]), yn = widen<Acc>(ny[i]);
-      st[i][0] += xn;
-      st[i][1] += yn;
-      st[i][2] += sprod(xn, xn);
-      st[i][3] += sprod(yn, yn);
-      st[i][4] += sprod(xn, yn);
-      if (drop) {
-        const Acc xo = widen<Acc>(ox[i]), yo = widen<Acc>(oy[i]);
-        st[i][0] -= xo;
-        st[i][1] -= yo;
-        st[i][2] -= sprod(xo, xo);
-        st[i][3] -= sprod(yo, yo);
-        st[i][4] -= sprod(xo, yo);
-      }
-    }
+    own.update(f - kt >= t0);  // frame f enters, frame f - kt leaves the box
     // prefetch the next entering and leaving frames
     if (f + 1 <= f_last) {
-      fetch(f + 1, nx, ny);
-      if (f + 1 - kt >= t0) fetch(f + 1 - kt, ox, oy);
+      fetch(f + 1, true);
+      if (f + 1 - kt >= t0) fetch(f + 1 - kt, false);
     }
     if (f < f_first_out) continue;  // warm-up frames: sums only
 
-    // temporal sums of the footprint to LDS
-#pragma unroll
-    for (int i = 0; i < S::PPT; ++i) {
-      const int p = tid + i * kVolNT;
-      if (p < npx) {
-        const int l = pr[i] * S::IWP + pc[i];
-#pragma unroll
-        for (int m = 0; m < 5; ++m) tsum[m * IH * S::IWP + l] = st[i][m];
-      }
-    }
+    // temporal sums of the footprint to LDS, once the previous map frame's
+    // row pass has read the array
+    if (f > f_first_out) __syncthreads();
+    own.store(tsum, IH);
     __syncthreads();
 
-    // k-wide running sums along the rows: task = (row, 16-column segment, moment)
-    const int ntask = IH * (kVolOW / kVolSeg) * 5;
-    for (int q = tid; q < ntask; q += kVolNT) {
-      const int r = q % IH;
-      const int rest = q / IH;
-      const int sg = rest % (kVolOW / kVolSeg), m = rest / (kVolOW / kVolSeg);
-      const Acc* src = tsum + (m * IH + r) * S::IWP + sg * kVolSeg;
-      Acc* dst = hsum + (m * IH + r) * S::HSP + sg * kVolSeg;
-      Acc s = (Acc)0;
-#pragma unroll
-      for (int c = 0; c < (KC > 0 ? KC : KCAP); ++c)
-        if (KC > 0 || c < k) s += src[c];
-      dst[0] = s;
-#pragma unroll
-      for (int j = 1; j < kVolSeg; ++j) {
-        s += src[j + k - 1] - src[j - 1];
-        dst[j] = s;
-      }
-    }
-    __syncthreads();
-
-    // k-tall running sums down the columns and the epilogue: task = (column, 4 rows)
-    const int t = f - f_first_out + t0;  // map frame
-    float part = 0.f;
-    const int j = tid % kVolOW, g = __builtin_amdgcn_readfirstlane(tid / kVolOW);  // g: wave-uniform
-    if (g < OH / G) {
-      Acc acc[G][5];
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        const Acc* col = hsum + (m * IH + G * g) * S::HSP + j;
+    // k-tall sums down the columns, in place: task = (moment, column), one
+    // thread walking the column (output row i lands in row i after the sums
+    // it needs have been read)
+    for (int q = tid; q < 5 * IW; q += kVolNT) {
+      const int m = q / IW, c = q - m * IW;
+      Acc* col = tsum + m * IH * S::IWP + c;
+      if constexpr (KC > 0) {
+        Acc ring[KC];  // the sums of rows i - 1 .. i + KC - 2, slot r % KC
         Acc s = (Acc)0;
 #pragma unroll
-        for (int r = 0; r < (KC > 0 ? KC : KCAP); ++r)
-          if (KC > 0 || r < k) s += col[r * S::HSP];
-        acc[0][m] = s;
+        for (int r = 0; r < KC; ++r) {
+          ring[r] = col[r * S::IWP];
+          s += ring[r];
+        }
+        col[0] = s;
 #pragma unroll
-        for (int i = 1; i < G; ++i) {
-          s += col[(i + k - 1) * S::HSP] - col[(i - 1) * S::HSP];
-          acc[i][m] = s;
+        for (int i = 1; i < OH; ++i) {
+          const Acc nv = col[(i + KC - 1) * S::IWP];
+          s += nv - ring[(i - 1) % KC];
+          ring[(i - 1) % KC] = nv;
+          col[i * S::IWP] = s;
+        }
+      } else {
+        Acc s = (Acc)0;  // inclusive prefix sums; the row pass differences them
+        for (int r = 0; r < IH; ++r) {
+          s += col[r * S::IWP];
+          col[r * S::IWP] = s;
         }
       }
-      const int oj = col0 + j;
+    }
+    __syncthreads();
+
+    // k-wide running sums along the rows and the epilogue: task = (map row,
+    // 4 adjacent columns); wave w takes rows 4 w .. 4 w + 3
+    const int t = f - f_first_out + t0;  // map frame
+    float part = 0.f;
+    const int i = tid >> 4, j0 = 4 * (tid & 15);
+    if (i < OH) {
+      const Acc* rows = tsum + i * S::IWP + j0;
+      // column sum (rows i .. i + k - 1) of moment m at column j0 + c
+      auto cs = [&](int m, int c) -> Acc {
+        const Acc* r = rows + m * IH * S::IWP + c;
+        if constexpr (KC > 0) {
+          return r[0];
+        } else {
+          Acc v = r[(k - 1) * S::IWP];
+          if (i > 0) v -= r[-S::IWP];
+          return v;
+        }
+      };
+      // the window sums of the 4 outputs one at a time, so that only one
+      // output's five sums are live through the epilogue
+      Acc acc[5];
 #pragma unroll
-      for (int i = 0; i < G; ++i) {
-        const int oi = row0 + G * g + i;
+      for (int m = 0; m < 5; ++m) {
+        acc[m] = (Acc)0;
+        if constexpr (KC > 0) {
+#pragma unroll
+          for (int c = 0; c < KC; ++c) acc[m] += cs(m, c);
+        } else {
+#pragma unroll 1
+          for (int c = 0; c < k; ++c) acc[m] += cs(m, c);
+        }
+      }
+      const int oi = row0 + i;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u > 0) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) acc[m] += cs(m, u + k - 1) - cs(m, u - 1);
+        }
+        const int oj = col0 + j0 + u;
         if (oi < a.Ho && oj < a.Wo) {
-          const float v = vol_value((double)acc[i][0], (double)acc[i][1], (double)acc[i][2], (double)acc[i][3],
-                                    (double)acc[i][4], a.N, a.invN2, a.C1, a.C2, a.mode);
+          const float v = vol_value((double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3],
+                                    (double)acc[4], a.N, a.invN2, a.C1, a.C2, a.mode);
           if (a.map) {
-            char* row = (char*)(a.map + (int64_t)t * a.map_fstride + (int64_t)oi * a.map_pitch);  // wave-uniform
+            char* row = (char*)(a.map + (int64_t)t * a.map_fstride + (int64_t)oi * a.map_pitch);
             *(float*)(row + 4u * (uint32_t)oj) = v;
           }
           part += v;
         }
       }
     }
-    // one partial per wave (no barrier); the finalize adds them in a fixed order
+    // one partial per wave; the finalize adds them in a fixed order
     const float tot = wave_sum(part);
     if ((tid & 63) == 0)
       a.partial[((int64_t)t * (a.tiles_x * a.tiles_y) + tile) * kVolWaves + (tid >> 6)] = tot;
@@ -285,18 +465,34 @@ constexpr int kVolOHInt = 16, kVolOHF64 = 8;
 
 int vol_tile_rows(bool int_acc, int) { return int_acc ? kVolOHInt : kVolOHF64; }
 
+template <typename T, typename Acc, bool QUAD>
+void launch_vol_q(const VolArgs& a, dim3 grid, hipStream_t st) {
+  constexpr int OH = std::is_same<Acc, uint32_t>::value ? kVolOHInt : kVolOHF64;
+  if (a.k == 11)
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 11, 11, QUAD>), grid, dim3(kVolNT), 0, st, a);
+  else if (a.k < 11)
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 0, 11, QUAD>), grid, dim3(kVolNT), 0, st, a);
+  else
+    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 0, kVolKMax, QUAD>), grid, dim3(kVolNT), 0, st, a);
+}
+
+// Integer clips whose rows are whole quads take the quad loads.
+bool vol_quads_ok(const VolArgs& a, int esize) {
+  for (const PlaneArg* pl : {&a.x, &a.y})
+    if (((uintptr_t)pl->data & (4 * esize - 1)) || (pl->pitch & 3) || (pl->bstride & 3)) return false;
+  return (a.W & 3) == 0;
+}
+
 template <typename T, typename Acc>
 int launch_vol_t(const VolArgs& a, int nsegs, hipStream_t st) {
-  constexpr bool kInt = std::is_same<Acc, uint32_t>::value;
-  constexpr int OH = kInt ? kVolOHInt : kVolOHF64;
   const dim3 grid(a.tiles_x * a.tiles_y, nsegs);
-  if (a.k == 11) {
-    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 4, 11, 11>), grid, dim3(kVolNT), 0, st, a);
-  } else if (a.k < 11) {
-    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 4, 0, 11>), grid, dim3(kVolNT), 0, st, a);
-  } else {
-    hipLaunchKernelGGL((vol_kernel<T, Acc, OH, 4, 0, kVolKMax>), grid, dim3(kVolNT), 0, st, a);
+  if constexpr (std::is_same<Acc, uint32_t>::value) {
+    if (vol_quads_ok(a, (int)sizeof(T))) {
+      launch_vol_q<T, Acc, true>(a, grid, st);
+      return (int)hipGetLastError();
+    }
   }
+  launch_vol_q<T, Acc, false>(a, grid, st);
   return (int)hipGetLastError();
 }
 
@@ -402,6 +598,8 @@ ssimx_status check_vol_images(const ssimx_params* p, int kt, const ssimx_image* 
   ssimx_status s;
   if ((s = check_vol(p, kt)) != SSIMX_OK) return s;
   if ((s = check_images(ref, dis, frames)) != SSIMX_OK) return s;
+  // the kernel forms in-frame offsets in 32 bits (at most 31 rows of a tile)
+  if (ref->pitch > kVolMaxPitch || dis->pitch > kVolMaxPitch) return SSIMX_EINVAL;
   if (frames < kt || ref->width < p->k || ref->height < p->k) return SSIMX_ETOOSMALL;
   return SSIMX_OK;
 }

@@ -240,6 +240,9 @@ def test_ssim3d_validates_before_launch(L):
     assert call(box, 9, frames=8) == L.ETOOSMALL
     assert call(box, 3, sc=None) == L.EINVAL          # neither map nor scores
     assert call(box, 3) == L.EWORKSPACE
+    wide = L.Image(12345, L.U8, 64, 48, (1 << 26) + 1, ((1 << 26) + 1) * 48)  # row pitch beyond 2^26
+    assert L.lib.ssimx_ssim3d(ctypes.byref(box), 3, ctypes.byref(wide), ctypes.byref(clip), 8, None, 64, 64 * 48,
+                              s, None, 0, None) == L.EINVAL
     assert L.lib.ssimx_ssim3d_workspace_size(ctypes.byref(box), 3, L.U8, 64, 48, 8, ctypes.byref(n)) == L.OK
     assert n.value > 0
     assert call(box, 3, ws=ctypes.c_void_p(1), nb=n.value - 1) == L.EWORKSPACE

@@ -110,6 +110,12 @@ def test_ssim3d_pitched_clip(P, dev):
     s, m = P.ssim3d(big_x[:, :64, :100], big_y[:, :64, :100], 3, cfg, return_map=True)
     r = O.ssim3d_map(x, y, oparams(cfg), 3)
     assert np.abs(m.cpu().numpy() - r["map"]).max() <= MAP_TOL
+    # unequal row pitches of the two clips (the kernel derives the distorted
+    # clip's offsets from the reference's)
+    wide_y = torch.zeros((7, 66, 171), dtype=torch.uint8, device=dev)
+    wide_y[:, :64, :100] = to_dev(y, dev)
+    s2, m2 = P.ssim3d(big_x[:, :64, :100], wide_y[:, :64, :100], 3, cfg, return_map=True)
+    assert torch.equal(m2, m) and torch.equal(s2, s)
 
 
 @pytest.mark.parametrize("n_scales,aggregation", [(3, "product"), (2, "sum"), (1, "product")])
