@@ -172,17 +172,21 @@ struct VolSums<uint32_t> {
 // SSIM terms from the five box sums (as float64 values, exact for 8-bit clips).
 __device__ __forceinline__ float vol_value(double sx, double sy, double sxx, double syy, double sxy, double N,
                                            float invN2, float C1, float C2, int mode) {
-  const double nxx = N * sxx - sx * sx;
-  const double nyy = N * syy - sy * sy;
-  const double nxy = N * sxy - sx * sy;
-  const double d = sx - sy;
+  // With P = sx sy and Q = sx^2 + sy^2: N^2 (mu_x^2 + mu_y^2) = Q,
+  // N^2 (sigma_x^2 + sigma_y^2) = N (sxx + syy) - Q, N^2 sigma_xy = N sxy - P,
+  // N^2 (mu_x - mu_y)^2 = Q - 2 P and N^2 var(x - y) = the variance sum - 2
+  // N^2 sigma_xy.  Exact for integer sums; for x == y both differences are 0.
+  const double P = sx * sy;
+  const double Q = fma(sx, sx, sy * sy);
+  const double nxy = fma(N, sxy, -P);
+  const double n2 = fma(N, sxx + syy, -Q);
   SsimTerms t;
-  t.A1 = (float)(2.0 * sx * sy) * invN2 + C1;
-  t.B1 = (float)(sx * sx + sy * sy) * invN2 + C1;
+  t.A1 = (float)(2.0 * P) * invN2 + C1;
+  t.B1 = (float)Q * invN2 + C1;
   t.A2 = (float)(2.0 * nxy) * invN2 + C2;
-  t.B2 = (float)(nxx + nyy) * invN2 + C2;
-  t.D1 = (float)(d * d) * invN2;                  // (mu_x - mu_y)^2
-  t.D2 = (float)(nxx + nyy - 2.0 * nxy) * invN2;  // variance of x - y
+  t.B2 = (float)n2 * invN2 + C2;
+  t.D1 = (float)fma(-2.0, P, Q) * invN2;    // (mu_x - mu_y)^2
+  t.D2 = (float)fma(-2.0, nxy, n2) * invN2;  // variance of x - y
   return ssim_value(t, mode);
 }
 
@@ -421,12 +425,32 @@ __global__ __launch_bounds__(kVolNT, (QUAD && KC > 0) ? 4 : 2) void vol_kernel(V
       // the window sums of the 4 outputs one at a time, so that only one
       // output's five sums are live through the epilogue
       Acc acc[5];
+      // KC > 0: the KC + 3 column sums of each moment, read as 16-byte
+      // vectors (row starts and j0 are multiples of 4 elements)
+      constexpr int NV = KC > 0 ? (KC + 3 + 3) / 4 * 4 : 1;
+      static_assert(KC == 0 || NV <= S::IWP - (kVolOW - 4), "vector reads stay inside the row");
+      Acc cv[5][NV];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         acc[m] = (Acc)0;
         if constexpr (KC > 0) {
+          const Acc* r = rows + m * IH * S::IWP;
 #pragma unroll
-          for (int c = 0; c < KC; ++c) acc[m] += cs(m, c);
+          for (int c = 0; c < NV; c += 16 / (int)sizeof(Acc)) {
+            if constexpr (sizeof(Acc) == 4) {
+              const uint4 q = *(const uint4*)(r + c);
+              cv[m][c] = q.x;
+              cv[m][c + 1] = q.y;
+              cv[m][c + 2] = q.z;
+              cv[m][c + 3] = q.w;
+            } else {
+              const double2 q = *(const double2*)(r + c);
+              cv[m][c] = q.x;
+              cv[m][c + 1] = q.y;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < KC; ++c) acc[m] += cv[m][c];
         } else {
 #pragma unroll 1
           for (int c = 0; c < k; ++c) acc[m] += cs(m, c);
@@ -437,7 +461,12 @@ __global__ __launch_bounds__(kVolNT, (QUAD && KC > 0) ? 4 : 2) void vol_kernel(V
       for (int u = 0; u < 4; ++u) {
         if (u > 0) {
 #pragma unroll
-          for (int m = 0; m < 5; ++m) acc[m] += cs(m, u + k - 1) - cs(m, u - 1);
+          for (int m = 0; m < 5; ++m) {
+            if constexpr (KC > 0)
+              acc[m] += cv[m][u + KC - 1] - cv[m][u - 1];
+            else
+              acc[m] += cs(m, u + k - 1) - cs(m, u - 1);
+          }
         }
         const int oj = col0 + j0 + u;
         if (oi < a.Ho && oj < a.Wo) {
