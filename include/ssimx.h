@@ -292,7 +292,7 @@ typedef enum {
 } ssimx_pool_kind;
 
 typedef struct {
-  ssimx_pool_kind kind;
+  int kind; /* ssimx_pool_kind */
   double p;  /* order / exponent / percentile, per kind */
   double o;  /* outer exponent of MEAN_DEV */
   double r;  /* divisor of PERCENTILE */

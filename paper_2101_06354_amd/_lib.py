@@ -11,7 +11,9 @@ import os
 from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_uint32, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libssimx.so")
+# SSIMX_LIBRARY names another build of the library to load (the host-sanitised
+# build of build_lib.py --sanitize-host, for instance).
+LIB_PATH = os.environ.get("SSIMX_LIBRARY") or os.path.join(HERE, "libssimx.so")
 
 # status codes
 OK, EINVAL, EDTYPE, ETOOSMALL, EWORKSPACE, EHIP, ENOTSUP, ENOMEM, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8

@@ -20,6 +20,37 @@
 
 namespace ssimx {
 
+// Timing frames: independent pseudo-random samples over the dtype's range
+// (8-bit full range, 16-bit 10-bit video range, floats in [0, 1)), from the
+// lowbias32 integer hash of the element index, so that candidates are timed
+// on data with the value spread of real frames rather than on constants.
+__device__ __forceinline__ uint32_t tune_hash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ __launch_bounds__(BLOCK) void tune_fill_kernel(void* out, int dtype, size_t n, uint32_t seed) {
+  for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (size_t)gridDim.x * BLOCK) {
+    const uint32_t h = tune_hash((uint32_t)i * 0x9e3779b9u + seed);
+    switch (dtype) {
+      case SSIMX_U8: ((uint8_t*)out)[i] = (uint8_t)(h >> 24); break;
+      case SSIMX_U16: ((uint16_t*)out)[i] = (uint16_t)(h >> 22); break;
+      case SSIMX_F32: ((float*)out)[i] = (float)(h >> 8) * (1.f / 16777216.f); break;
+      default: ((uint16_t*)out)[i] = (uint16_t)(__float_as_uint((float)(h >> 8) * (1.f / 16777216.f)) >> 16); break;
+    }
+  }
+}
+
+static int tune_fill(void* out, int dtype, size_t n, uint32_t seed, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<size_t>((n + BLOCK - 1) / BLOCK, 4096);
+  hipLaunchKernelGGL(tune_fill_kernel, dim3(std::max(1u, blocks)), dim3(BLOCK), 0, st, out, dtype, n, seed);
+  return (int)hipGetLastError();
+}
+
 static std::mutex g_tune_mu;
 static std::map<std::string, int> g_tune_cache;
 static int g_tile_override = -1;
@@ -183,8 +214,9 @@ ssimx_status ssimx_autotune(const ssimx_params* p, int dtype, int width, int hei
   if (!err) err = (int)hipMalloc(&y, plane);
   if (!err) err = (int)hipMalloc(&ws, wsb);
   if (!err) err = (int)hipMalloc(&score, sizeof(float) * batch);
-  if (!err) err = (int)hipMemsetAsync(x, 0x35, plane, st);
-  if (!err) err = (int)hipMemsetAsync(y, 0x3a, plane, st);
+  const size_t nel = (size_t)width * height * batch;
+  if (!err) err = tune_fill(x, dtype, nel, 0x2545f491u, st);
+  if (!err) err = tune_fill(y, dtype, nel, 0x9e3779b9u, st);
   if (!err) err = (int)hipEventCreate(&e0);
   if (!err) err = (int)hipEventCreate(&e1);
   if (!err) {

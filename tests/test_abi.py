@@ -266,8 +266,9 @@ def test_package_fails_loudly_without_the_library(tmp_path):
     src = os.path.join(ROOT, "paper_2101_06354_amd")
     dst = tmp_path / "paper_2101_06354_amd"
     shutil.copytree(src, dst, ignore=shutil.ignore_patterns("*.so", "_build", "csrc", "__pycache__"))
+    env = {k: v for k, v in os.environ.items() if k != "SSIMX_LIBRARY"}  # no other build to fall back on
     r = subprocess.run([sys.executable, "-c", "import paper_2101_06354_amd"], cwd=tmp_path,
-                       capture_output=True, text=True, timeout=120)
+                       capture_output=True, text=True, timeout=120, env=env)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "not built" in r.stderr
 

@@ -110,6 +110,9 @@ def test_autotune_and_cache_roundtrip(P, dev, tmp_path):
     box = P.SSIMConfig(window="box", k=8, stride=4)
     best2 = P.autotune(box, torch.uint8, 240, 426, 1)
     assert 0 <= best2 < P.num_tile_configs()
+    # the timing frames of every dtype (pseudo-random samples over its range)
+    for dt in (torch.uint16, torch.float32, torch.bfloat16):
+        assert 0 <= P.autotune(P.SSIMConfig(L=1.0), dt, 120, 200, 2) < P.num_tile_configs()
     path = str(tmp_path / "tune.json")
     P.tune_cache_save(path)
     text = open(path).read()
