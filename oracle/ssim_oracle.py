@@ -50,6 +50,7 @@ __all__ = [
     "rgb_to_ycbcr_bt709", "color_ssim", "BT709_Y", "BT709_CB", "BT709_CR",
     "box_sums3d", "ssim3d_map", "ssim3d", "msssim3d",
     "pool_geometric", "pool_harmonic", "pool_median", "pool_windowed",
+    "lw_weights", "pool_luminance_weighted",
 ]
 
 # Exponents of the original five-scale MS-SSIM, as used by the configurations
@@ -582,6 +583,28 @@ def y_grad_to_rgb_bt601(gy: np.ndarray) -> np.ndarray:
 def pool_mean(q: np.ndarray) -> float:
     """Arithmetic mean of the map (the baseline pooling)."""
     return mean_pool(q)
+
+
+def lw_weights(mu1: np.ndarray, a_s: float, b_s: float) -> np.ndarray:
+    """Luminance weights of the Luminance-Weighted Pooling subsection: 0 where
+    the reference's local mean mu1 lies below a_s, (mu1 - a_s)/b_s on
+    [a_s, a_s + b_s), 1 from a_s + b_s on (b_s = 0: a step at a_s)."""
+    mu1 = np.asarray(mu1, dtype=np.float64)
+    w = np.ones_like(mu1)
+    w[mu1 < a_s] = 0.0
+    if b_s > 0:
+        mid = (mu1 >= a_s) & (mu1 < a_s + b_s)
+        w[mid] = (mu1[mid] - a_s) / b_s
+    return w
+
+
+def pool_luminance_weighted(x, y, p: SSIMParams | None = None, a_s: float = 0.0, b_s: float = 0.0) -> float:
+    """S_LW = (1/MN) sum_x w_LW(mu1(x)) Q(x): the weighted sum divided by the
+    number of map positions, not by the sum of the weights (Luminance-Weighted
+    Pooling subsection); mu1 is the reference's windowed mean."""
+    r = ssim_map(x, y, p)
+    wq = lw_weights(r["mu_x"], a_s, b_s) * r["map"]
+    return math.fsum(wq.ravel().tolist()) / wq.size
 
 
 def pool_cov(q: np.ndarray) -> float:

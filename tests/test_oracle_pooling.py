@@ -193,3 +193,61 @@ def test_windowed_means_reduce_at_the_ends():
     assert abs(O.pool_windowed(w, 5, "am") - 1.0 / (5 * (n - 4))) < 1e-16
     with pytest.raises(ValueError):
         O.pool_windowed(s, n + 1, "am")
+
+
+# Luminance-Weighted Pooling subsection
+def test_lw_weight_shape():
+    a_s, b_s = 40.0, 20.0
+    mu = np.array([0.0, 39.999, 40.0, 45.0, 50.0, 59.999, 60.0, 255.0])
+    w = O.lw_weights(mu, a_s, b_s)
+    assert w[0] == 0 and w[1] == 0 and w[2] == 0        # below and at the lower limit
+    assert w[4] == 0.5 and w[6] == 1 and w[7] == 1       # midpoint, upper limit and above
+    assert np.all(np.diff(w) >= 0) and 0 < w[3] < w[4] < w[5] < 1
+    # b_s = 0: a step at a_s
+    assert list(O.lw_weights(np.array([9.9, 10.0, 10.1]), 10.0, 0.0)) == [0.0, 1.0, 1.0]
+
+
+def test_lw_zero_limits_is_the_baseline():
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 256, (40, 48)).astype(np.uint8)
+    y = np.clip(x.astype(int) + rng.integers(-20, 21, x.shape), 0, 255).astype(np.uint8)
+    p = O.SSIMParams()
+    assert O.pool_luminance_weighted(x, y, p, 0.0, 0.0) == pytest.approx(O.ssim_pooled(x, y, p), abs=1e-15)
+    # a lower limit above every local mean weighs everything out
+    assert O.pool_luminance_weighted(x, y, p, 300.0, 10.0) == 0.0
+
+
+def test_lw_constant_reference_closed_form():
+    rng = np.random.default_rng(6)
+    x = np.full((30, 34), 120.0)
+    y = x + rng.normal(0, 8, x.shape)
+    p = O.SSIMParams()
+    base = O.ssim_pooled(x, y, p)
+    # mu1 = 120 everywhere: weight (120 - a_s) / b_s inside the ramp, 1 above it
+    assert O.pool_luminance_weighted(x, y, p, 100.0, 40.0) == pytest.approx(0.5 * base, rel=1e-12)
+    assert O.pool_luminance_weighted(x, y, p, 60.0, 40.0) == pytest.approx(base, rel=1e-12)
+
+
+def test_lw_brute_force_direct_window():
+    """Direct 2-D window sums on a tiny half-dark, half-bright pair, position by
+    position, against the separable oracle."""
+    rng = np.random.default_rng(7)
+    h, w, k = 14, 18, 5
+    x = np.where(np.arange(w)[None, :] < 8, 10.0, 180.0) + rng.integers(0, 6, (h, w))
+    y = x + rng.integers(-9, 10, (h, w))
+    p = O.SSIMParams(window="gaussian", k=k, sigma=1.5)
+    g = O.window_2d("gaussian", k, 1.5)
+    C1, C2 = p.C1, p.C2
+    for a_s, b_s in [(60.0, 0.0), (30.0, 90.0), (100.0, 25.0)]:
+        tot, n = 0.0, 0
+        for i in range(h - k + 1):
+            for j in range(w - k + 1):
+                px, py = x[i:i + k, j:j + k], y[i:i + k, j:j + k]
+                mx, my = (g * px).sum(), (g * py).sum()
+                vx, vy = (g * (px - mx) ** 2).sum(), (g * (py - my) ** 2).sum()
+                cxy = (g * (px - mx) * (py - my)).sum()
+                q = (2 * mx * my + C1) * (2 * cxy + C2) / ((mx * mx + my * my + C1) * (vx + vy + C2))
+                wt = 0.0 if mx < a_s else (1.0 if mx >= a_s + b_s else (mx - a_s) / b_s)
+                tot += wt * q
+                n += 1
+        assert O.pool_luminance_weighted(x, y, p, a_s, b_s) == pytest.approx(tot / n, rel=1e-10, abs=1e-13)
