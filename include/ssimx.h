@@ -153,6 +153,19 @@ ssimx_status ssim_map(const ssimx_params* p, const ssimx_image* ref, const ssimx
 ssimx_status ssim_pooled(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
                          float* score_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Luminance-Weighted Pooling subsection: score_out[b] = (1 / map positions)
+ * sum w(mu_1) Q over the map, mu_1 the reference's local mean (float32, from
+ * the same statistics as Q), w = 0 for mu_1 < a_s, (mu_1 - a_s) / b_s on
+ * [a_s, a_s + b_s), 1 from a_s + b_s on (b_s = 0: a step at a_s, decided in
+ * float32).  The weighted sum is divided by the number of positions, not by
+ * the sum of the weights; a_s = b_s = 0 gives ssim_pooled's score for
+ * non-negative planes.  a_s, b_s finite, b_s >= 0 (else EINVAL).  Only the
+ * stride-1 Gaussian windows of the fast path (k = 7, 9, 11, 13, centre taps
+ * >= 0.04; any padding) are supported, else ENOTSUP.  Workspace: as
+ * ssim_pooled. */
+ssimx_status ssim_pooled_lw(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                            float a_s, float b_s, float* score_out, void* ws, size_t ws_bytes, void* stream);
+
 /* ssim_pooled for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same scores as ssim_pooled, without a workspace argument.  The scratch

@@ -74,6 +74,7 @@ _SIGS = {
     "ssimx_workspace_size": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, c_int, POINTER(c_size_t)]),
     "ssim_map": (c_int, [_P, _I, _I, c_int, c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ssim_pooled": (c_int, [_P, _I, _I, c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ssim_pooled_lw": (c_int, [_P, _I, _I, c_int, c_float, c_float, c_void_p, c_void_p, c_size_t, c_void_p]),
     "msssim": (c_int, [_P, _F, c_int, c_int, _I, _I, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ssimx_msssim_pyramid_layout": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, POINTER(c_int64),
                                             POINTER(c_int64), POINTER(c_int), POINTER(c_int)]),

@@ -21,7 +21,8 @@
 //
 // Kernel: fast_stats_kernel<K, T, EPI>, EPI = 0: SSIM / cs map + pooled
 // partials; EPI = 1: the three adjoint coefficient planes (the transposed
-// window over them is in fast_adjoint.hip).
+// window over them is in fast_adjoint.hip); EPI = 2: EPI 0 plus the next
+// MS-SSIM scale's 2x2 means; EPI = 3: EPI 0 with luminance-weighted partials.
 #include "fast_tile_body.hpp"
 
 namespace ssimx {
@@ -90,8 +91,10 @@ int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStrea
   dim3 grid(a.g.tiles_x * a.g.tiles_y, batch);
 #define SSIMX_K(KK)                                                                          \
   case KK:                                                                                   \
-    return epi == 0 ? launch_stats_k<KK, 0>(dtype, a, grid, st)                              \
-                    : epi == 1 ? launch_stats_k<KK, 1>(dtype, a, grid, st) : launch_stats_k<KK, 2>(dtype, a, grid, st);
+    return epi == 0   ? launch_stats_k<KK, 0>(dtype, a, grid, st)                            \
+           : epi == 1 ? launch_stats_k<KK, 1>(dtype, a, grid, st)                            \
+           : epi == 2 ? launch_stats_k<KK, 2>(dtype, a, grid, st)                            \
+                      : launch_stats_k<KK, 3>(dtype, a, grid, st);
   switch (a.g.k) {
     SSIMX_K(7)
     SSIMX_K(9)

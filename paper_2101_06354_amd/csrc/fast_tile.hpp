@@ -49,6 +49,8 @@ struct FastArgs {
   int64_t out_pitch, out_bstride;
   const float* coarse;
   int Wc, Hc;
+  // luminance-weighted forward (epi 3): weights of the reference's local mean
+  float lw_a, lw_b;
   float taps[KMAX_GAUSS];
 };
 
@@ -67,7 +69,9 @@ struct FastSegs {
 };
 
 bool fast_supported(int k, int stride);
-// epi 0: forward, 1: adjoint coefficients, 2: forward + 2x2 means (a.ds_x, a.ds_y)
+// epi 0: forward, 1: adjoint coefficients, 2: forward + 2x2 means (a.ds_x,
+// a.ds_y), 3: forward whose pooled partials weigh each value by the
+// luminance weight of the reference's local mean (a.lw_a, a.lw_b)
 int launch_fast_stats(int dtype, int epi, const FastArgs& a, int batch, hipStream_t st);
 int launch_fast_adjoint(int dtype, const FastArgs& a, int batch, hipStream_t st);
 // Segmented forms (float32 planes, window seg[0].g.k): epi 0 or 1 of the

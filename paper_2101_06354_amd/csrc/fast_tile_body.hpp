@@ -449,7 +449,8 @@ __host__ __device__ constexpr int fast_smem_floats() {
 
 // One map tile: returns this thread's share of the tile's pooled sum (EPI 0:
 // forward; EPI 2: forward that also writes the 2x2 means of its input to
-// a.ds_x, a.ds_y) or 0 (EPI 1: adjoint coefficients).  `smem` holds
+// a.ds_x, a.ds_y; EPI 3: forward with luminance-weighted values) or 0 (EPI 1:
+// adjoint coefficients).  `smem` holds
 // fast_smem_floats<K>() floats.
 template <int K, typename T, int EPI, bool EDGE>
 __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int frame, int tile, float* smem) {
@@ -550,7 +551,16 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
             char* row = (char*)(a.map + (int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch);
             *(float*)(row + cb) = val;
           }
-          acc += val;
+          if constexpr (EPI == 3) {
+            // Luminance-Weighted Pooling: weight of the reference's local mean
+            // mu_x = (mu_u + mu_v) / 2, 0 below a_s, a ramp over b_s, then 1
+            const float mx = 0.5f * ((Tu + Mu[j]) + (Tv + Mv[j]));
+            const float wgt = a.lw_b > 0.f ? fminf(fmaxf((mx - a.lw_a) / a.lw_b, 0.f), 1.f)
+                                           : (mx >= a.lw_a ? 1.f : 0.f);
+            acc = fmaf(wgt, val, acc);
+          } else {
+            acc += val;
+          }
         }
       };
       if constexpr (EPI != 1) {

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "launch.hpp"
@@ -375,7 +376,7 @@ void ms_weights(const float* weights, int n_scales, int flags, float* w) {
 ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, int mode,
                       float* map, int64_t map_pitch, int64_t map_bstride, float* out, int64_t out_stride,
                       float* partial, uint32_t* sat, int tile_idx, hipStream_t st, float* ds_x, float* ds_y,
-                      int* tiles_out) {
+                      int* tiles_out, const float* lw) {
   const Path path = choose_path(p, dtype);
   const float C1 = (float)p->C1, C2 = (float)p->C2;
   int err = 0, tiles = 0;
@@ -396,8 +397,16 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
       a.ds_y = ds_y;
       ds_done = true;
     }
-    err = launch_fast_stats(dtype, ds_done ? 2 : 0, a, batch, st);
+    int epi = ds_done ? 2 : 0;
+    if (lw) {
+      a.lw_a = lw[0];
+      a.lw_b = lw[1];
+      epi = 3;
+    }
+    err = launch_fast_stats(dtype, epi, a, batch, st);
     tiles = g.tiles_x * g.tiles_y;
+  } else if (lw) {
+    return SSIMX_ENOTSUP;  // luminance weights: the fast path only
   } else if (use_strided(p, dtype)) {
     FastArgs a{};
     g = strided_geom(p, W, H, tile_idx, batch);
@@ -479,11 +488,12 @@ ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, 
 
 static ssimx_status fwd_entry(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
                               float* map, int64_t map_pitch, int64_t map_bstride, float* score, void* ws,
-                              size_t ws_bytes, void* stream) {
+                              size_t ws_bytes, void* stream, const float* lw = nullptr) {
   ssimx_status s;
   if ((s = check_params(p)) != SSIMX_OK) return s;
   if ((s = check_images(ref, dis, batch)) != SSIMX_OK) return s;
   if ((s = check_path(p, ref->dtype)) != SSIMX_OK) return s;
+  if (lw && !use_fast(p, ref->dtype)) return SSIMX_ENOTSUP;
   int Wo, Ho;
   map_dims(p, ref->width, ref->height, Wo, Ho);
   if (Wo < 1 || Ho < 1) return SSIMX_ETOOSMALL;
@@ -500,7 +510,7 @@ static ssimx_status fwd_entry(const ssimx_params* p, const ssimx_image* ref, con
   PlaneArg x{ref->data, ref->pitch, ref->batch_stride}, y{dis->data, dis->pitch, dis->batch_stride};
   const int tile = pick_tile(p, ref->dtype, ref->width, ref->height, batch);
   return fwd_pass(p, ref->dtype, x, y, ref->width, ref->height, batch, 0, map, map_pitch, map_bstride, score, 1,
-                  partial, sat, tile, (hipStream_t)stream);
+                  partial, sat, tile, (hipStream_t)stream, nullptr, nullptr, nullptr, lw);
 }
 
 ssimx_status ms_forward(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
@@ -574,6 +584,13 @@ ssimx_status ssim_pooled(const ssimx_params* p, const ssimx_image* ref, const ss
                          float* score_out, void* ws, size_t ws_bytes, void* stream) {
   if (!score_out) return SSIMX_EINVAL;
   return fwd_entry(p, ref, dis, batch, nullptr, 0, 0, score_out, ws, ws_bytes, stream);
+}
+
+ssimx_status ssim_pooled_lw(const ssimx_params* p, const ssimx_image* ref, const ssimx_image* dis, int batch,
+                            float a_s, float b_s, float* score_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!score_out || !std::isfinite(a_s) || !std::isfinite(b_s) || b_s < 0.f) return SSIMX_EINVAL;
+  const float lw[2] = {a_s, b_s};
+  return fwd_entry(p, ref, dis, batch, nullptr, 0, 0, score_out, ws, ws_bytes, stream, lw);
 }
 
 ssimx_status msssim(const ssimx_params* p, const float* weights, int n_scales, int flags, const ssimx_image* ref,

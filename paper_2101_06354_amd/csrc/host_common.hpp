@@ -78,11 +78,12 @@ ssimx_status ms_bwd_levels(const ssimx_params* p, const float* w, int n_scales, 
 
 // ds_x, ds_y (nullable): also write the 2x2-average down-sampled planes
 // float32 [batch][H/2][W/2] (fused into the stride-1 band kernel when it runs
-// with valid borders, else a separate down-sampling launch).
+// with valid borders, else a separate down-sampling launch).  lw (nullable,
+// fast path only): {a_s, b_s} of luminance-weighted pooling.
 ssimx_status fwd_pass(const ssimx_params* p, int dtype, PlaneArg x, PlaneArg y, int W, int H, int batch, int mode,
                       float* map, int64_t map_pitch, int64_t map_bstride, float* out, int64_t out_stride,
                       float* partial, uint32_t* sat, int tile_idx, hipStream_t st, float* ds_x = nullptr,
-                      float* ds_y = nullptr, int* tiles_out = nullptr);
+                      float* ds_y = nullptr, int* tiles_out = nullptr, const float* lw = nullptr);
 ssimx_status ms_forward(const ssimx_params* p, const float* w, int n_scales, int flags, const ssimx_image* ref,
                         const ssimx_image* dis, int batch, float* score_out, float* cs_out, void* ws,
                         const MsLayout& L, hipStream_t st);

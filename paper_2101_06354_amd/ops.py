@@ -131,6 +131,21 @@ def ssim(x: torch.Tensor, y: torch.Tensor, cfg: SSIMConfig | None = None, return
     return score
 
 
+def ssim_lw(x: torch.Tensor, y: torch.Tensor, a_s: float, b_s: float, cfg: SSIMConfig | None = None, **kw):
+    """Luminance-weighted SSIM per frame (float32 [B]): the map weighted by
+    the reference x's local mean (0 below a_s, a ramp of length b_s, then 1),
+    summed and divided by the number of map positions."""
+    cfg = _cfg(cfg, kw)
+    xi, yi, b = _pair(x, y)
+    p = cfg.to_c()
+    ws = _workspace(workspace_size(cfg, L.OP_POOLED, xi.dtype, xi.height, xi.width, b), x.device)
+    score = torch.empty(b, dtype=torch.float32, device=x.device)
+    st = L.lib.ssim_pooled_lw(ctypes.byref(p), ctypes.byref(xi), ctypes.byref(yi), b, float(a_s), float(b_s),
+                              score.data_ptr(), ws.data_ptr(), ws.numel(), _stream(x))
+    L.check(st, "ssim_pooled_lw")
+    return score
+
+
 def _weights(weights, n_scales):
     if len(weights) < n_scales:
         raise ValueError("need one weight per scale")

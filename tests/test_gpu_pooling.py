@@ -155,3 +155,53 @@ def test_temporal_pooling_long_series(P, dev):
         for b in range(2):
             want = ref(s[b].astype(np.float64))
             assert abs(got[b] - want) <= _tol(want), (kind, b, got[b], want)
+
+
+# Luminance-Weighted Pooling subsection (ssim_pooled_lw): weights of the
+# reference's local mean inside the fast forward kernel.  Step limits are
+# placed away from every local mean of the frames (the float32 statistics
+# decide the step; a mean within 1e-3 of it could fall either side).
+def _lw_case(rng_seed, dtype):
+    if dtype == "u8":
+        x, y = synth.config0()
+        return x, y, 255.0
+    r, d = synth.config4(batch=1, h=150, w=171, stream=rng_seed)
+    return r[0, 0], d[0, 0], 1.0
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+@pytest.mark.parametrize("padding", ["valid", "reflect"])
+def test_luminance_weighted_pooling_against_oracle(P, dev, dtype, padding):
+    from _helpers import oparams
+    x, y, L = _lw_case(11, dtype)
+    cfg = P.SSIMConfig(L=L, padding=padding)
+    oc = oparams(cfg)
+    xt, yt = to_dev(x, dev)[None], to_dev(y, dev)[None]
+    base = P.ssim(xt, yt, cfg)
+    # a_s = b_s = 0 weighs every position 1: ssim_pooled's score bit for bit
+    assert torch.equal(P.ssim_lw(xt, yt, 0.0, 0.0, cfg), base)
+    mu1 = O.ssim_map(x, y, oc)["mu_x"]
+    lo, hi = float(mu1.min()), float(mu1.max())
+    cases = [(lo + 0.3 * (hi - lo), 0.25 * (hi - lo)), (lo + 0.1 * (hi - lo), 0.8 * (hi - lo)), (hi + 1.0, 5.0)]
+    step = lo + 0.55 * (hi - lo)
+    while np.abs(mu1 - step).min() < 1e-3 * max(1.0, L / 255.0):
+        step += 0.0137 * (hi - lo)
+    cases.append((step, 0.0))
+    for a_s, b_s in cases:
+        got = float(P.ssim_lw(xt, yt, a_s, b_s, cfg)[0])
+        want = O.pool_luminance_weighted(x, y, oc, a_s, b_s)
+        assert abs(got - want) <= SCORE_TOL, (a_s, b_s, got, want)
+
+
+def test_luminance_weighted_pooling_batch_and_refusals(P, dev):
+    x, y = synth.config1(frames=3, h=120, w=200)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    cfg = P.SSIMConfig()
+    s = P.ssim_lw(xt, yt, 60.0, 40.0, cfg)
+    from _helpers import oparams
+    for b in range(3):
+        assert abs(float(s[b]) - O.pool_luminance_weighted(x[b], y[b], oparams(cfg), 60.0, 40.0)) <= SCORE_TOL
+    with pytest.raises(Exception):
+        P.ssim_lw(xt, yt, 60.0, -1.0, cfg)  # negative ramp length
+    with pytest.raises(Exception):
+        P.ssim_lw(xt, yt, 60.0, 40.0, P.SSIMConfig(window="box", k=8))  # not the Gaussian fast path
