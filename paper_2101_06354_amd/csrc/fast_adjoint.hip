@@ -200,7 +200,14 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
   static_assert(S::CH == 16 && kTW == 64 && kNT == 256, "one pixel quad per thread and plane per chunk");
   __shared__ __align__(16) float C[kNM * S::CH * S::IWP];
   __shared__ __align__(16) float HM[kNM * S::PL];
-  __shared__ __align__(16) uint32_t XY[2][S::CH * kTW * sizeof(T) / 4];  // the chunk's x, y in their own packing
+  // 8- and 16-bit planes: the chunk's x, y quads are staged through LDS in
+  // their own packing (one 4- or 8-byte load per quad); float planes are
+  // loaded straight into the output stage's layout (one coalesced element per
+  // lane and row), which frees the 8 KB that would keep them at three
+  // workgroups per CU (staging 16-bit planes fits four anyway and measured
+  // faster than direct loads)
+  constexpr bool kStage = sizeof(T) <= 2;
+  __shared__ __align__(16) uint32_t XY[2][kStage ? S::CH * kTW * sizeof(T) / 4 : 1];
   constexpr int PL = S::PL;
   const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
   const int qx0 = __builtin_amdgcn_readfirstlane(txi * kTW), qy0 = __builtin_amdgcn_readfirstlane(tyi * a.QH);
@@ -220,20 +227,37 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
   const int qy_end = __builtin_amdgcn_readfirstlane(min(a.g.H, qy0 + a.QH));
   fetch_coef<K>(a, frame, qy0, c0, S::CH, q);
   fast::Quad<T> px4, py4;
-  fetch_xy<T>(a, X, Y, qy0, qx0, px4, py4);
+  if constexpr (kStage) fetch_xy<T>(a, X, Y, qy0, qx0, px4, py4);
+  const int gr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
+  const int px = qx0 + c;
   for (int cy = qy0; cy < qy_end; cy += S::CH) {
     __syncthreads();
     store_coef<K>(q, S::CH, C);
+    T xd[4], yd[4];  // direct path: this chunk's pixels of the lane's output column
+    if constexpr (kStage) {
 #pragma unroll
-    for (int w = 0; w < fast::Quad<T>::NW; ++w) {
-      XY[0][threadIdx.x * fast::Quad<T>::NW + w] = px4.w[w];
-      XY[1][threadIdx.x * fast::Quad<T>::NW + w] = py4.w[w];
+      for (int w = 0; w < fast::Quad<T>::NW; ++w) {
+        XY[0][threadIdx.x * fast::Quad<T>::NW + w] = px4.w[w];
+        XY[1][threadIdx.x * fast::Quad<T>::NW + w] = py4.w[w];
+      }
+    } else {
+      // issued here so that the row pass hides their latency
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int py = cy + 4 * gr + j;  // wave-uniform
+        xd[j] = T{};
+        yd[j] = T{};
+        if (py < qy_end && px < a.g.W) {
+          xd[j] = (X + (int64_t)py * a.x.pitch)[px];
+          yd[j] = (Y + (int64_t)py * a.y.pitch)[px];
+        }
+      }
     }
     // the next chunk's quads are loaded while this chunk's row and column
     // passes run (the registers were just staged)
     if (cy + S::CH < qy_end) {
       fetch_coef<K>(a, frame, cy + S::CH, c0, S::CH, q);
-      fetch_xy<T>(a, X, Y, cy + S::CH, qx0, px4, py4);
+      if constexpr (kStage) fetch_xy<T>(a, X, Y, cy + S::CH, qx0, px4, py4);
     }
     __syncthreads();
     coef_row_pass<K>(taps, C, S::CH, HM, S::HALO);
@@ -242,8 +266,6 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
     // cy + 4 w .. cy + 4 w + 3, so every output row base is wave-uniform
     static_assert((S::CH / 4) * kTW == kNT, "one column-pass item per thread, one row group per wave");
     {
-      const int gr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
-      const int px = qx0 + c;
       float G[kNM][4];
 #pragma unroll
       for (int m = 0; m < kNM; ++m)
@@ -270,11 +292,16 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
       for (int j = 0; j < 4; ++j) {
         const int py = cy + 4 * gr + j;  // wave-uniform
         if (py >= qy_end || px >= a.g.W) continue;
-        // staged row 4 gr + j, column c (quads are stored row-major, 16 per row)
-        const int e = ((4 * gr + j) * kTW + c) * (int)sizeof(T);
         T xe, ye;
-        __builtin_memcpy(&xe, xs + e, sizeof(T));
-        __builtin_memcpy(&ye, ys + e, sizeof(T));
+        if constexpr (kStage) {
+          // staged row 4 gr + j, column c (quads are stored row-major, 16 per row)
+          const int e = ((4 * gr + j) * kTW + c) * (int)sizeof(T);
+          __builtin_memcpy(&xe, xs + e, sizeof(T));
+          __builtin_memcpy(&ye, ys + e, sizeof(T));
+        } else {
+          xe = xd[j];
+          ye = yd[j];
+        }
         const float xv = to_f32<T>(xe), yv = to_f32<T>(ye);
         // dL/dy = W^T A + (u - t_u) W^T B_u - (v - t_v) W^T B_v
         float gy = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]) - ((xv - yv) - a.tv) * G[2][j];
