@@ -400,6 +400,9 @@ __device__ __forceinline__ void row_pass(const float* taps, const float* U, cons
       float au = 0.f, av = 0.f, qu = 0.f, qv = 0.f;
 #pragma unroll
       for (int t = 0; t < K; ++t) {
+        // the centring element's own terms are 0 for finite inputs; a
+        // non-finite one already makes t, and so every output, non-finite
+        if (j + t == S::SHIFT) continue;
         const float w = taps[t];
         au = fmaf(w, du[j + t], au);
         av = fmaf(w, dv[j + t], av);
@@ -523,16 +526,23 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
 #pragma unroll
       for (int m = 0; m < K + 3; ++m) {
         const float4 h = hb[m * (S::RS / 4)];
+        // the centring row (m == SHIFT) adds only its variances: its mean
+        // deviations are 0 for finite values, and a non-finite one already
+        // makes T, and so every output, non-finite
+        constexpr int kSelf = S::SHIFT;
+        const bool self = m == kSelf;
         const float du = h.x - Tu, dv = h.y - Tv;
-        const float su = fmaf(du, du, h.z);
-        const float sv = fmaf(dv, dv, h.w);
+        const float su = self ? h.z : fmaf(du, du, h.z);
+        const float sv = self ? h.w : fmaf(dv, dv, h.w);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int t = m - j;
           if (t >= 0 && t < K) {
             const float w = taps[t];
-            Mu[j] = fmaf(w, du, Mu[j]);
-            Mv[j] = fmaf(w, dv, Mv[j]);
+            if (!self) {
+              Mu[j] = fmaf(w, du, Mu[j]);
+              Mv[j] = fmaf(w, dv, Mv[j]);
+            }
             Su[j] = fmaf(w, su, Su[j]);
             Sv[j] = fmaf(w, sv, Sv[j]);
           }
