@@ -134,6 +134,9 @@ __device__ __forceinline__ void st_row_pass(const float* taps, const float* U, c
     float au = 0.f, av = 0.f, qu = 0.f, qv = 0.f;
 #pragma unroll
     for (int t = 0; t < K; ++t) {
+      // the middle element's deviations are 0 for finite inputs (a
+      // non-finite one already makes the centring value non-finite)
+      if (t == K / 2) continue;
       const float du = u[t] - tu, dv = v[t] - tv;
       au = fmaf(taps[t], du, au);
       av = fmaf(taps[t], dv, av);
@@ -202,6 +205,11 @@ __device__ __forceinline__ float strided_tile(const FastArgs& a, int frame, int 
       float Mu = 0.f, Mv = 0.f, Su = 0.f, Sv = 0.f;
 #pragma unroll
       for (int m = 0; m < K; ++m) {
+        if (m == K / 2) {  // the centring row adds only its variances
+          Su = fmaf(taps[m], h[2 * Sh::PLB + m * Sh::BWP], Su);
+          Sv = fmaf(taps[m], h[3 * Sh::PLB + m * Sh::BWP], Sv);
+          continue;
+        }
         const float du = h[m * Sh::BWP] - Tu, dv = h[Sh::PLB + m * Sh::BWP] - Tv;
         Mu = fmaf(taps[m], du, Mu);
         Mv = fmaf(taps[m], dv, Mv);
