@@ -99,12 +99,19 @@ def test_loss_call_against_composed_path(P, dev):
 # coarsest term (a seventh pass), cs clamping and the weighted-sum
 # aggregation; the level-by-level route with padded borders; rows that are not
 # 16-byte aligned (a view of wider planes) and bfloat16 storage.
-@pytest.mark.parametrize("case", ["five_scales_split_clamp", "sum", "reflect", "unaligned_rows", "bf16_unaligned"])
+@pytest.mark.parametrize("case", ["five_scales_split_clamp", "sum", "reflect", "unaligned_rows", "bf16_unaligned",
+                                  "one_scale_split", "two_scales", "gaussian_k7"])
 def test_loss_options_against_composed_path(P, dev, case):
     h, w, kw = 144, 186, dict(n_scales=3, renorm=True)
     cfg = P.SSIMConfig(L=1.0)
     if case == "five_scales_split_clamp":
         h, w, kw = 181, 195, dict(n_scales=5, renorm=True, cs_clamp=True, coarse_separate=True)
+    elif case == "one_scale_split":  # no pyramid level; the split l pass on the luma planes
+        kw = dict(n_scales=1, renorm=True, coarse_separate=True)
+    elif case == "two_scales":  # one level from the luma kernel, none from the second level
+        kw = dict(n_scales=2, renorm=True)
+    elif case == "gaussian_k7":
+        cfg = P.SSIMConfig(L=1.0, k=7, sigma=1.0)
     elif case == "sum":
         kw = dict(n_scales=4, renorm=False, aggregation="sum")
     elif case == "reflect":
