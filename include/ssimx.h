@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define SSIMX_VERSION 100
+#define SSIMX_VERSION 101
 
 typedef enum {
   SSIMX_OK = 0,

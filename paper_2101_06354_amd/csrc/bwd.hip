@@ -305,7 +305,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
   int err = 0;
   FastArgs fa{};
   if (fast) {
-    fill_fast_common(fa, &pf, lv.dtype, lv.x, lv.y, fast_geom(&pf, lv.W, lv.H, 0, batch));
+    fill_fast_common(fa, &pf, lv.dtype, lv.x, lv.y, fast_geom(&pf, lv.W, lv.H, 0, batch, kCoefTileRows));
     fa.mode = mode;
     fa.grad_map = grad_map;
     fa.gm_pitch = gm_pitch;

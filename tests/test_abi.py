@@ -416,11 +416,12 @@ def test_tune_cache_rejects_malformed_files(L, tmp_path, text):
 def test_tune_cache_rejects_missing_binary_and_oversized_files(L, tmp_path):
     assert L.lib.ssimx_tune_cache_load(str(tmp_path / "absent.json").encode()) == L.EINVAL
     assert L.lib.ssimx_tune_cache_load(None) == L.EINVAL
+    v = L.lib.ssimx_version()  # the current version: only the content may be refused
     b = tmp_path / "binary.json"
-    b.write_bytes(b'{"version": 100, "entries": {"cpu-bad|\x01": 1}}')
+    b.write_bytes(b'{"version": %d, "entries": {"cpu-bad|\x01": 1}}' % v)
     assert L.lib.ssimx_tune_cache_load(str(b).encode()) == L.EINVAL
     big = tmp_path / "big.json"
-    big.write_text('{"version": 100, "entries": {' + " " * (1 << 20) + "}}")
+    big.write_text('{"version": %d, "entries": {' % v + " " * (1 << 20) + "}}")
     assert L.lib.ssimx_tune_cache_load(str(big).encode()) == L.EINVAL
 
 
