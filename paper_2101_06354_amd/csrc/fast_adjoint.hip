@@ -153,21 +153,25 @@ __device__ __forceinline__ void store_coef(const CQuad* q, int nrows, float* C) 
   }
 }
 
-// Row pass of the transposed window: an item is one plane of one row and 4
-// adjacent outputs.  Consecutive lanes take consecutive 4-column groups of
-// the same plane and row, so every 8-lane phase of a 16-byte LDS read
-// touches 32 distinct banks.
+// Row pass of the transposed window: thread t takes row t / 16 and the 4
+// adjacent outputs of column group t % 16, in all three planes (a fixed
+// mapping: no index arithmetic per item).  Consecutive lanes take
+// consecutive 4-column groups of the same row, so every 8-lane phase of a
+// 16-byte LDS read touches 32 distinct banks.
 template <int K>
 __device__ __forceinline__ void coef_row_pass(const float* taps, const float* C, int nrows, float* HM, int band0) {
   using S = AShape<K>;
   constexpr int PLC = S::CH * S::IWP;
-  constexpr int NG = kTW / 4;
-  for (int it = threadIdx.x; it < nrows * kNM * NG; it += kNT) {
-    const int gq = it % NG, m = (it / NG) % kNM, r = it / (kNM * NG);
+  static_assert(kTW / 4 == 16 && kNT == 16 * S::CH, "one row and column group per thread");
+  const int r = threadIdx.x >> 4, gq = threadIdx.x & 15;
+  if (r >= nrows) return;
+  const float* src = C + r * S::IWP + 4 * gq;
+  float* dst = HM + (band0 + r) * kTWP + 4 * gq;
+#pragma unroll
+  for (int m = 0; m < kNM; ++m) {
     float z[4 * S::NREAD];
 #pragma unroll
-    for (int n = 0; n < S::NREAD; ++n)
-      *(float4*)&z[4 * n] = *(const float4*)&C[m * PLC + r * S::IWP + 4 * gq + 4 * n];
+    for (int n = 0; n < S::NREAD; ++n) *(float4*)&z[4 * n] = *(const float4*)&src[m * PLC + 4 * n];
     float h[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -176,19 +180,24 @@ __device__ __forceinline__ void coef_row_pass(const float* taps, const float* C,
       for (int t = 0; t < K; ++t) acc = fmaf(taps[t], z[S::LP + j + t], acc);
       h[j] = acc;
     }
-    *(float4*)&HM[m * S::PL + (band0 + r) * kTWP + 4 * gq] = make_float4(h[0], h[1], h[2], h[3]);
+    *(float4*)&dst[m * S::PL] = make_float4(h[0], h[1], h[2], h[3]);
   }
 }
 
+// The band's last K - 1 rows move to its top (thread t: row t / 16, column
+// group t % 16, all planes; the source rows CH.. and the destination rows
+// 0..K-2 do not overlap).
 template <int K>
 __device__ __forceinline__ void coef_band_shift(float* HM) {
   using S = AShape<K>;
-  constexpr int NV = S::HALO * kTW / 4;
-  for (int it = threadIdx.x; it < kNM * NV; it += kNT) {
-    const int m = it / NV, e = it - m * NV;
-    const int row = e / (kTW / 4), q = e % (kTW / 4);
-    *(float4*)&HM[m * S::PL + row * kTWP + 4 * q] = *(const float4*)&HM[m * S::PL + (S::CH + row) * kTWP + 4 * q];
-  }
+  static_assert(S::HALO <= S::CH && kNT == 16 * S::CH, "one row and column group per thread");
+  const int row = threadIdx.x >> 4, q = threadIdx.x & 15;
+  if (row >= S::HALO) return;
+  float4 v[kNM];
+#pragma unroll
+  for (int m = 0; m < kNM; ++m) v[m] = *(const float4*)&HM[m * S::PL + (S::CH + row) * kTWP + 4 * q];
+#pragma unroll
+  for (int m = 0; m < kNM; ++m) *(float4*)&HM[m * S::PL + row * kTWP + 4 * q] = v[m];
 }
 
 }  // namespace
