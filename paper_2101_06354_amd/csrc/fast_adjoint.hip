@@ -321,8 +321,7 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
             gy += 0.25f * *(const float*)(crow + 4u * (uint32_t)cxx);
           }
         }
-        char* orow = (char*)(a.out + (int64_t)frame * a.out_bstride + (int64_t)py * a.out_pitch);
-        *(float*)(orow + 4u * (uint32_t)px) = gy;
+        store_row_f32(a.out + (int64_t)frame * a.out_bstride + (int64_t)py * a.out_pitch + qx0, 4u * (uint32_t)c, gy);
       }
     }
     __syncthreads();

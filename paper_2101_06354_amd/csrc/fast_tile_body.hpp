@@ -518,7 +518,7 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
       const int gr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
       const int oj = ox0 + c;
       const bool col_in = oj < a.g.Wo;
-      const uint32_t cb = 4u * (uint32_t)oj;  // byte offset of the lane's column in a float row
+      const uint32_t cb = 4u * (uint32_t)c;  // byte offset of the lane's column from the tile's first
       const float4* hb = (const float4*)(HM + 4 * gr * S::RS) + (c + c / 8);  // (mean_u, mean_v, var_u, var_v)
       const float Tu = hb[S::SHIFT * (S::RS / 4)].x, Tv = hb[S::SHIFT * (S::RS / 4)].y;
       float Mu[4] = {0.f, 0.f, 0.f, 0.f}, Mv[4] = {0.f, 0.f, 0.f, 0.f};
@@ -558,8 +558,7 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
           const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
           const float val = ssim_value_uv_m<M>(Tu + Mu[j], Tv + Mv[j], var_u, var_v, c1x2, c2x2);
           if (a.map) {
-            char* row = (char*)(a.map + (int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch);
-            *(float*)(row + cb) = val;
+            store_row_f32(a.map + (int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + ox0, cb, val);
           }
           if constexpr (EPI == 3) {
             // Luminance-Weighted Pooling: weight of the reference's local mean
@@ -588,7 +587,7 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
           const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
           float g = gframe;
           if (a.grad_map) {
-            const char* row = (const char*)(a.grad_map + (int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch);
+            const char* row = (const char*)(a.grad_map + (int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch + ox0);
             g = *(const float*)(row + cb);
           }
           // reciprocal estimates (about 1 ulp) suffice for the adjoint.
@@ -616,10 +615,10 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
                                 fmaf(-bu, mean_u - a.tu, bv * (mean_v - a.tv)));
           // W^T is linear: the two A maps are combined before the transpose
           const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
-          char* row = (char*)(a.coef + ((int64_t)frame * a.g.Ho + oi) * a.cpitch);
-          *(float*)(row + cb) = ca;
-          *(float*)(row + 4 * qs + cb) = bu;
-          *(float*)(row + 8 * qs + cb) = bv;
+          float* row = a.coef + ((int64_t)frame * a.g.Ho + oi) * a.cpitch + ox0;
+          store_row_f32(row, cb, ca);
+          store_row_f32(row + qs, cb, bu);
+          store_row_f32(row + 2 * qs, cb, bv);
         }
       }
     }

@@ -209,6 +209,16 @@ __device__ __forceinline__ void seg_tile(const int* start, int s, int tiles, int
   tile = l - frame * tiles;
 }
 
+// Store of one float at byte offset `off` from a wave-uniform address (a
+// row's first column of the tile): a raw buffer store takes the 32-bit lane
+// offset as is, where a global store would form a 64-bit address per lane
+// with vector instructions.  `off` must stay below 2^31.
+__device__ __forceinline__ void store_row_f32(float* row, uint32_t off, float v) {
+  // gfx9 raw buffer: stride 0, range check against num_records only
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(row, 0, 0x7fffffff, 0x00020000);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
+}
+
 struct PlaneArg {
   const void* data;
   int64_t pitch, bstride;
