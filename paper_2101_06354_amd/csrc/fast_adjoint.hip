@@ -332,7 +332,7 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
 template <int K, typename T>
 __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
   int tile, frame;
-  xcd_tile(tile, frame);
+  xcd_tile_rows_last(a.qtiles_x, a.qtiles_y, tile, frame);
   fast_adjoint_tile<K, T>(a, frame, tile);
 }
 

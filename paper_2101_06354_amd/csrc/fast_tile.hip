@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kNT, sizeof(T) == 4 ? 3 : 4) void fast_stats_kernel
   __shared__ __align__(16) float smem[fast_smem_floats<K>()];
   __shared__ float red[kNT / 64];
   int tile, frame;
-  xcd_tile(tile, frame);
+  xcd_tile_rows_last(a.g.tiles_x, a.g.tiles_y, tile, frame);
   const float acc = fast_stats_tile<K, T, EPI>(a, frame, tile, smem);
   if constexpr (EPI != 1) {
     const float tot = block_sum<kNT>(acc, red);

@@ -192,6 +192,37 @@ __device__ __forceinline__ void xcd_tile(int& tile, int& frame) {
   tile = l - frame * nx;
 }
 
+// The same XCD ranges for a (tiles_x * tiles_y, frames) grid, with each
+// XCD taking the tiles of its range that lie in a frame's last tile row
+// after all its other tiles.  The last row is usually shorter (the map
+// height is rarely a multiple of the tile height), so the launch ends on
+// short tiles instead of full ones that would leave CUs idle.  Within the
+// XCD's range [lo, lo + cnt), the i-th workgroup takes the i-th tile of the
+// range's full rows, in order, then the range's last-row tiles in order (a
+// bijection on the range).
+__device__ __forceinline__ void xcd_tile_rows_last(int tiles_x, int tiles_y, int& tile, int& frame) {
+  const int T = gridDim.x;  // tiles per frame, tiles_x * tiles_y
+  const int n = T * gridDim.y;
+  const int b = blockIdx.x + T * blockIdx.y;
+  const int per = n >> 3, rem = n & 7, x = b & 7, i = b >> 3;
+  const int lo = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+  const int cnt = x < rem ? per + 1 : per;
+  const int body = tiles_x * (tiles_y - 1);  // tiles above the last row, per frame
+  // tiles of the full rows among logical indices [0, m)
+  auto full_before = [&](int m) { return (m / T) * body + min(m - (m / T) * T, body); };
+  const int f0 = full_before(lo), nf = full_before(lo + cnt) - f0;
+  int l;
+  if (i < nf) {
+    const int c = f0 + i;  // the c-th full-row tile of the grid (body > 0 here)
+    l = (c / body) * T + c % body;
+  } else {
+    const int c = (lo - f0) + (i - nf);  // the c-th last-row tile of the grid
+    l = (c / tiles_x) * T + body + c % tiles_x;
+  }
+  frame = l / T;
+  tile = l - frame * T;
+}
+
 // A launch made of segments, segment s owning workgroups [start[s],
 // start[s + 1]) of a one-dimensional grid (start[0] = 0), each laid over its
 // own (tiles, frames) grid with the XCD mapping above taken within the
