@@ -254,13 +254,14 @@ float shift_guess(const ssimx_params* p) {
   return (float)(sqrt(p->C2) / 0.03);
 }
 
-// Pixel tiles of the fast adjoint: 256-row tiles halve the share of the
-// K - 1 prologue rows when the launch still holds >= 4096 workgroups;
-// smaller launches take 128 rows, halved down to 32 while they would hold
-// fewer than 1024 workgroups.
+// Pixel tiles of the fast adjoint: the tallest of 512, 256 and 128 rows
+// (fewer K - 1 prologue rows per pixel) whose launch still holds >= 4096
+// workgroups; smaller launches take 128 rows, halved down to 32 while they
+// would hold fewer than 1024 workgroups.
 void adjoint_tiles(FastArgs& fa, int W, int H, int batch) {
   fa.qtiles_x = (W + 63) / 64;
-  fa.QH = (int64_t)fa.qtiles_x * ((H + 255) / 256) * batch >= 4096 ? 256 : 128;
+  fa.QH = 512;
+  while (fa.QH > 128 && (int64_t)fa.qtiles_x * ((H + fa.QH - 1) / fa.QH) * batch < 4096) fa.QH /= 2;
   while (fa.QH > 32 && (int64_t)fa.qtiles_x * ((H + fa.QH - 1) / fa.QH) * batch < 1024) fa.QH /= 2;
   fa.qtiles_y = (H + fa.QH - 1) / fa.QH;
 }
@@ -305,7 +306,7 @@ static ssimx_status bwd_level(const ssimx_params* p, const BwdLevel& lv, int bat
   int err = 0;
   FastArgs fa{};
   if (fast) {
-    fill_fast_common(fa, &pf, lv.dtype, lv.x, lv.y, fast_geom(&pf, lv.W, lv.H, 0, batch, kCoefTileRows));
+    fill_fast_common(fa, &pf, lv.dtype, lv.x, lv.y, coef_geom(&pf, lv.W, lv.H, batch));
     fa.mode = mode;
     fa.grad_map = grad_map;
     fa.gm_pitch = gm_pitch;

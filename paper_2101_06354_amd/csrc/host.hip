@@ -84,11 +84,12 @@ static const TileCfg kTiles[] = {{32, 32}, {64, 16}, {64, 32}, {32, 16}, {128, 8
 
 // 16-row chunks per tile of the stride-1 fast kernels, for the same index.
 // Each tile recomputes K - 1 rows of statistics above its first output row:
-// 256 rows spend 3.9% of the row passes there against 7.8% at 128 rows
-// (64 x 1080p Gaussian forward 0.566 -> 0.545 ms; 512 rows measured
-// 0.556 ms).  Small launches shorten the tile by the fill rule below, and the
-// coefficient pass keeps 128 rows.
-static const int kFastChunks[] = {16, 4, 32, 2, 8, 68};
+// 512 rows spend 1.9% of the row passes there, 128 rows 7.8%.  The kernels
+// take each frame's (shorter) last tile row after the full ones, so tall
+// tiles no longer leave the end of a launch to a few long tiles (64 x 1080p
+// Gaussian forward: 128 rows 0.566 ms, 256 rows 0.525 ms, 512 rows 0.519 ms).
+// Small launches shorten the tile by the fill rule below.
+static const int kFastChunks[] = {32, 4, 16, 2, 8, 68};
 
 int num_tile_cfgs() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
 int fast_chunks(int idx) { return kFastChunks[(idx >= 0 && idx < num_tile_cfgs()) ? idx : 0]; }
@@ -149,7 +150,12 @@ static int fill_rows(int rows, int min_rows, int64_t tiles_x, int Ho, int batch,
 Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch, int rows0) {
   int Wo, Ho;
   map_dims(p, W, H, Wo, Ho);
-  const int rows = (tile_idx == 0 && rows0 > 0) ? rows0 : 16 * fast_chunks(tile_idx);
+  int rows = (tile_idx == 0 && rows0 > 0) ? rows0 : 16 * fast_chunks(tile_idx);
+  // the default's 512 rows only while the launch keeps >= 4096 workgroups
+  // (fewer, longer tiles end a launch less evenly), else 256
+  if (tile_idx == 0 && rows0 == 0 && batch > 0 && rows > 256 &&
+      (int64_t)((Wo + 63) / 64) * ((Ho + rows - 1) / rows) * batch < 4096)
+    rows = 256;
   const int th = fill_rows(rows, 32, (Wo + 63) / 64, Ho, batch, tile_idx, 16, kFillMinWork);
   Geom g = geom_with(p, W, H, 64, th);
   g.TW = 64;
@@ -157,6 +163,11 @@ Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch, int
   g.tiles_x = (g.Wo + 63) / 64;
   g.tiles_y = (g.Ho + g.TH - 1) / g.TH;
   return g;
+}
+
+Geom coef_geom(const ssimx_params* p, int W, int H, int batch) {
+  const Geom g = fast_geom(p, W, H, 0, batch, 256);
+  return (int64_t)g.tiles_x * g.tiles_y * batch >= 8192 ? g : fast_geom(p, W, H, 0, batch, 128);
 }
 
 // Input rows per tile of the 8-bit box band kernel, for the same index.

@@ -35,10 +35,11 @@ int dtype_size(int dtype);
 // batch > 0: fill small launches; rows0 > 0: the default index's tile height
 // instead of the table's (a multiple of 16, at most the table's largest)
 Geom fast_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch = 0, int rows0 = 0);
-// Default tile height of the coefficient passes (pooled backward, training
-// loss): the pooled backward of 64 x 1080p frames measured 1.39 ms at 128
-// rows and 1.42 ms at 512.
-constexpr int kCoefTileRows = 128;
+// Tiles of the coefficient passes (pooled backward, training loss): 256 rows
+// when the launch still holds >= 8192 workgroups, else 128 (the coefficient
+// kernel writes three planes per position and loses less to short launches
+// on shorter tiles); small launches shorten them further by the fill rule.
+Geom coef_geom(const ssimx_params* p, int W, int H, int batch);
 Geom band_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch = 0);
 Geom strided_geom(const ssimx_params* p, int W, int H, int tile_idx, int batch = 0);
 bool use_strided(const ssimx_params* p, int dtype);

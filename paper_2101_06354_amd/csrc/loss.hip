@@ -556,7 +556,7 @@ ssimx_status seg_backward(const LossShape& sh, const LossLayout& l, char* ws, hi
     const int64_t pl = (int64_t)F.W[j] * F.H[j];
     const float* x = j ? (const float*)(msb + F.lvl_x_off[j]) : (const float*)(ws + l.yr);
     const float* y = j ? (const float*)(msb + F.lvl_y_off[j]) : (const float*)(ws + l.yd);
-    const Geom g = fast_geom(&pf, F.W[j], F.H[j], 0, B, kCoefTileRows);
+    const Geom g = coef_geom(&pf, F.W[j], F.H[j], B);
     FastArgs& a = fs.seg[j];
     fill_fast_common(a, &pf, SSIMX_F32, PlaneArg{x, F.W[j], pl}, PlaneArg{y, F.W[j], pl}, g);
     a.mode = j == M - 1 ? (split ? 3 : 0) : 1;
