@@ -455,7 +455,12 @@ __host__ __device__ constexpr int fast_smem_floats() {
 // a.ds_x, a.ds_y; EPI 3: forward with luminance-weighted values) or 0 (EPI 1:
 // adjoint coefficients).  `smem` holds
 // fast_smem_floats<K>() floats.
-template <int K, typename T, int EPI, bool EDGE>
+// GMAP (EPI 1): the upstream is a per-position map (a.grad_map) rather than
+// per-frame scalars.  It is a separate body because a load in the epilogue
+// makes the compiler wait there for every older memory operation (the next
+// chunk's prefetch and the previous outputs' stores) on both paths of a
+// runtime branch.
+template <int K, typename T, int EPI, bool EDGE, bool GMAP = false>
 __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int frame, int tile, float* smem) {
   using S = Shape<K>;
   float* U = smem;
@@ -488,7 +493,7 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
   if constexpr (down) emit_down<K>(a, U, V, oy0, S::HALO, ox0, oy0, own_r1, own_c1, frame);
   row_pass<K>(taps, U, V, S::HALO, HM, 0);
 
-  const float gframe = (EPI == 1 && !a.grad_map) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
+  const float gframe = (EPI == 1 && !GMAP) ? a.gscale[(int64_t)frame * a.gscale_stride] * a.gmul : 0.f;
   const float gl_frame = (EPI == 1 && a.mode == 3) ? a.gscale2[(int64_t)frame * a.gscale2_stride] * a.gmul : 0.f;
   float acc = 0.f;
   const float c1x2 = 2.f * a.C1, c2x2 = 2.f * a.C2;
@@ -586,7 +591,7 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
         {
           const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
           float g = gframe;
-          if (a.grad_map) {
+          if constexpr (GMAP) {
             const char* row = (const char*)(a.grad_map + (int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch + ox0);
             g = *(const float*)(row + cb);
           }
@@ -638,6 +643,11 @@ template <int K, typename T, int EPI>
 __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, int tile, float* smem) {
   const int txi = tile % a.g.tiles_x;
   const bool interior = a.vec_ok && a.g.pad == SSIMX_PAD_VALID && txi * kTW + Shape<K>::IWP <= a.g.W;
+  if constexpr (EPI == 1) {
+    if (a.grad_map)
+      return interior ? fast_stats_tile_body<K, T, EPI, false, true>(a, frame, tile, smem)
+                      : fast_stats_tile_body<K, T, EPI, true, true>(a, frame, tile, smem);
+  }
   return interior ? fast_stats_tile_body<K, T, EPI, false>(a, frame, tile, smem)
                   : fast_stats_tile_body<K, T, EPI, true>(a, frame, tile, smem);
 }
