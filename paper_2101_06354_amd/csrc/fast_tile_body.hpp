@@ -499,6 +499,15 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
   const float c1x2 = 2.f * a.C1, c2x2 = 2.f * a.C2;
   const int oy_end = __builtin_amdgcn_readfirstlane(min(a.g.Ho, oy0 + a.g.TH));
   fetch_chunk<K, T, EDGE>(a, X, Y, oy0 + S::HALO, ox0, cl, qx, qy);
+  if constexpr (EPI == 1 && !GMAP) {
+    // as many dropped stores as a chunk's epilogue issues: on entry to the
+    // chunk loop the prefetch then lies as far behind the newest memory
+    // operation as in every later iteration, so the one wait for it at the
+    // top of the loop can leave the previous chunk's twelve coefficient
+    // stores in flight (the forward's four stores measured better waited for)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) store_row_f32(nullptr, kStoreDrop + 4u * i, 0.f);  // distinct: none merged
+  }
   for (int cy = oy0; cy < oy_end; cy += kCH) {
     __syncthreads();  // U, V free; band rows [0, HALO) ready
     store_chunk<K, T>(qx, qy, U, V, ch);
@@ -524,6 +533,10 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
       const int oj = ox0 + c;
       const bool col_in = oj < a.g.Wo;
       const uint32_t cb = 4u * (uint32_t)c;  // byte offset of the lane's column from the tile's first
+      // coefficient stores: the same, or the dropped offset past the map's last
+      // column; a row past the tile's last ORs in the dropped offset too (a
+      // uniform choice, so no store is split into exec-masked branches)
+      const uint32_t lane_off = col_in ? cb : kStoreDrop;
       const float4* hb = (const float4*)(HM + 4 * gr * S::RS) + (c + c / 8);  // (mean_u, mean_v, var_u, var_v)
       const float Tu = hb[S::SHIFT * (S::RS / 4)].x, Tv = hb[S::SHIFT * (S::RS / 4)].y;
       float Mu[4] = {0.f, 0.f, 0.f, 0.f}, Mv[4] = {0.f, 0.f, 0.f, 0.f};
@@ -585,7 +598,8 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
 #pragma unroll
       for (int j = 0; j < 4 && EPI == 1; ++j) {
         const int oi = cy + 4 * gr + j;  // wave-uniform
-        if (oi >= oy_end || !col_in) continue;
+        if constexpr (GMAP)
+          if (oi >= oy_end || !col_in) continue;  // the upstream map is read only inside the map
         const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
         const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
         {
@@ -620,10 +634,14 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
                                 fmaf(-bu, mean_u - a.tu, bv * (mean_v - a.tv)));
           // W^T is linear: the two A maps are combined before the transpose
           const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
-          float* row = a.coef + ((int64_t)frame * a.g.Ho + oi) * a.cpitch + ox0;
-          store_row_f32(row, cb, ca);
-          store_row_f32(row + qs, cb, bu);
-          store_row_f32(row + 2 * qs, cb, bv);
+          // every row and lane stores, outside the map with the dropped
+          // offset: a fixed twelve stores per chunk, which the wait for the
+          // next chunk's loads at the top of the loop leaves in flight
+          float* row = a.coef + ((int64_t)frame * a.g.Ho + min(oi, oy_end - 1)) * a.cpitch + ox0;
+          const uint32_t off = lane_off | (oi < oy_end ? 0u : kStoreDrop);
+          store_row_f32(row, off, ca);
+          store_row_f32(row + qs, off, bu);
+          store_row_f32(row + 2 * qs, off, bv);
         }
       }
     }

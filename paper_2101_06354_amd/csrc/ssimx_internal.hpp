@@ -244,6 +244,11 @@ __device__ __forceinline__ void seg_tile(const int* start, int s, int tiles, int
 // row's first column of the tile): a raw buffer store takes the 32-bit lane
 // offset as is, where a global store would form a 64-bit address per lane
 // with vector instructions.  `off` must stay below 2^31.
+// An offset store_row_f32 drops (past the buffer's range, so the hardware
+// discards the store): a loop can then issue the same number of stores on
+// every path, and the compiler's wait for its loads need not include them.
+constexpr uint32_t kStoreDrop = 0x80000000u;
+
 __device__ __forceinline__ void store_row_f32(float* row, uint32_t off, float v) {
   // gfx9 raw buffer: stride 0, range check against num_records only
   const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(row, 0, 0x7fffffff, 0x00020000);
