@@ -202,21 +202,36 @@ __device__ __forceinline__ void coef_band_shift(float* HM) {
 
 }  // namespace
 
-// The adjoint of one (tile, frame): 64 pixel columns by a.QH pixel rows.
+// LDS of the adjoint tile, declared once per kernel (the tile bodies of one
+// kernel share it).  8- and 16-bit planes: the chunk's x, y quads are staged
+// through LDS in their own packing (one 4- or 8-byte load per quad); float
+// planes are loaded straight into the output stage's layout (one coalesced
+// element per lane and row), which frees the 8 KB that would keep them at
+// three workgroups per CU (staging 16-bit planes fits four anyway and
+// measured faster than direct loads).
 template <int K, typename T>
-__device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, int tile) {
+struct AdjSmem {
+  static constexpr bool kStage = sizeof(T) <= 2;
+  __align__(16) float C[kNM * AShape<K>::CH * AShape<K>::IWP];
+  __align__(16) float HM[kNM * AShape<K>::PL];
+  __align__(16) uint32_t XY[2][kStage ? AShape<K>::CH * kTW * sizeof(T) / 4 : 1];
+};
+
+// The adjoint of one (tile, frame): 64 pixel columns by a.QH pixel rows.
+// COARSE: a coarser scale's gradient is added through the 2x2 transpose.  It
+// is a separate body because its load in the output stage makes the
+// compiler wait there for every older memory operation; without it the
+// output stage issues a fixed four stores per chunk (rows past the tile and
+// columns past the plane with the dropped offset), and the wait for the next
+// chunk's loads at the top of the loop leaves them in flight.
+template <int K, typename T, bool COARSE>
+__device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, int tile, AdjSmem<K, T>& sm) {
   using S = AShape<K>;
   static_assert(S::CH == 16 && kTW == 64 && kNT == 256, "one pixel quad per thread and plane per chunk");
-  __shared__ __align__(16) float C[kNM * S::CH * S::IWP];
-  __shared__ __align__(16) float HM[kNM * S::PL];
-  // 8- and 16-bit planes: the chunk's x, y quads are staged through LDS in
-  // their own packing (one 4- or 8-byte load per quad); float planes are
-  // loaded straight into the output stage's layout (one coalesced element per
-  // lane and row), which frees the 8 KB that would keep them at three
-  // workgroups per CU (staging 16-bit planes fits four anyway and measured
-  // faster than direct loads)
-  constexpr bool kStage = sizeof(T) <= 2;
-  __shared__ __align__(16) uint32_t XY[2][kStage ? S::CH * kTW * sizeof(T) / 4 : 1];
+  float* C = sm.C;
+  float* HM = sm.HM;
+  auto& XY = sm.XY;
+  constexpr bool kStage = AdjSmem<K, T>::kStage;
   constexpr int PL = S::PL;
   const int tyi = tile / a.qtiles_x, txi = tile - tyi * a.qtiles_x;
   const int qx0 = __builtin_amdgcn_readfirstlane(txi * kTW), qy0 = __builtin_amdgcn_readfirstlane(tyi * a.QH);
@@ -237,8 +252,16 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
   fetch_coef<K>(a, frame, qy0, c0, S::CH, q);
   fast::Quad<T> px4, py4;
   if constexpr (kStage) fetch_xy<T>(a, X, Y, qy0, qx0, px4, py4);
+  if constexpr (!COARSE) {
+    // as many dropped stores as a chunk's output stage issues: the loop's
+    // entry then has the prefetch as far behind the newest memory operation
+    // as every later iteration (distinct offsets, so none is merged)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) store_row_f32(nullptr, kStoreDrop + 4u * i, 0.f);
+  }
   const int gr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
   const int px = qx0 + c;
+  const uint32_t lane_off = px < a.g.W ? 4u * (uint32_t)c : kStoreDrop;
   for (int cy = qy0; cy < qy_end; cy += S::CH) {
     __syncthreads();
     store_coef<K>(q, S::CH, C);
@@ -300,7 +323,8 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int py = cy + 4 * gr + j;  // wave-uniform
-        if (py >= qy_end || px >= a.g.W) continue;
+        if constexpr (COARSE)
+          if (py >= qy_end || px >= a.g.W) continue;
         T xe, ye;
         if constexpr (kStage) {
           // staged row 4 gr + j, column c (quads are stored row-major, 16 per row)
@@ -314,14 +338,15 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
         const float xv = to_f32<T>(xe), yv = to_f32<T>(ye);
         // dL/dy = W^T A + (u - t_u) W^T B_u - (v - t_v) W^T B_v
         float gy = fmaf((xv + yv) - a.tu, G[1][j], G[0][j]) - ((xv - yv) - a.tv) * G[2][j];
-        if (a.coarse) {
+        if constexpr (COARSE) {
           const int cyy = py >> 1, cxx = px >> 1;
           if (cyy < a.Hc && cxx < a.Wc) {
             const char* crow = (const char*)(a.coarse + ((int64_t)frame * a.Hc + cyy) * a.Wc);
             gy += 0.25f * *(const float*)(crow + 4u * (uint32_t)cxx);
           }
         }
-        store_row_f32(a.out + (int64_t)frame * a.out_bstride + (int64_t)py * a.out_pitch + qx0, 4u * (uint32_t)c, gy);
+        const uint32_t off = lane_off | (py < qy_end ? 0u : kStoreDrop);
+        store_row_f32(a.out + (int64_t)frame * a.out_bstride + (int64_t)min(py, qy_end - 1) * a.out_pitch + qx0, off, gy);
       }
     }
     __syncthreads();
@@ -331,9 +356,11 @@ __device__ __forceinline__ void fast_adjoint_tile(const FastArgs& a, int frame, 
 
 template <int K, typename T>
 __global__ __launch_bounds__(kNT, 4) void fast_adjoint_kernel(FastArgs a) {
+  __shared__ AdjSmem<K, T> sm;
   int tile, frame;
   xcd_tile_rows_last(a.qtiles_x, a.qtiles_y, tile, frame);
-  fast_adjoint_tile<K, T>(a, frame, tile);
+  if (a.coarse) fast_adjoint_tile<K, T, true>(a, frame, tile, sm);
+  else fast_adjoint_tile<K, T, false>(a, frame, tile, sm);
 }
 
 template <int K>
@@ -341,8 +368,10 @@ __global__ __launch_bounds__(kNT, 4) void fast_adjoint_segs_kernel(FastSegs m) {
   const int s = seg_of(m.start, m.n);
   const FastArgs& a = m.seg[s];
   int tile, frame;
+  __shared__ AdjSmem<K, float> sm;
   seg_tile(m.start, s, a.qtiles_x * a.qtiles_y, tile, frame);
-  fast_adjoint_tile<K, float>(a, frame, tile);
+  if (a.coarse) fast_adjoint_tile<K, float, true>(a, frame, tile, sm);
+  else fast_adjoint_tile<K, float, false>(a, frame, tile, sm);
 }
 
 // ---------------------------------------------------------------- dispatch
