@@ -295,6 +295,50 @@ def test_backward_row_pitch_beyond_vector_offsets(P, dev):
     del bx, by, vx, vy
 
 
+@pytest.mark.parametrize("frames,h,w", [(3, 150, 173), (2, 1080, 1920), (1, 40, 64)])
+def test_outputs_outside_the_map_stay_untouched(P, dev, frames, h, w):
+    """The band kernels store every row and lane of a chunk, positions past
+    the tile's last row or the plane's last column with an offset the
+    hardware drops: the pitch padding and the slack between frames of the
+    map and of the gradient keep their prior contents, and the valid parts
+    equal the densely stored results."""
+    import ctypes
+    L = P._lib
+    rng = np.random.default_rng(frames * 1000 + w)
+    x = rng.integers(0, 256, (frames, h, w)).astype(np.uint8)
+    y = np.clip(x.astype(np.int32) + rng.integers(-20, 21, x.shape), 0, 255).astype(np.uint8)
+    xt, yt = to_dev(x, dev), to_dev(y, dev)
+    cfg = P.SSIMConfig()
+    pc = cfg.to_c()
+    xi, yi = P.ops._image(xt), P.ops._image(yt)
+    ho, wo = P.map_shape(cfg, h, w)
+    sentinel = 12345.0
+    # map: 37 columns of pitch padding, 5 rows of slack per frame
+    mp, mrows = wo + 37, ho + 5
+    qmap = torch.full((frames * mrows * mp,), sentinel, dtype=torch.float32, device=dev)
+    score = torch.empty(frames, dtype=torch.float32, device=dev)
+    ws = torch.empty(P.workspace_size(cfg, L.OP_MAP, L.U8, h, w, frames), dtype=torch.uint8, device=dev)
+    L.check(L.lib.ssim_map(ctypes.byref(pc), ctypes.byref(xi), ctypes.byref(yi), frames, qmap.data_ptr(), mp,
+                           mrows * mp, score.data_ptr(), ws.data_ptr(), ws.numel(), None), "ssim_map")
+    # gradient: 29 columns of pitch padding, 3 rows of slack per frame
+    gp, grows = w + 29, h + 3
+    grad = torch.full((frames * grows * gp,), sentinel, dtype=torch.float32, device=dev)
+    up = torch.ones(frames, dtype=torch.float32, device=dev)
+    wsb = torch.empty(P.workspace_size(cfg, L.OP_POOLED_BACKWARD, L.U8, h, w, frames), dtype=torch.uint8,
+                      device=dev)
+    L.check(L.lib.ssim_pooled_backward(ctypes.byref(pc), ctypes.byref(xi), ctypes.byref(yi), frames, up.data_ptr(),
+                                       grad.data_ptr(), gp, grows * gp, wsb.data_ptr(), wsb.numel(), None),
+            "ssim_pooled_backward")
+    torch.cuda.synchronize()
+    m = qmap.view(frames, mrows, mp)
+    assert bool((m[:, :ho, wo:] == sentinel).all()) and bool((m[:, ho:, :] == sentinel).all())
+    _, dense_map = P.ssim(xt, yt, cfg, return_map=True)
+    assert torch.equal(m[:, :ho, :wo], dense_map)
+    g = grad.view(frames, grows, gp)
+    assert bool((g[:, :h, w:] == sentinel).all()) and bool((g[:, h:, :] == sentinel).all())
+    assert torch.equal(g[:, :h, :w], P.ssim_backward(xt, yt, up, cfg))
+
+
 @pytest.mark.parametrize("kind,n_scales,padding,aggregation",
                          [("u16", 5, "valid", "product"), ("u16", 3, "reflect", "product"),
                           ("u8", 4, "valid", "sum"), ("f32", 3, "valid", "product")])
