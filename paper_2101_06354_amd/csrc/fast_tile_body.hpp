@@ -603,7 +603,6 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
         const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
         const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
         {
-          const SsimTerms t = ssim_terms_uv(mean_u, mean_v, var_u, var_v, a.C1, a.C2);
           float g = gframe;
           if constexpr (GMAP) {
             const char* row = (const char*)(a.grad_map + (int64_t)frame * a.gm_bstride + (int64_t)oi * a.gm_pitch + ox0);
@@ -616,22 +615,29 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
           //   B_u = k_c var_v,  B_v = -k_c (A2 + B2),
           //   A   = k_l m_v (m_u m_v + A1 + B1) - B_u (m_u - t_u) + B_v (m_v - t_v)
           // (the three planes are A = A_u - A_v, B_u, B_v of the transpose).
-          const float ib1 = __builtin_amdgcn_rcpf(t.B1), ib2 = __builtin_amdgcn_rcpf(t.B2);
-          float fl, fc;
+          // In doubled terms, e = A1 + B1 = m_u^2 + 2 C1 and s = A2 + B2 =
+          // var_u + 2 C2 give 2 B1 = e + m_v^2, 2 A1 = e - m_v^2,
+          // 2 B2 = s + var_v, 2 A2 = s - var_v; with r1 = 1 / (2 B1) and
+          // r2 = 1 / (2 B2), 1 / B = 2 r and, for Q,
+          //   k_l = 4 g (2 A2) r2 r1^2,  k_c = 4 g (2 A1) r1 r2^2
+          // (cs: k_l = 0, k_c = 4 g r2^2; two upstreams: k_l = 4 g_l r1^2).
+          const float e = fmaf(mean_u, mean_u, c1x2), s2 = var_u + c2x2;
+          const float r1 = __builtin_amdgcn_rcpf(fmaf(mean_v, mean_v, e)), r2 = __builtin_amdgcn_rcpf(s2 + var_v);
+          const float g4 = 4.f * g;
+          float kl, kc;
           if (a.mode == 1) {
-            fl = 0.f;
-            fc = g;
+            kl = 0.f;
+            kc = (g4 * r2) * r2;
           } else if (a.mode == 3) {
-            fl = gl_frame;
-            fc = g;
+            kl = ((4.f * gl_frame) * r1) * r1;
+            kc = (g4 * r2) * r2;
           } else {
-            fl = g * (t.A2 * ib2);
-            fc = g * (t.A1 * ib1);
+            const float q = g4 * (r1 * r2);
+            kl = (q * r1) * (s2 - var_v);
+            kc = (q * r2) * fmaf(-mean_v, mean_v, e);
           }
-          const float kl = fl * (ib1 * ib1), kc = fc * (ib2 * ib2);
-          const float bu = kc * var_v, bv = -kc * (t.A2 + t.B2);
-          const float ca = fmaf(kl * mean_v, fmaf(mean_u, mean_v, t.A1 + t.B1),
-                                fmaf(-bu, mean_u - a.tu, bv * (mean_v - a.tv)));
+          const float bu = kc * var_v, bv = -kc * s2;
+          const float ca = fmaf(kl * mean_v, fmaf(mean_u, mean_v, e), fmaf(-bu, mean_u - a.tu, bv * (mean_v - a.tv)));
           // W^T is linear: the two A maps are combined before the transpose
           const int64_t qs = (int64_t)a.batch * a.g.Ho * a.cpitch;
           // every row and lane stores, outside the map with the dropped
