@@ -460,7 +460,10 @@ __host__ __device__ constexpr int fast_smem_floats() {
 // makes the compiler wait there for every older memory operation (the next
 // chunk's prefetch and the previous outputs' stores) on both paths of a
 // runtime branch.
-template <int K, typename T, int EPI, bool EDGE, bool GMAP = false>
+// MODE >= 0 (EPI 1, interior tiles): the coefficient mode (0 Q, 1 cs, 3 the
+// two upstreams) fixed at compile time, so that the four outputs' epilogues
+// form one block; MODE = -1 reads a.mode per output.
+template <int K, typename T, int EPI, bool EDGE, bool GMAP = false, int MODE = -1>
 __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int frame, int tile, float* smem) {
   using S = Shape<K>;
   float* U = smem;
@@ -625,10 +628,11 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
           const float r1 = __builtin_amdgcn_rcpf(fmaf(mean_v, mean_v, e)), r2 = __builtin_amdgcn_rcpf(s2 + var_v);
           const float g4 = 4.f * g;
           float kl, kc;
-          if (a.mode == 1) {
+          const int mode = MODE >= 0 ? MODE : a.mode;
+          if (mode == 1) {
             kl = 0.f;
             kc = (g4 * r2) * r2;
-          } else if (a.mode == 3) {
+          } else if (mode == 3) {
             kl = ((4.f * gl_frame) * r1) * r1;
             kc = (g4 * r2) * r2;
           } else {
@@ -671,6 +675,11 @@ __device__ __forceinline__ float fast_stats_tile(const FastArgs& a, int frame, i
     if (a.grad_map)
       return interior ? fast_stats_tile_body<K, T, EPI, false, true>(a, frame, tile, smem)
                       : fast_stats_tile_body<K, T, EPI, true, true>(a, frame, tile, smem);
+    if (interior) {  // one body per coefficient mode
+      if (a.mode == 1) return fast_stats_tile_body<K, T, EPI, false, false, 1>(a, frame, tile, smem);
+      if (a.mode == 3) return fast_stats_tile_body<K, T, EPI, false, false, 3>(a, frame, tile, smem);
+      return fast_stats_tile_body<K, T, EPI, false, false, 0>(a, frame, tile, smem);
+    }
   }
   return interior ? fast_stats_tile_body<K, T, EPI, false>(a, frame, tile, smem)
                   : fast_stats_tile_body<K, T, EPI, true>(a, frame, tile, smem);
