@@ -543,7 +543,9 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
       const float4* hb = (const float4*)(HM + 4 * gr * S::RS) + (c + c / 8);  // (mean_u, mean_v, var_u, var_v)
       const float Tu = hb[S::SHIFT * (S::RS / 4)].x, Tv = hb[S::SHIFT * (S::RS / 4)].y;
       float Mu[4] = {0.f, 0.f, 0.f, 0.f}, Mv[4] = {0.f, 0.f, 0.f, 0.f};
-      float Su[4] = {0.f, 0.f, 0.f, 0.f}, Sv[4] = {0.f, 0.f, 0.f, 0.f};
+      // the second moments of u start at 2 C2: every use of var_u below takes
+      // var_u + 2 C2, which the fma that removes the squared mean then yields
+      float Su[4] = {c2x2, c2x2, c2x2, c2x2}, Sv[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int m = 0; m < K + 3; ++m) {
         const float4 h = hb[m * (S::RS / 4)];
@@ -576,8 +578,8 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
         for (int j = 0; j < 4; ++j) {
           const int oi = cy + 4 * gr + j;  // wave-uniform
           if (oi >= oy_end || !col_in) continue;
-          const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
-          const float val = ssim_value_uv_m<M>(Tu + Mu[j], Tv + Mv[j], var_u, var_v, c1x2, c2x2);
+          const float s2 = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);  // s2 = var_u + 2 C2
+          const float val = ssim_value_uv_s<M>(Tu + Mu[j], Tv + Mv[j], s2, var_v, c1x2);
           if (a.map) {
             store_row_f32(a.map + (int64_t)frame * a.map_bstride + (int64_t)oi * a.map_pitch + ox0, cb, val);
           }
@@ -604,7 +606,7 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
         if constexpr (GMAP)
           if (oi >= oy_end || !col_in) continue;  // the upstream map is read only inside the map
         const float mean_u = Tu + Mu[j], mean_v = Tv + Mv[j];
-        const float var_u = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);
+        const float s2 = fmaf(-Mu[j], Mu[j], Su[j]), var_v = fmaf(-Mv[j], Mv[j], Sv[j]);  // s2 = var_u + 2 C2
         {
           float g = gframe;
           if constexpr (GMAP) {
@@ -624,7 +626,7 @@ __device__ __forceinline__ float fast_stats_tile_body(const FastArgs& a, int fra
           // r2 = 1 / (2 B2), 1 / B = 2 r and, for Q,
           //   k_l = 4 g (2 A2) r2 r1^2,  k_c = 4 g (2 A1) r1 r2^2
           // (cs: k_l = 0, k_c = 4 g r2^2; two upstreams: k_l = 4 g_l r1^2).
-          const float e = fmaf(mean_u, mean_u, c1x2), s2 = var_u + c2x2;
+          const float e = fmaf(mean_u, mean_u, c1x2);
           const float r1 = __builtin_amdgcn_rcpf(fmaf(mean_v, mean_v, e)), r2 = __builtin_amdgcn_rcpf(s2 + var_v);
           const float g4 = 4.f * g;
           float kl, kc;

@@ -56,17 +56,23 @@ __device__ __forceinline__ float ssim_value(const SsimTerms& t, int mode) {
 // which needs neither A1 nor the halvings.  x == y still gives b = var_v = 0
 // and Q == 1.0f exactly, and swapping x and y leaves b and var_v unchanged.
 // c1x2 = 2 C1, c2x2 = 2 C2.
+// The same from s = var_u + 2 C2 (a caller may accumulate the variance of u
+// on top of 2 C2 and so skip the addition).
 template <int MODE>
-__device__ __forceinline__ float ssim_value_uv_m(float mean_u, float mean_v, float var_u, float var_v, float c1x2,
-                                                 float c2x2) {
+__device__ __forceinline__ float ssim_value_uv_s(float mean_u, float mean_v, float s, float var_v, float c1x2) {
   const float b = mean_v * mean_v;
-  const float s = var_u + c2x2;
   if constexpr (MODE == 1) return fmaf(-2.f * var_v, __builtin_amdgcn_rcpf(s + var_v), 1.f);
   const float B1 = fmaf(mean_u, mean_u, b) + c1x2;
   if constexpr (MODE == 3) return fmaf(-2.f * b, __builtin_amdgcn_rcpf(B1), 1.f);
   const float B2 = s + var_v, A2 = s - var_v;
   const float n = fmaf(b, A2, var_v * B1);
   return fmaf(n, -2.f * __builtin_amdgcn_rcpf(B1 * B2), 1.f);
+}
+
+template <int MODE>
+__device__ __forceinline__ float ssim_value_uv_m(float mean_u, float mean_v, float var_u, float var_v, float c1x2,
+                                                 float c2x2) {
+  return ssim_value_uv_s<MODE>(mean_u, mean_v, var_u + c2x2, var_v, c1x2);
 }
 
 __device__ __forceinline__ float ssim_value_uv(float mean_u, float mean_v, float var_u, float var_v, float c1x2,
